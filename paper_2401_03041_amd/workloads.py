@@ -1,0 +1,218 @@
+"""Seeded synthetic inputs for the coupled thermocapillary sweep.
+
+This module only *describes* problems: grid sizes, boundary flags, material
+parameters, droplet lists, heat sources and initial temperature fields drawn
+from a seeded generator.  It holds none of the method's arithmetic (no
+equilibria, no collision, no interface profile) and imports nothing from the
+GPU library or from the oracle, so both sides can be fed the very same inputs.
+
+Every configuration is a plain ``dict``:
+
+``shape``            (nx, ny, nz)
+``periodic_y``       False: no-slip walls at y = -1/2 and y = ny - 1/2
+``q_pf``             phase-field stencil, 15 or 27
+``q_thermal``        thermal stencil, 7/15/19/27 (thermal LB only)
+``thermal``          "lb", "rk2" or "rk4"
+``precision``        "fp64" or "fp32" (GPU storage and collision precision)
+material parameters  rho_h, rho_l, nu_h, nu_l, mobility, xi, sigma_ref,
+                     sigma_t, t_ref, kappa_h, kappa_l, g, omega_bulk,
+                     normal_eps (regularisation scale of the interface normal)
+walls                u_wall_bot, u_wall_top, t_wall_bot, t_wall_top
+inputs               droplets [(x, y, z, R)], heat_sources
+                     [(Q, x, y, z, w, d_cut)], t_init (see ``temperature``)
+"""
+from __future__ import annotations
+
+import copy
+
+import numpy as np
+
+DEFAULTS = dict(
+    periodic_y=True, q_pf=15, q_thermal=7, thermal="lb", precision="fp64",
+    rho_h=1.0, rho_l=1.0, nu_h=1.0 / 6.0, nu_l=1.0 / 6.0, mobility=0.05, xi=5.0,
+    sigma_ref=0.0, sigma_t=0.0, t_ref=0.0, kappa_h=0.2, kappa_l=0.2,
+    g=(0.0, 0.0, 0.0), omega_bulk=1.0, normal_eps=1e-6,
+    u_wall_bot=(0.0, 0.0, 0.0), u_wall_top=(0.0, 0.0, 0.0), t_wall_bot=0.0, t_wall_top=0.0,
+    droplets=[], heat_sources=[], t_init={"kind": "uniform", "value": 0.0},
+    u_init=(0.0, 0.0, 0.0),
+)
+
+
+def make(**kw) -> dict:
+    cfg = copy.deepcopy(DEFAULTS)
+    cfg.update(kw)
+    cfg["shape"] = tuple(int(v) for v in cfg["shape"])
+    return cfg
+
+
+# ---------------------------------------------------------------------------------------
+# The five benchmark problems (droplet domains of the paper's kind, synthetic)
+# ---------------------------------------------------------------------------------------
+def static_droplet(n: int = 32, steps: int = 200, precision: str = "fp64", **kw) -> dict:
+    """Static droplet: n^3 periodic, sphere R = n/4 at the box centre, density ratio 10,
+    viscosity 0.1/0.01, sigma(T) = 1e-3 - 1e-5 T, linear T gradient 1e-3/cell along x."""
+    c = (n - 1) / 2.0  # geometric centre of the cell-centred box
+    return make(name=f"static_droplet_{n}", shape=(n, n, n), precision=precision, steps=steps,
+                rho_h=1.0, rho_l=0.1, nu_h=0.1, nu_l=0.01, mobility=0.05, xi=5.0,
+                sigma_ref=1e-3, sigma_t=-1e-5, t_ref=0.0, kappa_h=0.2, kappa_l=0.2,
+                droplets=[(c, c, c, n / 4.0)],
+                t_init={"kind": "linear", "axis": 0, "origin": c, "slope": 1e-3, "value": 0.0}, **kw)
+
+
+def migration(shape=(128, 256, 128), marangoni: float = 1.0, thermal: str = "lb", q_thermal: int = 7,
+              precision: str = "fp64", steps: int = 2000, radius: float = 16.0, **kw) -> dict:
+    """Thermocapillary migration between walls at T = 0 (bottom) and T = 1 (top),
+    periodic in x and z, droplet of radius 16 near the cold wall, unit property
+    ratios.  kappa follows from Ma = U R / kappa with U = |sigma_T| G R / mu."""
+    nx, ny, nz = shape
+    G = 1.0 / ny
+    nu = 1.0 / 6.0
+    sigma_t = -1.6e-3
+    u_ref = abs(sigma_t) * G * radius / nu
+    kappa = u_ref * radius / marangoni
+    return make(name=f"migration_Ma{marangoni:g}_{thermal}{q_thermal if thermal == 'lb' else ''}",
+                shape=shape, periodic_y=False, thermal=thermal, q_thermal=q_thermal, precision=precision,
+                steps=steps, rho_h=1.0, rho_l=1.0, nu_h=nu, nu_l=nu, mobility=0.05, xi=5.0,
+                sigma_ref=5e-3, sigma_t=sigma_t, t_ref=0.5, kappa_h=kappa, kappa_l=kappa,
+                t_wall_bot=0.0, t_wall_top=1.0,
+                droplets=[(nx / 2.0, ny / 4.0, nz / 2.0, radius)],
+                t_init={"kind": "conduction"}, **kw)
+
+
+def droplet_block(n: int = 512, ndrop: int = 64, seed: int = 0, precision: str = "fp32",
+                  steps: int = 500, radius=(10.0, 24.0), sigma_range=(24.0, 64.0), **kw) -> dict:
+    """Full single-GPU block: n^3 periodic, ndrop droplets with radii ~ U[10, 24]
+    at random non-overlapping centres, density ratio 100, smooth random T field
+    (sum of 8 Gaussians of amplitude 0.5)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xi = 5.0
+    drops = []
+    tries = 0
+    while len(drops) < ndrop:
+        tries += 1
+        if tries > 200000:
+            raise RuntimeError("could not place droplets")
+        r = float(rng.uniform(radius[0], radius[1]))
+        p = rng.uniform(0.0, n, size=3)
+        ok = True
+        for (qx, qy, qz, qr) in drops:
+            d = np.array([qx, qy, qz]) - p
+            d -= n * np.round(d / n)
+            if np.linalg.norm(d) < r + qr + 2 * xi:
+                ok = False
+                break
+        if ok:
+            drops.append((float(p[0]), float(p[1]), float(p[2]), r))
+    gauss = []
+    for _ in range(8):
+        c = rng.uniform(0.0, n, size=3)
+        s = float(rng.uniform(sigma_range[0], sigma_range[1]))
+        gauss.append((0.5, float(c[0]), float(c[1]), float(c[2]), s))
+    return make(name=f"droplet_block_{n}", shape=(n, n, n), precision=precision, steps=steps,
+                rho_h=1.0, rho_l=0.01, nu_h=0.1, nu_l=0.1, mobility=0.05, xi=xi,
+                sigma_ref=1e-3, sigma_t=-1e-5, t_ref=0.0, kappa_h=0.2, kappa_l=0.2,
+                droplets=drops, t_init={"kind": "gaussians", "list": gauss}, seed=seed, **kw)
+
+
+def capture(shape=(256, 128, 96), precision: str = "fp32", steps: int = 5000, **kw) -> dict:
+    """Thermal-tweezer capture channel: hemisphere R = 12 on the bottom wall at
+    x = 40, Gaussian heater (Q = 0.8, w = 16) on the bottom wall at x = 128,
+    top wall moving at 0.02, both walls at T = 0.  Parameters follow the
+    paper's droplet study (Ma = 0.01, Ca = 0.16, Re = 0.08, xi = 4)."""
+    nx, ny, nz = shape
+    R = 12.0 * nx / 256.0
+    gamma = 0.02 / ny
+    U = gamma * R
+    Re, Ca, Ma = 0.08, 0.16, 0.01
+    nu = U * R / Re
+    sigma_ref = U * nu / Ca
+    sigma_t = 0.04 * sigma_ref
+    kappa = U * R / Ma
+    return make(name=f"capture_{nx}x{ny}x{nz}", shape=shape, periodic_y=False, precision=precision,
+                steps=steps, rho_h=1.0, rho_l=1.0, nu_h=nu, nu_l=nu, mobility=0.05, xi=4.0,
+                sigma_ref=sigma_ref, sigma_t=sigma_t, t_ref=0.0, kappa_h=kappa, kappa_l=kappa,
+                u_wall_top=(0.02, 0.0, 0.0), t_wall_bot=0.0, t_wall_top=0.0,
+                droplets=[(40.0 * nx / 256.0, -0.5, nz / 2.0, R)],
+                heat_sources=[(0.8, nx / 2.0, -0.5, nz / 2.0, 2.0 * 8.0 * nx / 256.0, 0.0)],
+                t_init={"kind": "uniform", "value": 0.0}, **kw)
+
+
+# ---------------------------------------------------------------------------------------
+# Initial temperature fields (inputs; evaluated on any box of the global domain)
+# ---------------------------------------------------------------------------------------
+def _coords(cfg, origin, dims):
+    ox, oy, oz = origin
+    nx, ny, nz = dims
+    z = (oz + np.arange(nz, dtype=np.float64))[:, None, None]
+    y = (oy + np.arange(ny, dtype=np.float64))[None, :, None]
+    x = (ox + np.arange(nx, dtype=np.float64))[None, None, :]
+    return x, y, z
+
+
+def temperature(cfg: dict, origin=(0, 0, 0), dims=None) -> np.ndarray:
+    """Initial temperature on the box [origin, origin + dims) of the global grid,
+    shape (nz, ny, nx)."""
+    dims = tuple(cfg["shape"]) if dims is None else tuple(dims)
+    spec = cfg["t_init"]
+    kind = spec["kind"]
+    x, y, z = _coords(cfg, origin, dims)
+    out = np.zeros((dims[2], dims[1], dims[0]))
+    if kind == "uniform":
+        out += spec.get("value", 0.0)
+    elif kind == "linear":
+        axis = (x, y, z)[spec["axis"]]
+        out += spec.get("value", 0.0) + spec["slope"] * (axis - spec["origin"])
+    elif kind == "conduction":
+        ny = cfg["shape"][1]
+        out += cfg["t_wall_bot"] + (cfg["t_wall_top"] - cfg["t_wall_bot"]) * (y + 0.5) / ny
+    elif kind == "gaussians":
+        L = np.array(cfg["shape"], dtype=np.float64)
+        for (amp, cx, cy, cz, s) in spec["list"]:
+            fac = []
+            for coord, c, Ln in ((x, cx, L[0]), (y, cy, L[1]), (z, cz, L[2])):
+                d = coord - c
+                d = d - Ln * np.round(d / Ln)
+                fac.append(np.exp(-d * d / (2.0 * s * s)))
+            out += amp * fac[0] * fac[1] * fac[2]
+    elif kind == "array":
+        out += np.asarray(spec["value"], dtype=np.float64)[
+            origin[2]:origin[2] + dims[2], origin[1]:origin[1] + dims[1], origin[0]:origin[0] + dims[0]]
+    else:
+        raise ValueError(kind)
+    return out
+
+
+def velocity(cfg: dict, origin=(0, 0, 0), dims=None):
+    """Initial velocity components (uniform by default, or arrays)."""
+    dims = tuple(cfg["shape"]) if dims is None else tuple(dims)
+    u = cfg.get("u_init", (0.0, 0.0, 0.0))
+    out = []
+    for a in range(3):
+        v = u[a]
+        if np.ndim(v) == 0:
+            out.append(np.full((dims[2], dims[1], dims[0]), float(v)))
+        else:
+            arr = np.asarray(v, dtype=np.float64)
+            out.append(arr[origin[2]:origin[2] + dims[2], origin[1]:origin[1] + dims[1],
+                           origin[0]:origin[0] + dims[0]].copy())
+    return out
+
+
+def cropped(cfg: dict, shape) -> dict:
+    """Same physics on a smaller grid: droplets and heaters keep their positions
+    relative to the box size (used for parity cases the oracle finishes quickly)."""
+    out = copy.deepcopy(cfg)
+    old = np.array(cfg["shape"], dtype=np.float64)
+    new = np.array(shape, dtype=np.float64)
+    f = new / old
+    out["shape"] = tuple(int(v) for v in shape)
+    out["droplets"] = [(x * f[0], y if y < 0 else y * f[1], z * f[2], r * float(np.min(f)))
+                       for (x, y, z, r) in cfg["droplets"]]
+    out["heat_sources"] = [(Q, x * f[0], y if y < 0 else y * f[1], z * f[2], w * float(np.min(f)), dc)
+                           for (Q, x, y, z, w, dc) in cfg["heat_sources"]]
+    if cfg["t_init"]["kind"] == "gaussians":
+        out["t_init"] = {"kind": "gaussians",
+                         "list": [(a, cx * f[0], cy * f[1], cz * f[2], s * float(np.min(f)))
+                                  for (a, cx, cy, cz, s) in cfg["t_init"]["list"]]}
+    out["name"] = cfg.get("name", "cfg") + "_crop"
+    return out
