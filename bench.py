@@ -1,0 +1,211 @@
+#!/usr/bin/env python3
+"""Throughput of the coupled thermocapillary sweep on one MI355X.
+
+One step = phase-field LB (D3Q15) + hydrodynamic LB (D3Q27, all forces) +
+thermal LB (D3Q7) over the whole grid.  Default workload: the single-GPU
+droplet block, 512^3 periodic cells, 64 droplets (radii uniform in [10, 24],
+density ratio 100) in a smooth random temperature field, shifted-FP32
+storage; the same block in FP64 is timed after it.  Inputs are resident in
+HBM before the timed region; the timed region is `steps` calls of the whole
+step bracketed by device synchronisations.
+
+Prints one JSON line (metric, value in MLUPS, roofline of the dominant kernel
+from HIP events on the library's stream, and the FP64 oracle timed on the host
+cores over a bounded sample of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline per coupled step, FP32 vs FP64; adjoint/forward cost"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hydro_droplet_block_512.md")
+
+
+def _log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _kernel_sha() -> str:
+    h = hashlib.sha256()
+    for name in ("kernels_hydro.hip", "lattice.hpp", "kernels.hpp"):
+        with open(os.path.join(ROOT, "paper_2401_03041_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _traffic(precision: str):
+    """Measured HBM bytes per hydrodynamic launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    scaled by a copy kernel), if taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        line = line.strip().strip("`")
+        if line.startswith("traffic_") and "=" in line:
+            k, v = line.split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("traffic_kernel_sha") != _kernel_sha():
+        return None
+    key = f"traffic_bytes_per_launch_{precision}"
+    return float(vals[key]) if key in vals else None
+
+
+def run_gpu(cfg: dict, steps: int, warmup: int, precision: str) -> dict:
+    import torch
+
+    from paper_2401_03041_amd import tcplb
+    cfg = dict(cfg, precision=precision)
+    t0 = time.perf_counter()
+    d = tcplb.domain_from_workload(cfg)
+    torch.cuda.synchronize()
+    _log(f"{precision}: set-up {time.perf_counter() - t0:.1f} s")
+    d.step(warmup)
+    d.synchronize()
+    d.set_profiling(True)
+    d.kernel_times()  # reset
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    d.step(steps)
+    d.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    times = d.kernel_times()
+    d.set_profiling(False)
+    mass, _ = d.reduce()
+    ncell = d.ncell
+    bpc = d.algorithmic_bytes()
+    kernels = {}
+    for k, (ms, n) in times.items():
+        if n == 0:
+            continue
+        avg = ms / n
+        kernels[k] = {"avg_ms": avg, "launches": n,
+                      "algorithmic_bytes_per_launch": bpc[k] * ncell / (2 if k == "rk" else 1),
+                      "achieved_GBs": bpc[k] * ncell / (avg * 1e-3) / 1e9}
+    step_bytes = sum(bpc.values()) * ncell
+    d.close()
+    del d
+    torch.cuda.empty_cache()
+    mlups = ncell * steps / elapsed / 1e6
+    _log(f"{precision}: {mlups:.1f} MLUPS, {1e3 * elapsed / steps:.3f} ms/step, mass {mass:.6e}")
+    return {"mlups": mlups, "ms_per_step": 1e3 * elapsed / steps, "kernels": kernels,
+            "step_bytes_per_cell": step_bytes / ncell, "mass": mass,
+            "effective_GBs": step_bytes * steps / elapsed / 1e9}
+
+
+def roofline(res: dict, precision: str) -> dict:
+    k = res["kernels"]["hydro"]
+    achieved = k["achieved_GBs"]
+    return {"bound": "hbm", "kernel": "hydro (D3Q27 central-moment step with forces)",
+            "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(precision),
+            "algorithmic_bytes_per_launch": k["algorithmic_bytes_per_launch"],
+            "avg_launch_ms": k["avg_ms"]}
+
+
+def cpu_baseline(cfg: dict, box: int, steps: int) -> dict:
+    """The FP64 oracle on a box x box x box piece of the same workload (its own
+    initialisation from the droplet list and temperature Gaussians, periodic wrap
+    on the piece)."""
+    from oracle import oracle as O
+    from paper_2401_03041_amd import workloads as W
+    sub = dict(cfg, shape=(box, box, box))
+    origin = (0, 0, 0)
+    d = O.OracleDomain(sub)
+    d.set_droplets(cfg["droplets"], gdim=cfg["shape"], origin=origin, periodic=(1, 1, 1))
+    d.set_field("T", W.temperature(cfg, origin=origin, dims=(box, box, box)))
+    d.initialize()
+    t0 = time.perf_counter()
+    d.step(steps)
+    el = time.perf_counter() - t0
+    mlups = box ** 3 * steps / el / 1e6
+    _log(f"oracle: {mlups:.3f} MLUPS on {O.num_threads()} threads ({el:.1f} s)")
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{box}^3 corner of the droplet block (its droplets and temperature field), "
+                      f"{steps} steps, FP64, {el:.1f} s"}
+
+
+def copy_calibration(gib: float = 4.0, reps: int = 5) -> None:
+    """A plain device copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = int(gib * (1 << 30)) // 4
+    a = torch.empty(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    _log(f"copy calibration: {reps} copies of {n * 4} bytes")
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=512, help="edge of the cubic droplet block")
+    ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: steps/2; 0 skips)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-box", type=int, default=64)
+    ap.add_argument("--oracle-steps", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernel")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the single-GPU block is the unit this build "
+              "measures (--gpus 1)", file=sys.stderr)
+        return 2
+    if args.copy_calibration:
+        copy_calibration()
+        return 0
+
+    from paper_2401_03041_amd import workloads as W
+    cfg = W.droplet_block(n=args.n, precision="fp32")
+    fp32 = run_gpu(cfg, args.steps, args.warmup, "fp32")
+    fp64_steps = args.steps // 2 if args.fp64_steps is None else args.fp64_steps
+    fp64 = run_gpu(cfg, fp64_steps, max(2, args.warmup // 4), "fp64") if fp64_steps > 0 else None
+    base = None if args.no_cpu_baseline else cpu_baseline(cfg, args.oracle_box, args.oracle_steps)
+
+    line = {
+        "metric": METRIC,
+        "value": round(fp32["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(fp32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"droplet block {args.n}^3 periodic, 64 droplets r~U[10,24], density ratio 100, "
+                               "D3Q15 phase field + D3Q27 hydro + D3Q7 thermal LB, shifted-FP32 storage",
+                   "grid": [args.n] * 3, "precision": "fp32", "parallelism": "single GPU"},
+        "roofline": roofline(fp32, "fp32"),
+        "cpu_baseline": base,
+        "step_bytes_per_cell": fp32["step_bytes_per_cell"],
+        "effective_GBs": round(fp32["effective_GBs"], 1),
+        "kernels": {k: {kk: round(vv, 5) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                    for k, v in fp32["kernels"].items()},
+    }
+    if fp64 is not None:
+        line["fp64"] = {"value": round(fp64["mlups"], 2), "unit": "MLUPS", "steps": fp64_steps,
+                        "ms_per_step": round(fp64["ms_per_step"], 4), "dtype": "f64",
+                        "roofline": roofline(fp64, "fp64"), "effective_GBs": round(fp64["effective_GBs"], 1),
+                        "step_bytes_per_cell": fp64["step_bytes_per_cell"]}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

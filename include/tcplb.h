@@ -1,0 +1,195 @@
+/*
+ * tcplb.h -- C interface of the MI355X (gfx950) thermocapillary phase-field
+ * lattice Boltzmann library.
+ *
+ * One domain advances the coupled sweep of Holzer et al. (arXiv 2401.03041):
+ * per time step the conservative Allen-Cahn phase-field LB (D3Q15 or D3Q27,
+ * Sec. 2.2 Eq. lb_interface), the velocity-based D3Q27 central-moment
+ * hydrodynamic LB with surface tension, temperature-dependent Marangoni,
+ * pressure and viscous correction forces (Sec. 2.1-2.2), and the thermal
+ * field as a D3Q7/15/19/27 passive-scalar LB (Eq. lb_thermal) or an RK2/RK4
+ * finite-difference energy update (Eq. rk2, Eq. rk4), in the order of
+ * Algorithm 1 (LB) or Algorithm 2 (RK).
+ *
+ * Conventions shared by every call
+ *  - Lattice units: dx = dt = 1, c_s^2 = 1/3.
+ *  - Cell (x, y, z), 0 <= x < nx etc., has linear index x + nx*(y + ny*z);
+ *    host arrays are FP64 in that order.  Device arrays given to or taken
+ *    from the library are FP64 in the same order.
+ *  - The domain is periodic in x and z.  In y it is periodic, or bounded by
+ *    no-slip walls at y = -1/2 and y = ny - 1/2 (halfway bounce-back).
+ *  - Every call returns an int: TCP_OK (0) or a negative TCP_ERR_* code; no
+ *    C++ exception crosses this interface.  tcp_last_error() gives text.
+ *  - Work is enqueued on the HIP stream given at creation; calls that return
+ *    host data synchronise that stream, all other calls are asynchronous.
+ *  - A domain is not thread-safe: calls on one domain must not overlap.
+ */
+#ifndef TCPLB_H
+#define TCPLB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    TCP_OK = 0,
+    TCP_ERR_ARG = -1,         /* invalid argument or parameter value */
+    TCP_ERR_UNSUPPORTED = -2, /* valid request this build does not implement */
+    TCP_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
+    TCP_ERR_OOM = -4,         /* device allocation failed */
+    TCP_ERR_NONFINITE = -5,   /* a reduction met NaN or Inf in the phase field */
+    TCP_ERR_STATE = -6        /* call out of order (e.g. step before initialize) */
+};
+
+/* field selectors for tcp_set_field / tcp_get_field */
+enum {
+    TCP_PHI = 0,   /* phase indicator phi (0 light, 1 heavy)               set/get */
+    TCP_UX = 1,    /* velocity components                                 set/get */
+    TCP_UY = 2,
+    TCP_UZ = 3,
+    TCP_T = 4,     /* temperature                                          set/get */
+    TCP_P = 5,     /* pressure p = p* rho c_s^2 (Sec. 2.2)                 get */
+    TCP_PSTAR = 6, /* normalised pressure p* = sum_i g_i (Sec. 2.2)        get */
+    TCP_RHO = 7    /* density rho(phi) (Sec. 2.2)                          get */
+};
+
+/* PDF selectors for tcp_get_pdfs */
+enum { TCP_PDF_H = 0, TCP_PDF_G = 1, TCP_PDF_F = 2 };
+
+enum { TCP_THERMAL_LB = 0, TCP_THERMAL_RK2 = 1, TCP_THERMAL_RK4 = 2 };
+enum { TCP_FP64 = 0, TCP_FP32 = 1 };
+
+/* Kernel kinds reported by tcp_kernel_times */
+enum { TCP_K_PHASE = 0, TCP_K_HYDRO = 1, TCP_K_THERMAL = 2, TCP_K_RK = 3, TCP_K_COUNT = 4 };
+
+typedef struct tcp_domain tcp_domain;
+
+/* Device memory provider.  alloc returns a device pointer of at least `bytes`
+ * bytes (256-byte aligned) or NULL; free releases it.  ctx is passed through. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, void *ctx);
+    void *ctx;
+} tcp_allocator;
+
+/* Laser heat source q_T (Eq. HeatSource): Q exp(-2 d^2 / w^2) where
+ * d is the distance to (x, y, z); zero where d > d_cut, no cut-off if
+ * d_cut <= 0.  Coordinates are cell-centre units (cell i sits at i). */
+typedef struct {
+    double Q, x, y, z, w, d_cut;
+} tcp_heat_source;
+
+/* Spherical droplet for tcp_set_droplets: centre (x, y, z), radius r. */
+typedef struct {
+    double x, y, z, r;
+} tcp_droplet;
+
+/* Physical and numerical parameters (Sec. 2.1-2.3, Sec. 3.1). */
+typedef struct {
+    int32_t nx, ny, nz;
+    int32_t walls_y;        /* 0: periodic in y; 1: no-slip walls at y = -1/2, ny - 1/2 */
+    int32_t q_pf;           /* phase-field stencil: 15 or 27 */
+    int32_t q_thermal;      /* thermal LB stencil: 7, 15, 19 or 27 */
+    int32_t thermal;        /* TCP_THERMAL_LB, _RK2 or _RK4 */
+    int32_t precision;      /* TCP_FP64: FP64 storage and arithmetic;
+                               TCP_FP32: FP32 storage and arithmetic */
+    double rho_h, rho_l;    /* densities of the heavy (phi = 1) and light phase */
+    double nu_h, nu_l;      /* kinematic viscosities (lattice units) */
+    double mobility;        /* interface mobility M */
+    double xi;              /* interface width */
+    double sigma_ref;       /* surface tension at t_ref */
+    double sigma_t;         /* d sigma / d T */
+    double t_ref;           /* reference temperature of sigma(T) */
+    double kappa_h, kappa_l;/* thermal diffusivities (rho c_p = 1) */
+    double g[3];            /* gravitational acceleration */
+    double omega_bulk;      /* relaxation rate of the trace of the second moments */
+    double normal_eps;      /* n = grad phi / sqrt(|grad phi|^2 + normal_eps^2) */
+    double u_wall_bot[3];   /* wall velocities (walls_y = 1) */
+    double u_wall_top[3];
+    double t_wall_bot;      /* uniform wall temperatures; tcp_set_wall_temperature */
+    double t_wall_top;      /*   overrides them with per-column values */
+    double t_shift;         /* thermal PDFs are stored as f_i - w_i t_shift */
+} tcp_params;
+
+/* Fill *p with defaults: 32^3 periodic, D3Q15 phase field, D3Q7 thermal LB,
+ * FP64, unit densities, nu = 1/6, M = 0.05, xi = 5, no surface tension,
+ * kappa = 0.2, omega_bulk = 1, normal_eps = 1e-6. */
+int tcp_params_default(tcp_params *p);
+
+/* Validate *p and allocate a domain.  Rejects (TCP_ERR_ARG) any relaxation
+ * rate outside (0, 2), and for RK thermal updates kappa_max above the
+ * real-axis stability bound of the isotropic Laplacian (2/5.78 for RK2,
+ * 2.785/5.78 for RK4).  alloc: NULL uses hipMalloc/hipFree.  stream: a
+ * hipStream_t (NULL: the default stream).  On success *out owns all device
+ * state; release it with tcp_destroy. */
+int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tcp_domain **out);
+int tcp_destroy(tcp_domain *d);
+
+/* Copy one macroscopic field into the domain.  Exactly one of host (FP64
+ * host array) or dev (FP64 device array) is non-NULL; both hold nx*ny*nz
+ * values.  The library keeps no reference to the caller's array. */
+int tcp_set_field(tcp_domain *d, int which, const double *host, const void *dev);
+
+/* phi := max over droplets of 1/2 + 1/2 tanh(2 (r_k - dist_k) / xi)
+ * (the tanh interface of Sec. 3.1), with minimum-image distances along the
+ * periodic axes.  n = 0 sets phi = 0. */
+int tcp_set_droplets(tcp_domain *d, const tcp_droplet *drops, int n);
+
+/* Heat sources of Eq. HeatSource (at most 16); replaces any previous set. */
+int tcp_set_heat_sources(tcp_domain *d, const tcp_heat_source *src, int n);
+
+/* Per-column wall temperature (walls_y = 1): wall 0 = bottom, 1 = top;
+ * Tw holds nx*nz FP64 host values, index x + nx*z. */
+int tcp_set_wall_temperature(tcp_domain *d, int wall, const double *Tw);
+
+/* Set all PDFs to the equilibria of the current phi, u, T with p* = 0
+ * (Sec. 4.1 initialisation).  Must precede tcp_step. */
+int tcp_initialize(tcp_domain *d);
+
+/* Advance nsteps coupled time steps (asynchronous). */
+int tcp_step(tcp_domain *d, int64_t nsteps);
+
+/* Read back one field as FP64 into host (synchronises) or dev (FP64 device
+ * array of nx*ny*nz values, asynchronous); exactly one is non-NULL. */
+int tcp_get_field(tcp_domain *d, int which, double *host, void *dev);
+
+/* Post-collision PDFs of the current step, unshifted FP64, component-major:
+ * out[i*N + cell], i in the stencil order of App. B.  Synchronises. */
+int tcp_get_pdfs(tcp_domain *d, int which, double *host_out);
+
+/* FP64 diagnostics: mass = sum phi and centroid = sum phi x / sum phi with
+ * integer cell coordinates.  Synchronises.  TCP_ERR_NONFINITE if phi holds
+ * NaN or Inf. */
+int tcp_reduce(tcp_domain *d, double *mass, double centroid[3]);
+
+/* Raw state (all PDF buffers and fields, storage precision) for checkpoint
+ * and restart: tcp_state_bytes gives the size; save/load copy to/from a host
+ * buffer of that size.  Loading restores a bitwise identical state. */
+int tcp_state_bytes(const tcp_domain *d, size_t *bytes);
+int tcp_save_state(tcp_domain *d, void *host);
+int tcp_load_state(tcp_domain *d, const void *host);
+
+/* Wait for all work enqueued on the domain's stream. */
+int tcp_synchronize(tcp_domain *d);
+
+/* Per-kernel timing with HIP events on the domain's stream.  While enabled,
+ * every launch is bracketed by two events.  tcp_kernel_times synchronises,
+ * writes the summed milliseconds and launch counts per TCP_K_* kind (arrays
+ * of TCP_K_COUNT entries) and resets the counters. */
+int tcp_set_profiling(tcp_domain *d, int enabled);
+int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches);
+
+/* Bytes each kernel kind moves per cell by the algorithmic model (each PDF
+ * read and written once, each scalar field read or written once). */
+int tcp_algorithmic_bytes(const tcp_domain *d, double *bytes_per_cell);
+
+const char *tcp_error_string(int code);
+const char *tcp_last_error(const tcp_domain *d);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCPLB_H */

@@ -84,7 +84,8 @@ def _load():
     lib.ora_moment_matrix.argtypes = [C.c_int, C.c_int, dp, dp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
     lib.ora_cm_collide.argtypes = [C.c_int, C.c_int, dp, dp, dp, dp, dp, dp]
     lib.ora_equilibrium.argtypes = [C.c_int, C.c_int, C.c_double, dp, dp]
-    lib.ora_iso_grad_lap.argtypes = [vp, dp, C.c_int, C.c_int, C.c_int, dp, dp]
+    lib.ora_iso_grad_lap.argtypes = [vp, dp, C.c_int, C.c_int, C.c_int, C.c_int, dp, dp]
+    lib.ora_guo_source.argtypes = [dp, dp, dp]
     lib.ora_heat_source.restype = C.c_double
     lib.ora_heat_source.argtypes = [vp, C.c_double, C.c_double, C.c_double]
     _lib = lib
@@ -210,11 +211,12 @@ class OracleDomain:
         self._lib.ora_reduce(self._h, _dptr(m), _dptr(c))
         return float(m[0]), c
 
-    def iso_grad_lap(self, psi, x, y, z):
+    def iso_grad_lap(self, psi, x, y, z, ghost: str = "mirror"):
         a = _f64(psi)
         g = np.zeros(3)
         l = np.zeros(1)
-        self._lib.ora_iso_grad_lap(self._h, _dptr(a), int(x), int(y), int(z), _dptr(g), _dptr(l))
+        self._lib.ora_iso_grad_lap(self._h, _dptr(a), int(x), int(y), int(z), int(ghost != "mirror"),
+                                   _dptr(g), _dptr(l))
         return g, float(l[0])
 
     def heat_source(self, x, y, z) -> float:
@@ -249,6 +251,13 @@ def cm_collide(q: int, kind: int, rate, u, f, feq, S) -> np.ndarray:
     args = [_f64(a) for a in (rate, u, f, feq, S)]
     if lib.ora_cm_collide(q, kind, *[_dptr(a) for a in args], _dptr(out)) != 0:
         raise RuntimeError("singular moment matrix")
+    return out
+
+
+def guo_source(u, acc) -> np.ndarray:
+    lib = _load()
+    out = np.zeros(27)
+    lib.ora_guo_source(_dptr(_f64(u)), _dptr(_f64(acc)), _dptr(out))
     return out
 
 

@@ -458,6 +458,17 @@ static void eq_hydro(const stencil *s, double pstar, const double u[3], double *
     for (int i = 0; i < s->q; ++i) out[i] = s->w[i] * (pstar + eq_poly(s->e[i], u));
 }
 
+/* Guo source in velocity form (R15): S_i = w_i [(e_i - u)/c_s^2 + (e_i.u) e_i/c_s^4] . a */
+static void guo_source(const stencil *s, const double u[3], const double acc[3], double *S)
+{
+    for (int i = 0; i < s->q; ++i) {
+        double eu = s->e[i][0] * u[0] + s->e[i][1] * u[1] + s->e[i][2] * u[2];
+        double v = 0.0;
+        for (int a = 0; a < 3; ++a) v += ((s->e[i][a] - u[a]) / CS2 + eu * s->e[i][a] / (CS2 * CS2)) * acc[a];
+        S[i] = s->w[i] * v;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Pull streaming with wall rules                                            */
 /* ------------------------------------------------------------------------ */
@@ -590,14 +601,7 @@ static int step_hydro(ora_domain *d)
                 double acc[3] = {F[0] / rho, F[1] / rho, F[2] / rho};
                 double u[3] = {u0[0] + 0.5 * acc[0], u0[1] + 0.5 * acc[1], u0[2] + 0.5 * acc[2]};
                 eq_hydro(s, pstar, u, geq);
-                /* Guo source in velocity form (R15) */
-                for (int i = 0; i < q; ++i) {
-                    double eu = s->e[i][0] * u[0] + s->e[i][1] * u[1] + s->e[i][2] * u[2];
-                    double v = 0.0;
-                    for (int a = 0; a < 3; ++a)
-                        v += ((s->e[i][a] - u[a]) / CS2 + eu * s->e[i][a] / (CS2 * CS2)) * acc[a];
-                    S[i] = s->w[i] * v;
-                }
+                guo_source(s, u, acc, S);
                 /* rates per moment (R14) */
                 for (int j = 0; j < q; ++j) {
                     int tg = d->Bg.r[j].tag;
@@ -995,10 +999,19 @@ int ora_equilibrium(int q, int kind, double zeroth, const double u[3], double *o
     return 0;
 }
 
-/* isotropic gradient and Laplacian of a periodic field (pin tests of R17) */
-int ora_iso_grad_lap(const ora_domain *d, const double *psi, int x, int y, int z, double *grad, double *lap)
+/* isotropic gradient and Laplacian (pin tests of R12, R11, R17); ghost 0: the
+ * phase-field mirror ghost, 1: the Dirichlet temperature ghost */
+int ora_iso_grad_lap(const ora_domain *d, const double *psi, int x, int y, int z, int ghost, double *grad,
+                     double *lap)
 {
-    iso_grad_lap(d, phi_at, psi, x, y, z, grad, lap);
+    iso_grad_lap(d, ghost ? temp_at : phi_at, psi, x, y, z, grad, lap);
+    return 0;
+}
+
+/* hydrodynamic Guo source (pin tests of R15) */
+int ora_guo_source(const double u[3], const double acc[3], double *S)
+{
+    guo_source(get_stencil(27), u, acc, S);
     return 0;
 }
 

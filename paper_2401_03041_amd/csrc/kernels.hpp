@@ -1,0 +1,133 @@
+// kernels.hpp -- argument blocks and host-side launchers of the gfx950
+// kernels (internal to the library; the public interface is tcplb.h).
+#pragma once
+
+#include "lattice.hpp"
+
+namespace tcp {
+
+// Threads of one work-group: 64 along x (one wavefront per row), 4 rows in y.
+constexpr int kBX = 64;
+constexpr int kBY = 4;
+
+// K1: conservative Allen-Cahn LB (Eq. lb_interface, Eq. phasefieldforce)
+struct PfArgs {
+    Geometry geo;
+    const void *h_src;
+    void *h_dst;
+    const void *phi_old; // phi^n (stencil for the interface normal)
+    void *phi_new;       // phi^{n+1} = sum_i h_i (output)
+    const void *u[3];    // u^n
+    double omega_phi;    // 1 / (1/2 + M / c_s^2)
+    double inv_xi;
+    double eps2;         // normal_eps^2
+};
+
+// K2: velocity-based D3Q27 central-moment hydrodynamics with forces (Sec. 2.1-2.2)
+struct HydroArgs {
+    Geometry geo;
+    const void *g_src;
+    void *g_dst;
+    const void *phi;   // phi^n (stencil)
+    const void *T;     // T^n (stencil)
+    const double *twb; // wall temperatures, nx*nz (walls only)
+    const double *twt;
+    void *u[3];        // u^{n+1} (output)
+    double rho_l, drho;  // rho(phi) = rho_l + phi_c drho
+    double tau_l, dtau;  // tau(phi) = tau_l + phi_c dtau, tau = nu / c_s^2
+    double sigma_ref, sigma_t, t_ref, xi;
+    double g[3];
+    double omega_bulk;
+    double uw_bot[3], uw_top[3];
+};
+
+// K3: passive-scalar thermal LB (Eq. lb_thermal)
+struct ThermalArgs {
+    Geometry geo;
+    const void *f_src;
+    void *f_dst;
+    const void *phi;   // phi^{n+1} (local)
+    const void *u[3];  // u^{n+1} (local)
+    void *T;           // T^{n+1} (output)
+    const double *twb;
+    const double *twt;
+    double kappa_l, dkappa;
+    double t_shift;    // f is stored as f_i - w_i t_shift
+    HeatSources src;
+};
+
+// RK stage of the energy equation (Eq. rk2, Eq. rk4):
+//   k = R(theta_in);  acc = (first ? 0 : acc) + w_acc k;
+//   last ? T += acc : theta_out = T + a_next k
+struct RkArgs {
+    Geometry geo;
+    const void *theta_in; // stage argument (stencil)
+    void *theta_out;
+    void *T;
+    void *acc;
+    const void *phi;      // phi^{n+1} (stencil, grad kappa)
+    const void *u[3];     // u^{n+1}
+    const double *twb;
+    const double *twt;
+    double kappa_l, dkappa;
+    double a_next, w_acc;
+    int first, last;
+    HeatSources src;
+};
+
+template <int Q, typename S, typename R>
+void launch_pf(const PfArgs &a, hipStream_t s);
+template <typename S, typename R>
+void launch_hydro(const HydroArgs &a, hipStream_t s);
+template <int Q, typename S, typename R>
+void launch_thermal(const ThermalArgs &a, hipStream_t s);
+template <typename S, typename R>
+void launch_rk(const RkArgs &a, hipStream_t s);
+
+// ---- set-up, read-back and diagnostics (kernels_aux.hip) -------------------
+struct Droplets {
+    int n;
+    const double *xyzr; // device, n x 4
+    double inv_xi;
+    int periodic[3];
+};
+template <typename S>
+void launch_droplets(const Geometry &g, const Droplets &d, void *phi, hipStream_t s);
+template <typename S>
+void launch_from_f64(const double *src, void *dst, int64_t n, hipStream_t s);
+
+struct InitArgs {
+    Geometry geo;
+    int q_pf, q_th;
+    const void *phi;
+    const void *u[3];
+    const void *T;
+    void *h, *g, *f;
+    void *phi_other;
+    double t_shift;
+};
+template <typename S>
+void launch_init(const InitArgs &a, hipStream_t s);
+
+// which: 0 phi, 1..3 u, 4 T, 5 p, 6 p*, 7 rho
+struct ReadArgs {
+    Geometry geo;
+    int which;
+    const void *phi, *T, *g;
+    const void *u[3];
+    double rho_l, drho;
+    double *out;
+};
+template <typename S>
+void launch_read(const ReadArgs &a, hipStream_t s);
+template <typename S>
+void launch_read_pdfs(const void *src, int q, int64_t N, double t_shift, int is_thermal, double *out,
+                      hipStream_t s);
+
+// FP64 sums of phi, phi x, phi y, phi z in fixed order: partial sums per
+// work-group, then one work-group adds them up.
+constexpr int kReduceBlocks = 1024;
+template <typename S>
+void launch_reduce(const Geometry &g, const void *phi, double *partial, double *out4, hipStream_t s);
+
+} // namespace tcp

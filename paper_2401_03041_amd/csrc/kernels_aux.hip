@@ -1,0 +1,227 @@
+// kernels_aux.hip -- set-up, read-back and FP64 diagnostics.
+//
+//  - droplets: phi = max_k 1/2 + 1/2 tanh(2 (r_k - d_k)/xi), the tanh interface
+//    of Sec. 3.1, minimum-image distances along periodic axes (FP64).
+//  - init: every PDF at the equilibrium of the current fields with p* = 0.
+//  - read: storage -> FP64 fields, p = p* rho(phi) c_s^2 with p* = sum_i g_i.
+//  - reduce: FP64 sums of phi and phi x in a fixed order (deterministic).
+#include "kernels.hpp"
+
+namespace tcp {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+template <typename S>
+__global__ void __launch_bounds__(kThreads) k_droplets(const Geometry g, const Droplets d, S *phi)
+{
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (c >= g.N) return;
+    const int x = (int)(c % g.nx);
+    const int y = (int)((c / g.nx) % g.ny);
+    const int z = (int)(c / g.plane);
+    const double L[3] = {(double)g.nx, (double)g.ny, (double)g.nz};
+    const double p[3] = {(double)x, (double)y, (double)z};
+    double best = 0.0;
+    for (int k = 0; k < d.n; ++k) {
+        double r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            double dd = p[a] - d.xyzr[4 * k + a];
+            if (d.periodic[a]) {
+                dd = fmod(dd, L[a]);
+                if (dd > 0.5 * L[a]) dd -= L[a];
+                if (dd < -0.5 * L[a]) dd += L[a];
+            }
+            r2 += dd * dd;
+        }
+        const double v = 0.5 + 0.5 * tanh(2.0 * (d.xyzr[4 * k + 3] - sqrt(r2)) * d.inv_xi);
+        best = (k == 0 || v > best) ? v : best;
+    }
+    phi[c] = static_cast<S>(best);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kThreads) k_from_f64(const double *src, S *dst, int64_t n)
+{
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (c < n) dst[c] = static_cast<S>(src[c]);
+}
+
+// equilibria with runtime stencil choice (set-up only)
+template <int Q, typename S>
+__device__ void store_scalar_eq(S *dst, int64_t N, int64_t c, double psi, double shift, const double u[3])
+{
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < Q; ++i) {
+        const double eu = vel<Q>(i, 0) * u[0] + vel<Q>(i, 1) * u[1] + vel<Q>(i, 2) * u[2];
+        const double w = weight<Q>(i);
+        dst[i * N + c] = static_cast<S>(psi * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) - w * shift);
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kThreads) k_init(const InitArgs a)
+{
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t N = a.geo.N;
+    if (c >= N) return;
+    const double phi = static_cast<double>(static_cast<const S *>(a.phi)[c]);
+    const double T = static_cast<double>(static_cast<const S *>(a.T)[c]);
+    double u[3];
+    for (int k = 0; k < 3; ++k) u[k] = static_cast<double>(static_cast<const S *>(a.u[k])[c]);
+    S *h = static_cast<S *>(a.h), *g = static_cast<S *>(a.g), *f = static_cast<S *>(a.f);
+    if (a.q_pf == 15) store_scalar_eq<15>(h, N, c, phi, 0.0, u);
+    else store_scalar_eq<27>(h, N, c, phi, 0.0, u);
+    // incompressible g_eq with p* = 0
+    const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    for (int i = 0; i < 27; ++i) {
+        const double eu = vel27(i, 0) * u[0] + vel27(i, 1) * u[1] + vel27(i, 2) * u[2];
+        g[i * N + c] = static_cast<S>(weight<27>(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+    }
+    if (f) {
+        switch (a.q_th) {
+        case 7: store_scalar_eq<7>(f, N, c, T, a.t_shift, u); break;
+        case 15: store_scalar_eq<15>(f, N, c, T, a.t_shift, u); break;
+        case 19: store_scalar_eq<19>(f, N, c, T, a.t_shift, u); break;
+        default: store_scalar_eq<27>(f, N, c, T, a.t_shift, u); break;
+        }
+    }
+    static_cast<S *>(a.phi_other)[c] = static_cast<S>(phi);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kThreads) k_read(const ReadArgs a)
+{
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int64_t N = a.geo.N;
+    if (c >= N) return;
+    double v = 0.0;
+    if (a.which == 0) v = static_cast<const S *>(a.phi)[c];
+    else if (a.which >= 1 && a.which <= 3) v = static_cast<const S *>(a.u[a.which - 1])[c];
+    else if (a.which == 4) v = static_cast<const S *>(a.T)[c];
+    else {
+        double ps = 0.0;
+        if (a.which == 5 || a.which == 6)
+            for (int i = 0; i < 27; ++i) ps += static_cast<double>(static_cast<const S *>(a.g)[i * N + c]);
+        const double phi = static_cast<const S *>(a.phi)[c];
+        const double phic = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
+        const double rho = a.rho_l + phic * a.drho;
+        v = a.which == 5 ? ps * rho / 3.0 : (a.which == 6 ? ps : rho);
+    }
+    a.out[c] = v;
+}
+
+template <int Q, typename S>
+__global__ void __launch_bounds__(kThreads) k_read_pdfs(const S *src, int64_t N, double shift, double *out)
+{
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (c >= N) return;
+    for (int i = 0; i < Q; ++i) out[i * N + c] = static_cast<double>(src[i * N + c]) + weight<Q>(i) * shift;
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kThreads) k_reduce_partial(const Geometry g, const S *phi, double *partial)
+{
+    __shared__ double sh[4][kThreads];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < g.N; c += (int64_t)gridDim.x * kThreads) {
+        const double p = static_cast<double>(phi[c]);
+        const int x = (int)(c % g.nx);
+        const int y = (int)((c / g.nx) % g.ny);
+        const int z = (int)(c / g.plane);
+        acc[0] += p;
+        acc[1] += p * x;
+        acc[2] += p * y;
+        acc[3] += p * z;
+    }
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) partial[4 * blockIdx.x + k] = sh[k][0];
+}
+
+__global__ void __launch_bounds__(kThreads) k_reduce_final(const double *partial, int nblocks, double *out4)
+{
+    __shared__ double sh[4][kThreads];
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = threadIdx.x; b < nblocks; b += kThreads)
+        for (int k = 0; k < 4; ++k) acc[k] += partial[4 * b + k];
+    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int k = 0; k < 4; ++k) out4[k] = sh[k][0];
+}
+
+inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
+
+} // namespace
+
+template <typename S>
+void launch_droplets(const Geometry &g, const Droplets &d, void *phi, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_droplets<S>), dim3(blocks_for(g.N)), dim3(kThreads), 0, s, g, d, static_cast<S *>(phi));
+}
+
+template <typename S>
+void launch_from_f64(const double *src, void *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_from_f64<S>), dim3(blocks_for(n)), dim3(kThreads), 0, s, src, static_cast<S *>(dst), n);
+}
+
+template <typename S>
+void launch_init(const InitArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_init<S>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a);
+}
+
+template <typename S>
+void launch_read(const ReadArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_read<S>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a);
+}
+
+template <typename S>
+void launch_read_pdfs(const void *src, int q, int64_t N, double t_shift, int is_thermal, double *out, hipStream_t s)
+{
+    const S *p = static_cast<const S *>(src);
+    const double sh = is_thermal ? t_shift : 0.0;
+    const dim3 gr(blocks_for(N)), bl(kThreads);
+    switch (q) {
+    case 7: hipLaunchKernelGGL((k_read_pdfs<7, S>), gr, bl, 0, s, p, N, sh, out); break;
+    case 15: hipLaunchKernelGGL((k_read_pdfs<15, S>), gr, bl, 0, s, p, N, sh, out); break;
+    case 19: hipLaunchKernelGGL((k_read_pdfs<19, S>), gr, bl, 0, s, p, N, sh, out); break;
+    default: hipLaunchKernelGGL((k_read_pdfs<27, S>), gr, bl, 0, s, p, N, sh, out); break;
+    }
+}
+
+template <typename S>
+void launch_reduce(const Geometry &g, const void *phi, double *partial, double *out4, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_reduce_partial<S>), dim3(kReduceBlocks), dim3(kThreads), 0, s, g,
+                       static_cast<const S *>(phi), partial);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, s, partial, kReduceBlocks, out4);
+}
+
+#define TCP_AUX_INST(S)                                                                                      \
+    template void launch_droplets<S>(const Geometry &, const Droplets &, void *, hipStream_t);              \
+    template void launch_from_f64<S>(const double *, void *, int64_t, hipStream_t);                         \
+    template void launch_init<S>(const InitArgs &, hipStream_t);                                            \
+    template void launch_read<S>(const ReadArgs &, hipStream_t);                                            \
+    template void launch_read_pdfs<S>(const void *, int, int64_t, double, int, double *, hipStream_t);      \
+    template void launch_reduce<S>(const Geometry &, const void *, double *, double *, hipStream_t);
+TCP_AUX_INST(double)
+TCP_AUX_INST(float)
+#undef TCP_AUX_INST
+
+} // namespace tcp

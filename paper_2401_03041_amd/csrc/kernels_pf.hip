@@ -1,0 +1,102 @@
+// kernels_pf.hip -- K1: conservative Allen-Cahn phase-field LB step
+// (Eq. lb_interface with the counter-term of Eq. phasefieldforce applied as a
+// source in collision space).  One thread per cell, pull streaming from the
+// post-collision PDFs of the previous step, halfway bounce-back at y walls.
+//
+// Collision: central moments about u^n on the moment basis of the stencil,
+// first-order moments relaxed with omega_phi, all higher ones with rate one.
+// Because the higher moments relax fully, the post-collision state is
+// h_eq + S/2 plus the inverse transform of the relaxed first-order moments
+// (FirstOrder<Q>), which is what the kernel evaluates.
+#include "kernels.hpp"
+
+namespace tcp {
+
+template <int Q, typename S, typename R>
+__global__ void __launch_bounds__(kBX *kBY) k_phase_field(const PfArgs a)
+{
+    const int x = blockIdx.x * kBX + threadIdx.x;
+    const int y = blockIdx.y * kBY + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= a.geo.nx || y >= a.geo.ny) return;
+    const Nbr nb(a.geo, x, y, z);
+    const int64_t N = a.geo.N;
+    const S *hs = static_cast<const S *>(a.h_src);
+
+    // pull; a link that crosses a wall returns the cell's own opposite PDF
+    R h[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        if (nb.ghost(-ey))
+            h[i] = ld<R>(hs + opposite<Q>(i) * N + nb.c);
+        else
+            h[i] = ld<R>(hs + i * N + nb.at(-ex, -ey, -ez));
+    }
+    R phi = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        phi += h[i];
+        j[0] += R(vel<Q>(i, 0)) * h[i];
+        j[1] += R(vel<Q>(i, 1)) * h[i];
+        j[2] += R(vel<Q>(i, 2)) * h[i];
+    }
+
+    // interface normal from the isotropic gradient of phi^n (mirror ghosts)
+    const S *po = static_cast<const S *>(a.phi_old);
+    R gr[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 1; i < 27; ++i) {
+        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+        const R v = R(weight<27>(i)) * ld<R>(po + nb.at(ex, ey, ez));
+        gr[0] += R(ex) * v;
+        gr[1] += R(ey) * v;
+        gr[2] += R(ez) * v;
+    }
+    gr[0] *= R(3);
+    gr[1] *= R(3);
+    gr[2] *= R(3);
+    const R inv = R(1) / sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + R(a.eps2));
+    const R lam = R(4) * phi * (R(1) - phi) * R(a.inv_xi);
+    const R F[3] = {lam * gr[0] * inv, lam * gr[1] * inv, lam * gr[2] * inv};
+
+    R u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(static_cast<const S *>(a.u[k]) + nb.c);
+
+    // relaxed first-order central moment of h - h_eq + S/2
+    const R om1 = R(1) - R(a.omega_phi);
+    const R sixth = R(1.0 / 6.0);
+    const R v[3] = {om1 * (j[0] - phi * u[0] + sixth * F[0]), om1 * (j[1] - phi * u[1] + sixth * F[1]),
+                    om1 * (j[2] - phi * u[2] + sixth * F[2])};
+    R d[Q];
+    FirstOrder<Q, R>::apply(u, v, d);
+
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    S *hd = static_cast<S *>(a.h_dst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        const R w = R(weight<Q>(i));
+        const R eu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
+        const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
+        const R heq = phi * w * (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
+        st(hd + i * N + nb.c, heq + R(0.5) * w * eF + d[i]);
+    }
+    st(static_cast<S *>(a.phi_new) + nb.c, phi);
+}
+
+template <int Q, typename S, typename R>
+void launch_pf(const PfArgs &a, hipStream_t s)
+{
+    dim3 block(kBX, kBY, 1);
+    dim3 grid((a.geo.nx + kBX - 1) / kBX, (a.geo.ny + kBY - 1) / kBY, a.geo.nz);
+    hipLaunchKernelGGL((k_phase_field<Q, S, R>), grid, block, 0, s, a);
+}
+
+template void launch_pf<15, double, double>(const PfArgs &, hipStream_t);
+template void launch_pf<27, double, double>(const PfArgs &, hipStream_t);
+template void launch_pf<15, float, float>(const PfArgs &, hipStream_t);
+template void launch_pf<27, float, float>(const PfArgs &, hipStream_t);
+
+} // namespace tcp

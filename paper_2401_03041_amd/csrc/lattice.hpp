@@ -1,0 +1,292 @@
+// lattice.hpp -- compile-time lattice tables, storage conversion and
+// neighbour addressing shared by the gfx950 kernels.
+//
+// Velocity order and weights follow App. B (stencils figure and weight
+// equations): 0 rest; 1/2 = +y/-y; 3/4 = -x/+x; 5/6 = +z/-z; 7-10 the xy
+// edges NW NE SW SE; 11-14 TN TS TW TE; 15-18 BN BS BW BE; 19-26 the corners
+// TNE TNW TSE TSW BNE BNW BSE BSW.  D3Q15 is the rest + faces + the eight
+// corners (in the same corner order); D3Q19 is 0-18; D3Q7 is 0-6.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tcp {
+
+// ----------------------------------------------------------------------------
+// velocities and weights
+// ----------------------------------------------------------------------------
+__host__ __device__ constexpr int vel27(int i, int a)
+{
+    constexpr int t[27][3] = {
+        {0, 0, 0},   {0, 1, 0},   {0, -1, 0},  {-1, 0, 0}, {1, 0, 0},   {0, 0, 1},   {0, 0, -1},
+        {-1, 1, 0},  {1, 1, 0},   {-1, -1, 0}, {1, -1, 0}, {0, 1, 1},   {0, -1, 1},  {-1, 0, 1},
+        {1, 0, 1},   {0, 1, -1},  {0, -1, -1}, {-1, 0, -1}, {1, 0, -1}, {1, 1, 1},   {-1, 1, 1},
+        {1, -1, 1},  {-1, -1, 1}, {1, 1, -1},  {-1, 1, -1}, {1, -1, -1}, {-1, -1, -1}};
+    return t[i][a];
+}
+
+// D3Q15 maps its corner slots 7..14 onto D3Q27 slots 19..26
+template <int Q>
+__host__ __device__ constexpr int vel(int i, int a)
+{
+    return vel27((Q == 15 && i >= 7) ? i + 12 : i, a);
+}
+
+template <int Q>
+__host__ __device__ constexpr double weight(int i)
+{
+    if (Q == 7) return i == 0 ? 0.0 : 1.0 / 6.0;
+    if (Q == 15) return i == 0 ? 16.0 / 72.0 : (i < 7 ? 8.0 / 72.0 : 1.0 / 72.0);
+    if (Q == 19) return i == 0 ? 12.0 / 36.0 : (i < 7 ? 2.0 / 36.0 : 1.0 / 36.0);
+    return i == 0 ? 64.0 / 216.0 : (i < 7 ? 16.0 / 216.0 : (i < 19 ? 4.0 / 216.0 : 1.0 / 216.0));
+}
+
+template <int Q>
+__host__ __device__ constexpr int opposite(int i)
+{
+    for (int j = 0; j < Q; ++j)
+        if (vel<Q>(j, 0) == -vel<Q>(i, 0) && vel<Q>(j, 1) == -vel<Q>(i, 1) && vel<Q>(j, 2) == -vel<Q>(i, 2))
+            return j;
+    return -1;
+}
+
+// ----------------------------------------------------------------------------
+// storage <-> arithmetic precision
+// ----------------------------------------------------------------------------
+template <typename R, typename S>
+__device__ __forceinline__ R ld(const S *p)
+{
+    return static_cast<R>(*p);
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ void st(S *p, R v)
+{
+    *p = static_cast<S>(v);
+}
+
+// ----------------------------------------------------------------------------
+// geometry and neighbour addressing
+// ----------------------------------------------------------------------------
+struct Geometry {
+    int nx, ny, nz;
+    int walls;     // 1: no-slip walls at y = -1/2 and y = ny - 1/2
+    int64_t N;     // nx*ny*nz
+    int64_t plane; // nx*ny
+};
+
+// Offsets of the 3x3x3 neighbourhood of one cell.  Periodic wrap in x and z
+// (and y when there are no walls).  With walls, rows beyond the walls are
+// flagged so callers apply their boundary rule.
+struct Nbr {
+    int xo[3];     // x-1, x, x+1 (wrapped)
+    int64_t yo[3]; // row offsets of y-1, y, y+1 (wrapped or clamped)
+    int64_t zo[3]; // plane offsets of z-1, z, z+1 (wrapped)
+    int zi[3];     // z-1, z, z+1 (wrapped)
+    int64_t c;     // own linear index
+    bool below;    // y == 0 with a wall below
+    bool above;    // y == ny-1 with a wall above
+
+    __device__ __forceinline__ Nbr(const Geometry &g, int x, int y, int z)
+    {
+        xo[0] = x == 0 ? g.nx - 1 : x - 1;
+        xo[1] = x;
+        xo[2] = x == g.nx - 1 ? 0 : x + 1;
+        int ym = y == 0 ? (g.walls ? 0 : g.ny - 1) : y - 1;
+        int yp = y == g.ny - 1 ? (g.walls ? g.ny - 1 : 0) : y + 1;
+        yo[0] = (int64_t)ym * g.nx;
+        yo[1] = (int64_t)y * g.nx;
+        yo[2] = (int64_t)yp * g.nx;
+        int zm = z == 0 ? g.nz - 1 : z - 1;
+        int zp = z == g.nz - 1 ? 0 : z + 1;
+        zi[0] = zm;
+        zi[1] = z;
+        zi[2] = zp;
+        zo[0] = (int64_t)zm * g.plane;
+        zo[1] = (int64_t)z * g.plane;
+        zo[2] = (int64_t)zp * g.plane;
+        c = x + yo[1] + zo[1];
+        below = g.walls && y == 0;
+        above = g.walls && y == g.ny - 1;
+    }
+    // index of the cell at offset (dx, dy, dz); rows beyond a wall are
+    // clamped onto the wall-adjacent row (the mirror ghost of phi)
+    __device__ __forceinline__ int64_t at(int dx, int dy, int dz) const
+    {
+        return xo[dx + 1] + yo[dy + 1] + zo[dz + 1];
+    }
+    // true when the offset dy leaves the fluid through a wall
+    __device__ __forceinline__ bool ghost(int dy) const
+    {
+        return (dy < 0 && below) || (dy > 0 && above);
+    }
+    // wall-column index x + nx*z of the neighbour at (dx, dz)
+    __device__ __forceinline__ int64_t col(int dx, int dz, const Geometry &g) const
+    {
+        return xo[dx + 1] + (int64_t)zi[dz + 1] * g.nx;
+    }
+};
+
+// ----------------------------------------------------------------------------
+// heat sources (Eq. HeatSource)
+// ----------------------------------------------------------------------------
+constexpr int kMaxSources = 16;
+
+struct HeatSources {
+    int n;
+    double Q[kMaxSources], x[kMaxSources], y[kMaxSources], z[kMaxSources];
+    double inv_w2[kMaxSources], dcut2[kMaxSources]; // dcut2 <= 0: no cut-off
+};
+
+template <typename R>
+__device__ __forceinline__ R heat_source(const HeatSources &hs, int x, int y, int z)
+{
+    R q = R(0);
+    for (int k = 0; k < hs.n; ++k) {
+        R dx = R(x) - R(hs.x[k]), dy = R(y) - R(hs.y[k]), dz = R(z) - R(hs.z[k]);
+        R d2 = dx * dx + dy * dy + dz * dz;
+        if (hs.dcut2[k] > 0.0 && d2 > R(hs.dcut2[k])) continue;
+        q += R(hs.Q[k]) * exp(R(-2) * d2 * R(hs.inv_w2[k]));
+    }
+    return q;
+}
+
+// ----------------------------------------------------------------------------
+// Inverse central-moment transform restricted to the first-order moments.
+//
+// All moments of order >= 2 of the phase-field and thermal collisions relax
+// with rate one, so f* = f_eq + S/2 + d where d is the unique PDF vector whose
+// central moments (basis of the stencil, about u) are zero except the three
+// first-order ones, which equal v.  The functions below build d from its raw
+// moments (found from the central ones by the binomial shift, which is
+// triangular in the polynomial degree) followed by the constant inverse of
+// the raw-moment matrix of the stencil.
+// ----------------------------------------------------------------------------
+template <int Q, typename R>
+struct FirstOrder;
+
+template <typename R>
+struct FirstOrder<7, R> {
+    __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[7])
+    {
+        d[0] = R(-2) * (u[0] * v[0] + u[1] * v[1] + u[2] * v[2]);
+        d[1] = v[1] * (u[1] + R(0.5));
+        d[2] = v[1] * (u[1] - R(0.5));
+        d[3] = v[0] * (u[0] - R(0.5));
+        d[4] = v[0] * (u[0] + R(0.5));
+        d[5] = v[2] * (u[2] + R(0.5));
+        d[6] = v[2] * (u[2] - R(0.5));
+    }
+};
+
+template <typename R>
+struct FirstOrder<15, R> {
+    __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[15])
+    {
+        const R ux = u[0], uy = u[1], uz = u[2], vx = v[0], vy = v[1], vz = v[2];
+        // raw moments of d
+        const R rxx = R(2) * ux * vx, ryy = R(2) * uy * vy, rzz = R(2) * uz * vz;
+        const R rxy = ux * vy + uy * vx, rxz = ux * vz + uz * vx, ryz = uy * vz + uz * vy;
+        const R rxyy = uy * uy * vx + R(2) * ux * uy * vy;
+        const R ryzz = uz * uz * vy + R(2) * uy * uz * vz;
+        const R rzxx = ux * ux * vz + R(2) * uz * ux * vx;
+        const R rxyz = uy * uz * vx + ux * uz * vy + ux * uy * vz;
+        // x^2 y^2 row: on this lattice x^2 y coincides with y z^2
+        const R rxxyy = R(-2) * ux * uy * uy * vx + R(2) * uy * uz * uz * vy + R(4) * uy * uy * uz * vz;
+        // inverse of the raw-moment matrix: corners by a Walsh-Hadamard sum
+#pragma unroll
+        for (int k = 7; k < 15; ++k) {
+            const R sx = R(vel<15>(k, 0)), sy = R(vel<15>(k, 1)), sz = R(vel<15>(k, 2));
+            d[k] = R(0.125) * (rxxyy + sx * rxyy + sy * ryzz + sz * rzxx + sx * sy * rxy + sx * sz * rxz +
+                               sy * sz * ryz + sx * sy * sz * rxyz);
+        }
+        const R ex = rxx - rxxyy, ox = vx - rxyy;
+        const R ey = ryy - rxxyy, oy = vy - ryzz;
+        const R ez = rzz - rxxyy, oz = vz - rzxx;
+        d[4] = R(0.5) * (ex + ox);
+        d[3] = R(0.5) * (ex - ox);
+        d[1] = R(0.5) * (ey + oy);
+        d[2] = R(0.5) * (ey - oy);
+        d[5] = R(0.5) * (ez + oz);
+        d[6] = R(0.5) * (ez - oz);
+        d[0] = R(2) * rxxyy - (rxx + ryy + rzz);
+    }
+};
+
+template <typename R>
+struct FirstOrder<19, R> {
+    __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[19])
+    {
+        const R ux = u[0], uy = u[1], uz = u[2], vx = v[0], vy = v[1], vz = v[2];
+        // the D3Q19 basis is closed under taking factors, so every raw moment
+        // of d is v . grad_u of the monomial evaluated at u
+        const R rxx = R(2) * ux * vx, ryy = R(2) * uy * vy, rzz = R(2) * uz * vz;
+        const R rxy = ux * vy + uy * vx, rxz = ux * vz + uz * vx, ryz = uy * vz + uz * vy;
+        const R rxxy = R(2) * ux * uy * vx + ux * ux * vy, rxyy = uy * uy * vx + R(2) * ux * uy * vy;
+        const R rxxz = R(2) * ux * uz * vx + ux * ux * vz, rxzz = uz * uz * vx + R(2) * ux * uz * vz;
+        const R ryyz = R(2) * uy * uz * vy + uy * uy * vz, ryzz = uz * uz * vy + R(2) * uy * uz * vz;
+        const R rxxyy = R(2) * ux * uy * uy * vx + R(2) * ux * ux * uy * vy;
+        const R rxxzz = R(2) * ux * uz * uz * vx + R(2) * ux * ux * uz * vz;
+        const R ryyzz = R(2) * uy * uz * uz * vy + R(2) * uy * uy * uz * vz;
+#pragma unroll
+        for (int k = 7; k < 19; ++k) {
+            const int sx = vel<19>(k, 0), sy = vel<19>(k, 1), sz = vel<19>(k, 2);
+            R val;
+            if (sz == 0) // xy edges
+                val = rxxyy + R(sx) * rxyy + R(sy) * rxxy + R(sx * sy) * rxy;
+            else if (sy == 0) // xz edges
+                val = rxxzz + R(sx) * rxzz + R(sz) * rxxz + R(sx * sz) * rxz;
+            else // yz edges
+                val = ryyzz + R(sy) * ryzz + R(sz) * ryyz + R(sy * sz) * ryz;
+            d[k] = R(0.25) * val;
+        }
+        const R ex = rxx - rxxyy - rxxzz, ox = vx - rxyy - rxzz;
+        const R ey = ryy - rxxyy - ryyzz, oy = vy - rxxy - ryzz;
+        const R ez = rzz - rxxzz - ryyzz, oz = vz - rxxz - ryyz;
+        d[4] = R(0.5) * (ex + ox);
+        d[3] = R(0.5) * (ex - ox);
+        d[1] = R(0.5) * (ey + oy);
+        d[2] = R(0.5) * (ey - oy);
+        d[5] = R(0.5) * (ez + oz);
+        d[6] = R(0.5) * (ez - oz);
+        d[0] = (rxxyy + rxxzz + ryyzz) - (rxx + ryy + rzz);
+    }
+};
+
+// D3Q27: the moment matrix is the tensor product of three 3x3 matrices
+// (c - u)^p, p = 0..2, c = -1, 0, 1, so its inverse factorises; m_p(c) below is
+// column p of the 1-D inverse evaluated at lattice coordinate c.
+template <typename R>
+struct Axis1D {
+    R m0[3], m1[3], m2[3]; // index c + 1
+    __device__ __forceinline__ explicit Axis1D(R u)
+    {
+        const R u2 = u * u;
+        m0[1] = R(1) - u2;
+        m0[0] = R(0.5) * (u2 - u);
+        m0[2] = R(0.5) * (u2 + u);
+        m1[1] = R(-2) * u;
+        m1[0] = u - R(0.5);
+        m1[2] = u + R(0.5);
+        m2[1] = R(-1);
+        m2[0] = R(0.5);
+        m2[2] = R(0.5);
+    }
+};
+
+template <typename R>
+struct FirstOrder<27, R> {
+    __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[27])
+    {
+        const Axis1D<R> X(u[0]), Y(u[1]), Z(u[2]);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int a = vel27(i, 0) + 1, b = vel27(i, 1) + 1, c = vel27(i, 2) + 1;
+            d[i] = v[0] * X.m1[a] * Y.m0[b] * Z.m0[c] + v[1] * X.m0[a] * Y.m1[b] * Z.m0[c] +
+                   v[2] * X.m0[a] * Y.m0[b] * Z.m1[c];
+        }
+    }
+};
+
+} // namespace tcp

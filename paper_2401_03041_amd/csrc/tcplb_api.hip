@@ -1,0 +1,765 @@
+// tcplb_api.hip -- host implementation of the C interface in include/tcplb.h:
+// parameter validation, buffer ownership, the per-step schedule of
+// Algorithm 1 (phase field -> hydrodynamics -> thermal LB) and Algorithm 2
+// (... -> RK stages), read-back, diagnostics and per-kernel event timing.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tcplb.h"
+#include "kernels.hpp"
+
+using namespace tcp;
+
+struct TimingRecord {
+    int kind;
+    hipEvent_t start, stop;
+};
+
+struct tcp_domain {
+    tcp_params P{};
+    Geometry geo{};
+    tcp_allocator A{};
+    bool own_alloc = true;
+    hipStream_t stream = nullptr;
+    size_t sb = 8; // bytes per stored value
+
+    void *h[2]{}, *g[2]{}, *f[2]{}, *phi[2]{}, *u[3]{}, *T = nullptr;
+    void *rk[3]{}; // theta_a, theta_b, acc
+    double *twb = nullptr, *twt = nullptr;
+    double *partial = nullptr, *out4 = nullptr;
+    HeatSources src{};
+    int cur = 0;
+    bool initialized = false;
+
+    double omega_phi = 1.0, tau_h = 0.5, tau_l = 0.5;
+    std::string err;
+
+    bool prof = false;
+    std::vector<TimingRecord> records;
+    std::vector<hipEvent_t> pool;
+    std::vector<void *> owned;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(tcp_domain *d, int code, const std::string &msg)
+{
+    if (d) d->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int hip_fail(tcp_domain *d, const char *what, hipError_t e)
+{
+    return fail(d, TCP_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define TCP_HIP(d, call)                                                                                     \
+    do {                                                                                                      \
+        hipError_t e_ = (call);                                                                               \
+        if (e_ != hipSuccess) return hip_fail((d), #call, e_);                                                \
+    } while (0)
+
+void *dev_alloc(tcp_domain *d, size_t bytes)
+{
+    if (bytes == 0) bytes = 256;
+    void *p = nullptr;
+    if (d->own_alloc) {
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    } else {
+        p = d->A.alloc(bytes, d->A.ctx);
+    }
+    return p;
+}
+
+void dev_free(tcp_domain *d, void *p)
+{
+    if (!p) return;
+    if (d->own_alloc) (void)hipFree(p);
+    else d->A.free(p, d->A.ctx);
+}
+
+// allocation owned by the domain until tcp_destroy
+void *own(tcp_domain *d, size_t bytes)
+{
+    void *p = dev_alloc(d, bytes);
+    if (p) d->owned.push_back(p);
+    return p;
+}
+
+// Scratch device buffer released (after a stream synchronisation) when it goes out of scope.
+struct Scratch {
+    tcp_domain *d;
+    void *p;
+    Scratch(tcp_domain *dd, size_t bytes) : d(dd), p(dev_alloc(dd, bytes)) {}
+    ~Scratch()
+    {
+        if (p) {
+            (void)hipStreamSynchronize(d->stream);
+            dev_free(d, p);
+        }
+    }
+};
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// ---- timing ---------------------------------------------------------------
+struct KernelTimer {
+    tcp_domain *d;
+    int kind;
+    hipEvent_t a = nullptr, b = nullptr;
+    hipEvent_t take()
+    {
+        hipEvent_t e = nullptr;
+        if (!d->pool.empty()) {
+            e = d->pool.back();
+            d->pool.pop_back();
+        } else if (hipEventCreate(&e) != hipSuccess) {
+            e = nullptr;
+        }
+        return e;
+    }
+    KernelTimer(tcp_domain *dd, int k) : d(dd), kind(k)
+    {
+        if (!d->prof) return;
+        a = take();
+        b = take();
+        if (a) (void)hipEventRecord(a, d->stream);
+    }
+    ~KernelTimer()
+    {
+        if (!d->prof || !a || !b) return;
+        (void)hipEventRecord(b, d->stream);
+        d->records.push_back({kind, a, b});
+    }
+};
+
+// ---- per-step schedule ------------------------------------------------------
+template <typename S>
+void phase_step(tcp_domain *d)
+{
+    PfArgs a{};
+    a.geo = d->geo;
+    a.h_src = d->h[d->cur];
+    a.h_dst = d->h[1 - d->cur];
+    a.phi_old = d->phi[d->cur];
+    a.phi_new = d->phi[1 - d->cur];
+    for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+    a.omega_phi = d->omega_phi;
+    a.inv_xi = 1.0 / d->P.xi;
+    a.eps2 = d->P.normal_eps * d->P.normal_eps;
+    KernelTimer t(d, TCP_K_PHASE);
+    if (d->P.q_pf == 15) launch_pf<15, S, S>(a, d->stream);
+    else launch_pf<27, S, S>(a, d->stream);
+}
+
+template <typename S>
+void hydro_step(tcp_domain *d)
+{
+    const tcp_params &P = d->P;
+    HydroArgs a{};
+    a.geo = d->geo;
+    a.g_src = d->g[d->cur];
+    a.g_dst = d->g[1 - d->cur];
+    a.phi = d->phi[d->cur];
+    a.T = d->T;
+    a.twb = d->twb;
+    a.twt = d->twt;
+    for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+    a.rho_l = P.rho_l;
+    a.drho = P.rho_h - P.rho_l;
+    a.tau_l = d->tau_l;
+    a.dtau = d->tau_h - d->tau_l;
+    a.sigma_ref = P.sigma_ref;
+    a.sigma_t = P.sigma_t;
+    a.t_ref = P.t_ref;
+    a.xi = P.xi;
+    for (int k = 0; k < 3; ++k) {
+        a.g[k] = P.g[k];
+        a.uw_bot[k] = P.u_wall_bot[k];
+        a.uw_top[k] = P.u_wall_top[k];
+    }
+    a.omega_bulk = P.omega_bulk;
+    KernelTimer t(d, TCP_K_HYDRO);
+    launch_hydro<S, S>(a, d->stream);
+}
+
+template <typename S>
+void thermal_step(tcp_domain *d)
+{
+    const tcp_params &P = d->P;
+    if (P.thermal == TCP_THERMAL_LB) {
+        ThermalArgs a{};
+        a.geo = d->geo;
+        a.f_src = d->f[d->cur];
+        a.f_dst = d->f[1 - d->cur];
+        a.phi = d->phi[1 - d->cur];
+        for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+        a.T = d->T;
+        a.twb = d->twb;
+        a.twt = d->twt;
+        a.kappa_l = P.kappa_l;
+        a.dkappa = P.kappa_h - P.kappa_l;
+        a.t_shift = P.t_shift;
+        a.src = d->src;
+        KernelTimer t(d, TCP_K_THERMAL);
+        switch (P.q_thermal) {
+        case 7: launch_thermal<7, S, S>(a, d->stream); break;
+        case 15: launch_thermal<15, S, S>(a, d->stream); break;
+        case 19: launch_thermal<19, S, S>(a, d->stream); break;
+        default: launch_thermal<27, S, S>(a, d->stream); break;
+        }
+        return;
+    }
+    RkArgs a{};
+    a.geo = d->geo;
+    a.T = d->T;
+    a.phi = d->phi[1 - d->cur];
+    for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+    a.twb = d->twb;
+    a.twt = d->twt;
+    a.kappa_l = P.kappa_l;
+    a.dkappa = P.kappa_h - P.kappa_l;
+    a.src = d->src;
+    if (P.thermal == TCP_THERMAL_RK2) {
+        // theta = T + k1/2; T += R(theta)
+        a.theta_in = d->T;
+        a.theta_out = d->rk[0];
+        a.acc = nullptr;
+        a.first = 1;
+        a.last = 0;
+        a.a_next = 0.5;
+        a.w_acc = 0.0;
+        {
+            KernelTimer t(d, TCP_K_RK);
+            launch_rk<S, S>(a, d->stream);
+        }
+        a.theta_in = d->rk[0];
+        a.first = 1;
+        a.last = 1;
+        a.w_acc = 1.0;
+        KernelTimer t(d, TCP_K_RK);
+        launch_rk<S, S>(a, d->stream);
+        return;
+    }
+    // RK4: K1..K4, stage arguments T + K1/2, T + K2/2, T + K3
+    const void *in[4] = {d->T, d->rk[0], d->rk[1], d->rk[0]};
+    void *out[4] = {d->rk[0], d->rk[1], d->rk[0], nullptr};
+    const double wacc[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+    const double anext[4] = {0.5, 0.5, 1.0, 0.0};
+    a.acc = d->rk[2];
+    for (int s = 0; s < 4; ++s) {
+        a.theta_in = in[s];
+        a.theta_out = out[s];
+        a.first = s == 0;
+        a.last = s == 3;
+        a.w_acc = wacc[s];
+        a.a_next = anext[s];
+        KernelTimer t(d, TCP_K_RK);
+        launch_rk<S, S>(a, d->stream);
+    }
+}
+
+template <typename S>
+void one_step(tcp_domain *d)
+{
+    phase_step<S>(d);
+    hydro_step<S>(d);
+    thermal_step<S>(d);
+    d->cur = 1 - d->cur;
+}
+
+int validate(const tcp_params *p, std::string &why)
+{
+    char buf[256];
+    if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "grid dimensions must be >= 1"; return TCP_ERR_ARG; }
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31 || (int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 40)) {
+        why = "grid too large"; return TCP_ERR_ARG;
+    }
+    if (p->walls_y != 0 && p->walls_y != 1) { why = "walls_y must be 0 or 1"; return TCP_ERR_ARG; }
+    if (p->walls_y && p->ny < 2) { why = "walls need ny >= 2"; return TCP_ERR_ARG; }
+    if (p->q_pf != 15 && p->q_pf != 27) { why = "q_pf must be 15 or 27"; return TCP_ERR_ARG; }
+    if (p->q_thermal != 7 && p->q_thermal != 15 && p->q_thermal != 19 && p->q_thermal != 27) {
+        why = "q_thermal must be 7, 15, 19 or 27"; return TCP_ERR_ARG;
+    }
+    if (p->thermal < 0 || p->thermal > 2) { why = "thermal must be LB, RK2 or RK4"; return TCP_ERR_ARG; }
+    if (p->precision != TCP_FP64 && p->precision != TCP_FP32) { why = "precision must be FP64 or FP32"; return TCP_ERR_ARG; }
+    const double vals[] = {p->rho_h, p->rho_l, p->nu_h, p->nu_l, p->mobility, p->xi, p->kappa_h, p->kappa_l, p->omega_bulk};
+    const char *names[] = {"rho_h", "rho_l", "nu_h", "nu_l", "mobility", "xi", "kappa_h", "kappa_l", "omega_bulk"};
+    for (int k = 0; k < 9; ++k)
+        if (!finite_pos(vals[k])) {
+            std::snprintf(buf, sizeof buf, "%s must be finite and > 0", names[k]);
+            why = buf;
+            return TCP_ERR_ARG;
+        }
+    const double others[] = {p->sigma_ref, p->sigma_t, p->t_ref, p->g[0], p->g[1], p->g[2], p->normal_eps,
+                             p->u_wall_bot[0], p->u_wall_bot[1], p->u_wall_bot[2], p->u_wall_top[0],
+                             p->u_wall_top[1], p->u_wall_top[2], p->t_wall_bot, p->t_wall_top, p->t_shift};
+    for (double v : others)
+        if (!std::isfinite(v)) { why = "parameters must be finite"; return TCP_ERR_ARG; }
+    if (p->omega_bulk >= 2.0) { why = "omega_bulk must lie in (0, 2)"; return TCP_ERR_ARG; }
+    for (const double *uw : {p->u_wall_bot, p->u_wall_top})
+        if (std::sqrt(uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2]) >= 0.1) {
+            why = "wall speed must stay below 0.1"; return TCP_ERR_ARG;
+        }
+    if (p->thermal != TCP_THERMAL_LB) {
+        // real-axis stability of RK2 / RK4 against the most negative symbol of the
+        // isotropic Laplacian, -6 * 208/216 at k = (pi, pi, pi)
+        const double lmin = 6.0 * 208.0 / 216.0;
+        const double bound = (p->thermal == TCP_THERMAL_RK2 ? 2.0 : 2.785) / lmin;
+        const double kmax = p->kappa_h > p->kappa_l ? p->kappa_h : p->kappa_l;
+        if (kmax > bound) {
+            std::snprintf(buf, sizeof buf, "kappa %.4g exceeds the RK stability bound %.4g", kmax, bound);
+            why = buf;
+            return TCP_ERR_ARG;
+        }
+    }
+    return TCP_OK;
+}
+
+template <typename F>
+int guarded(tcp_domain *d, F &&fn)
+{
+    try {
+        return fn();
+    } catch (const std::bad_alloc &) {
+        return fail(d, TCP_ERR_OOM, "host allocation failed");
+    } catch (...) {
+        return fail(d, TCP_ERR_HIP, "unexpected exception");
+    }
+}
+
+int check_launch(tcp_domain *d)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(d, "kernel launch", e);
+    return TCP_OK;
+}
+
+} // namespace
+
+namespace {
+struct Piece {
+    void *p;
+    size_t bytes;
+};
+std::vector<Piece> state_pieces(const tcp_domain *d)
+{
+    const size_t N = (size_t)d->geo.N, sb = d->sb;
+    std::vector<Piece> v;
+    v.push_back({d->h[d->cur], N * d->P.q_pf * sb});
+    v.push_back({d->g[d->cur], N * 27 * sb});
+    if (d->P.thermal == TCP_THERMAL_LB) v.push_back({d->f[d->cur], N * d->P.q_thermal * sb});
+    v.push_back({d->phi[d->cur], N * sb});
+    for (int k = 0; k < 3; ++k) v.push_back({d->u[k], N * sb});
+    v.push_back({d->T, N * sb});
+    return v;
+}
+} // namespace
+
+extern "C" {
+
+int tcp_params_default(tcp_params *p)
+{
+    if (!p) return TCP_ERR_ARG;
+    std::memset(p, 0, sizeof *p);
+    p->nx = p->ny = p->nz = 32;
+    p->q_pf = 15;
+    p->q_thermal = 7;
+    p->thermal = TCP_THERMAL_LB;
+    p->precision = TCP_FP64;
+    p->rho_h = p->rho_l = 1.0;
+    p->nu_h = p->nu_l = 1.0 / 6.0;
+    p->mobility = 0.05;
+    p->xi = 5.0;
+    p->kappa_h = p->kappa_l = 0.2;
+    p->omega_bulk = 1.0;
+    p->normal_eps = 1e-6;
+    return TCP_OK;
+}
+
+int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tcp_domain **out)
+{
+    if (!p || !out) return fail(nullptr, TCP_ERR_ARG, "null argument");
+    *out = nullptr;
+    std::string why;
+    int rc = validate(p, why);
+    if (rc != TCP_OK) return fail(nullptr, rc, why);
+    if (alloc && (!alloc->alloc || !alloc->free)) return fail(nullptr, TCP_ERR_ARG, "allocator needs alloc and free");
+    tcp_domain *d = new (std::nothrow) tcp_domain();
+    if (!d) return fail(nullptr, TCP_ERR_OOM, "host allocation failed");
+    d->P = *p;
+    if (alloc) {
+        d->A = *alloc;
+        d->own_alloc = false;
+    }
+    d->stream = static_cast<hipStream_t>(stream);
+    d->sb = p->precision == TCP_FP64 ? 8 : 4;
+    d->geo.nx = p->nx;
+    d->geo.ny = p->ny;
+    d->geo.nz = p->nz;
+    d->geo.walls = p->walls_y;
+    d->geo.plane = (int64_t)p->nx * p->ny;
+    d->geo.N = d->geo.plane * p->nz;
+    d->omega_phi = 1.0 / (0.5 + 3.0 * p->mobility);
+    d->tau_h = 3.0 * p->nu_h;
+    d->tau_l = 3.0 * p->nu_l;
+    const size_t N = (size_t)d->geo.N, sb = d->sb;
+    bool ok = true;
+    for (int b = 0; b < 2; ++b) {
+        ok = ok && (d->h[b] = own(d, N * p->q_pf * sb));
+        ok = ok && (d->g[b] = own(d, N * 27 * sb));
+        if (p->thermal == TCP_THERMAL_LB) ok = ok && (d->f[b] = own(d, N * p->q_thermal * sb));
+        ok = ok && (d->phi[b] = own(d, N * sb));
+    }
+    for (int k = 0; k < 3; ++k) ok = ok && (d->u[k] = own(d, N * sb));
+    ok = ok && (d->T = own(d, N * sb));
+    if (p->thermal != TCP_THERMAL_LB)
+        for (int k = 0; k < (p->thermal == TCP_THERMAL_RK2 ? 1 : 3); ++k) ok = ok && (d->rk[k] = own(d, N * sb));
+    const size_t ncol = (size_t)p->nx * p->nz;
+    ok = ok && (d->twb = static_cast<double *>(own(d, ncol * sizeof(double))));
+    ok = ok && (d->twt = static_cast<double *>(own(d, ncol * sizeof(double))));
+    ok = ok && (d->partial = static_cast<double *>(own(d, 4 * kReduceBlocks * sizeof(double))));
+    ok = ok && (d->out4 = static_cast<double *>(own(d, 4 * sizeof(double))));
+    if (!ok) {
+        tcp_destroy(d);
+        return fail(nullptr, TCP_ERR_OOM, "device allocation failed");
+    }
+    std::vector<double> col(ncol, p->t_wall_bot);
+    hipError_t e = hipMemcpyAsync(d->twb, col.data(), ncol * sizeof(double), hipMemcpyHostToDevice, d->stream);
+    if (e == hipSuccess) {
+        std::fill(col.begin(), col.end(), p->t_wall_top);
+        e = hipMemcpyAsync(d->twt, col.data(), ncol * sizeof(double), hipMemcpyHostToDevice, d->stream);
+    }
+    // zero the fields so that an uninitialised read is well defined
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMemsetAsync(d->u[k], 0, N * sb, d->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(d->T, 0, N * sb, d->stream);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemsetAsync(d->phi[b], 0, N * sb, d->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
+    if (e != hipSuccess) {
+        std::string msg = std::string("set-up: ") + hipGetErrorString(e);
+        tcp_destroy(d);
+        return fail(nullptr, TCP_ERR_HIP, msg);
+    }
+    *out = d;
+    return TCP_OK;
+}
+
+int tcp_destroy(tcp_domain *d)
+{
+    if (!d) return TCP_ERR_ARG;
+    (void)hipStreamSynchronize(d->stream);
+    for (auto &r : d->records) {
+        (void)hipEventDestroy(r.start);
+        (void)hipEventDestroy(r.stop);
+    }
+    for (auto e : d->pool) (void)hipEventDestroy(e);
+    for (void *p : d->owned) dev_free(d, p);
+    delete d;
+    return TCP_OK;
+}
+
+int tcp_set_field(tcp_domain *d, int which, const double *host, const void *dev)
+{
+    if (!d) return TCP_ERR_ARG;
+    if ((host == nullptr) == (dev == nullptr)) return fail(d, TCP_ERR_ARG, "give exactly one of host or dev");
+    void *dst = nullptr;
+    switch (which) {
+    case TCP_PHI: dst = d->phi[d->cur]; break;
+    case TCP_UX: case TCP_UY: case TCP_UZ: dst = d->u[which - TCP_UX]; break;
+    case TCP_T: dst = d->T; break;
+    default: return fail(d, TCP_ERR_ARG, "field cannot be set");
+    }
+    return guarded(d, [&]() -> int {
+        const int64_t N = d->geo.N;
+        const double *src = static_cast<const double *>(dev);
+        Scratch tmp(d, host ? (size_t)N * sizeof(double) : 0);
+        if (host) {
+            if (!tmp.p) return fail(d, TCP_ERR_OOM, "staging allocation failed");
+            TCP_HIP(d, hipMemcpyAsync(tmp.p, host, (size_t)N * sizeof(double), hipMemcpyHostToDevice, d->stream));
+            src = static_cast<const double *>(tmp.p);
+        }
+        if (d->sb == 8) launch_from_f64<double>(src, dst, N, d->stream);
+        else launch_from_f64<float>(src, dst, N, d->stream);
+        d->initialized = false;
+        return check_launch(d);
+    });
+}
+
+int tcp_set_droplets(tcp_domain *d, const tcp_droplet *drops, int n)
+{
+    if (!d || n < 0 || (n > 0 && !drops)) return fail(d, TCP_ERR_ARG, "bad droplet list");
+    return guarded(d, [&]() -> int {
+        Scratch tmp(d, (size_t)(n > 0 ? n : 1) * 4 * sizeof(double));
+        if (!tmp.p) return fail(d, TCP_ERR_OOM, "staging allocation failed");
+        std::vector<double> xyzr((size_t)n * 4);
+        for (int k = 0; k < n; ++k) {
+            xyzr[4 * k + 0] = drops[k].x;
+            xyzr[4 * k + 1] = drops[k].y;
+            xyzr[4 * k + 2] = drops[k].z;
+            xyzr[4 * k + 3] = drops[k].r;
+        }
+        if (n > 0)
+            TCP_HIP(d, hipMemcpyAsync(tmp.p, xyzr.data(), xyzr.size() * sizeof(double), hipMemcpyHostToDevice, d->stream));
+        Droplets dl{};
+        dl.n = n;
+        dl.xyzr = static_cast<const double *>(tmp.p);
+        dl.inv_xi = 1.0 / d->P.xi;
+        dl.periodic[0] = 1;
+        dl.periodic[1] = d->P.walls_y ? 0 : 1;
+        dl.periodic[2] = 1;
+        if (d->sb == 8) launch_droplets<double>(d->geo, dl, d->phi[d->cur], d->stream);
+        else launch_droplets<float>(d->geo, dl, d->phi[d->cur], d->stream);
+        d->initialized = false;
+        return check_launch(d);
+    });
+}
+
+int tcp_set_heat_sources(tcp_domain *d, const tcp_heat_source *s, int n)
+{
+    if (!d) return TCP_ERR_ARG;
+    if (n < 0 || n > kMaxSources || (n > 0 && !s)) return fail(d, TCP_ERR_ARG, "at most 16 heat sources");
+    HeatSources hs{};
+    hs.n = n;
+    for (int k = 0; k < n; ++k) {
+        if (!std::isfinite(s[k].Q) || !finite_pos(s[k].w) || !std::isfinite(s[k].x) || !std::isfinite(s[k].y) ||
+            !std::isfinite(s[k].z) || !std::isfinite(s[k].d_cut))
+            return fail(d, TCP_ERR_ARG, "heat source needs finite values and w > 0");
+        hs.Q[k] = s[k].Q;
+        hs.x[k] = s[k].x;
+        hs.y[k] = s[k].y;
+        hs.z[k] = s[k].z;
+        hs.inv_w2[k] = 1.0 / (s[k].w * s[k].w);
+        hs.dcut2[k] = s[k].d_cut > 0.0 ? s[k].d_cut * s[k].d_cut : 0.0;
+    }
+    d->src = hs;
+    return TCP_OK;
+}
+
+int tcp_set_wall_temperature(tcp_domain *d, int wall, const double *Tw)
+{
+    if (!d) return TCP_ERR_ARG;
+    if ((wall != 0 && wall != 1) || !Tw) return fail(d, TCP_ERR_ARG, "wall must be 0 or 1, Tw non-NULL");
+    double *dst = wall == 0 ? d->twb : d->twt;
+    TCP_HIP(d, hipMemcpyAsync(dst, Tw, (size_t)d->P.nx * d->P.nz * sizeof(double), hipMemcpyHostToDevice, d->stream));
+    TCP_HIP(d, hipStreamSynchronize(d->stream));
+    return TCP_OK;
+}
+
+int tcp_initialize(tcp_domain *d)
+{
+    if (!d) return TCP_ERR_ARG;
+    InitArgs a{};
+    a.geo = d->geo;
+    a.q_pf = d->P.q_pf;
+    a.q_th = d->P.q_thermal;
+    a.phi = d->phi[d->cur];
+    for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+    a.T = d->T;
+    a.h = d->h[d->cur];
+    a.g = d->g[d->cur];
+    a.f = d->P.thermal == TCP_THERMAL_LB ? d->f[d->cur] : nullptr;
+    a.phi_other = d->phi[1 - d->cur];
+    a.t_shift = d->P.t_shift;
+    if (d->sb == 8) launch_init<double>(a, d->stream);
+    else launch_init<float>(a, d->stream);
+    int rc = check_launch(d);
+    if (rc == TCP_OK) d->initialized = true;
+    return rc;
+}
+
+int tcp_step(tcp_domain *d, int64_t nsteps)
+{
+    if (!d) return TCP_ERR_ARG;
+    if (nsteps < 0) return fail(d, TCP_ERR_ARG, "nsteps must be >= 0");
+    if (!d->initialized) return fail(d, TCP_ERR_STATE, "tcp_initialize must precede tcp_step");
+    return guarded(d, [&]() -> int {
+        for (int64_t n = 0; n < nsteps; ++n) {
+            if (d->sb == 8) one_step<double>(d);
+            else one_step<float>(d);
+        }
+        return check_launch(d);
+    });
+}
+
+int tcp_get_field(tcp_domain *d, int which, double *host, void *dev)
+{
+    if (!d) return TCP_ERR_ARG;
+    if ((host == nullptr) == (dev == nullptr)) return fail(d, TCP_ERR_ARG, "give exactly one of host or dev");
+    if (which < TCP_PHI || which > TCP_RHO) return fail(d, TCP_ERR_ARG, "unknown field");
+    return guarded(d, [&]() -> int {
+        const int64_t N = d->geo.N;
+        Scratch tmp(d, host ? (size_t)N * sizeof(double) : 0);
+        if (host && !tmp.p) return fail(d, TCP_ERR_OOM, "staging allocation failed");
+        ReadArgs a{};
+        a.geo = d->geo;
+        a.which = which; // TCP_PHI..TCP_RHO use the read-kernel codes 0..7
+        a.phi = d->phi[d->cur];
+        a.T = d->T;
+        a.g = d->g[d->cur];
+        for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+        a.rho_l = d->P.rho_l;
+        a.drho = d->P.rho_h - d->P.rho_l;
+        a.out = host ? static_cast<double *>(tmp.p) : static_cast<double *>(dev);
+        if (d->sb == 8) launch_read<double>(a, d->stream);
+        else launch_read<float>(a, d->stream);
+        int rc = check_launch(d);
+        if (rc != TCP_OK) return rc;
+        if (host) {
+            TCP_HIP(d, hipMemcpyAsync(host, tmp.p, (size_t)N * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+            TCP_HIP(d, hipStreamSynchronize(d->stream));
+        }
+        return TCP_OK;
+    });
+}
+
+int tcp_get_pdfs(tcp_domain *d, int which, double *host_out)
+{
+    if (!d || !host_out) return TCP_ERR_ARG;
+    const void *src = nullptr;
+    int q = 0;
+    if (which == TCP_PDF_H) { src = d->h[d->cur]; q = d->P.q_pf; }
+    else if (which == TCP_PDF_G) { src = d->g[d->cur]; q = 27; }
+    else if (which == TCP_PDF_F && d->P.thermal == TCP_THERMAL_LB) { src = d->f[d->cur]; q = d->P.q_thermal; }
+    else return fail(d, TCP_ERR_ARG, "unknown PDF field for this configuration");
+    return guarded(d, [&]() -> int {
+        const int64_t N = d->geo.N;
+        Scratch tmp(d, (size_t)N * q * sizeof(double));
+        if (!tmp.p) return fail(d, TCP_ERR_OOM, "staging allocation failed");
+        if (d->sb == 8)
+            launch_read_pdfs<double>(src, q, N, d->P.t_shift, which == TCP_PDF_F, static_cast<double *>(tmp.p), d->stream);
+        else
+            launch_read_pdfs<float>(src, q, N, d->P.t_shift, which == TCP_PDF_F, static_cast<double *>(tmp.p), d->stream);
+        int rc = check_launch(d);
+        if (rc != TCP_OK) return rc;
+        TCP_HIP(d, hipMemcpyAsync(host_out, tmp.p, (size_t)N * q * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+        TCP_HIP(d, hipStreamSynchronize(d->stream));
+        return TCP_OK;
+    });
+}
+
+int tcp_reduce(tcp_domain *d, double *mass, double centroid[3])
+{
+    if (!d || !mass || !centroid) return TCP_ERR_ARG;
+    if (d->sb == 8) launch_reduce<double>(d->geo, d->phi[d->cur], d->partial, d->out4, d->stream);
+    else launch_reduce<float>(d->geo, d->phi[d->cur], d->partial, d->out4, d->stream);
+    int rc = check_launch(d);
+    if (rc != TCP_OK) return rc;
+    double h4[4];
+    TCP_HIP(d, hipMemcpyAsync(h4, d->out4, sizeof h4, hipMemcpyDeviceToHost, d->stream));
+    TCP_HIP(d, hipStreamSynchronize(d->stream));
+    *mass = h4[0];
+    for (int k = 0; k < 3; ++k) centroid[k] = h4[k + 1] / h4[0];
+    for (double v : h4)
+        if (!std::isfinite(v)) return fail(d, TCP_ERR_NONFINITE, "phase field holds NaN or Inf");
+    return TCP_OK;
+}
+
+
+int tcp_state_bytes(const tcp_domain *d, size_t *bytes)
+{
+    if (!d || !bytes) return TCP_ERR_ARG;
+    size_t s = 0;
+    for (auto &p : state_pieces(d)) s += p.bytes;
+    *bytes = s;
+    return TCP_OK;
+}
+
+int tcp_save_state(tcp_domain *d, void *host)
+{
+    if (!d || !host) return TCP_ERR_ARG;
+    if (!d->initialized) return fail(d, TCP_ERR_STATE, "nothing to save before tcp_initialize");
+    char *dst = static_cast<char *>(host);
+    for (auto &p : state_pieces(d)) {
+        TCP_HIP(d, hipMemcpyAsync(dst, p.p, p.bytes, hipMemcpyDeviceToHost, d->stream));
+        dst += p.bytes;
+    }
+    TCP_HIP(d, hipStreamSynchronize(d->stream));
+    return TCP_OK;
+}
+
+int tcp_load_state(tcp_domain *d, const void *host)
+{
+    if (!d || !host) return TCP_ERR_ARG;
+    const char *src = static_cast<const char *>(host);
+    for (auto &p : state_pieces(d)) {
+        TCP_HIP(d, hipMemcpyAsync(p.p, src, p.bytes, hipMemcpyHostToDevice, d->stream));
+        src += p.bytes;
+    }
+    TCP_HIP(d, hipStreamSynchronize(d->stream));
+    d->initialized = true;
+    return TCP_OK;
+}
+
+int tcp_synchronize(tcp_domain *d)
+{
+    if (!d) return TCP_ERR_ARG;
+    TCP_HIP(d, hipStreamSynchronize(d->stream));
+    return TCP_OK;
+}
+
+int tcp_set_profiling(tcp_domain *d, int enabled)
+{
+    if (!d) return TCP_ERR_ARG;
+    d->prof = enabled != 0;
+    return TCP_OK;
+}
+
+int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches)
+{
+    if (!d || !ms || !launches) return TCP_ERR_ARG;
+    TCP_HIP(d, hipStreamSynchronize(d->stream));
+    for (int k = 0; k < TCP_K_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto &r : d->records) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, r.start, r.stop) == hipSuccess) {
+            ms[r.kind] += t;
+            launches[r.kind] += 1;
+        }
+        d->pool.push_back(r.start);
+        d->pool.push_back(r.stop);
+    }
+    d->records.clear();
+    return TCP_OK;
+}
+
+int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
+{
+    if (!d || !b) return TCP_ERR_ARG;
+    const double sb = (double)d->sb;
+    b[TCP_K_PHASE] = (2.0 * d->P.q_pf + 5.0) * sb;  // h in/out, phi^n in, phi^{n+1} out, u in
+    b[TCP_K_HYDRO] = (54.0 + 5.0) * sb;              // g in/out, phi^n, T^n in, u out
+    b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? (2.0 * d->P.q_thermal + 5.0) * sb : 0.0;
+    b[TCP_K_RK] = d->P.thermal == TCP_THERMAL_RK2 ? 13.0 * sb : (d->P.thermal == TCP_THERMAL_RK4 ? 33.0 * sb : 0.0);
+    return TCP_OK;
+}
+
+const char *tcp_error_string(int code)
+{
+    switch (code) {
+    case TCP_OK: return "ok";
+    case TCP_ERR_ARG: return "invalid argument";
+    case TCP_ERR_UNSUPPORTED: return "unsupported";
+    case TCP_ERR_HIP: return "HIP runtime error";
+    case TCP_ERR_OOM: return "out of memory";
+    case TCP_ERR_NONFINITE: return "non-finite values";
+    case TCP_ERR_STATE: return "call out of order";
+    default: return "unknown error";
+    }
+}
+
+const char *tcp_last_error(const tcp_domain *d)
+{
+    return d ? d->err.c_str() : g_create_error.c_str();
+}
+
+} // extern "C"

@@ -1,0 +1,90 @@
+"""C interface checks that need no GPU: the built library loads, exports every
+entry point include/tcplb.h declares, its parameter structs match the
+header's layout, and invalid parameters are rejected before any device work."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tcplb.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(tcp_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2401_03041_amd import tcplb
+    lib = tcplb.load()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(tcplb.EXPORTS) == names
+
+
+def test_params_layout_matches_header():
+    """Field order of tcp_params in the header equals the ctypes mirror."""
+    from paper_2401_03041_amd import tcplb
+    text = open(HEADER).read()
+    body = text[text.index("typedef struct {\n    int32_t nx"):]
+    body = body[:body.index("} tcp_params;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    names, count = [], 0
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl or decl.startswith("typedef"):
+            decl = decl.replace("typedef struct {", "").strip()
+        if not decl:
+            continue
+        parts = decl.split(None, 1)
+        width = 4 if parts[0] == "int32_t" else 8
+        for v in parts[1].split(","):
+            v = v.strip()
+            names.append(v.split("[")[0])
+            count += width * (int(v.split("[")[1].rstrip("]")) if "[" in v else 1)
+    assert names == [f for f, _ in tcplb.Params._fields_]
+    assert C.sizeof(tcplb.Params) == count
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 0), ("q_pf", 19), ("q_thermal", 9), ("thermal", 3), ("precision", 2), ("nu_l", 0.0),
+    ("mobility", -1.0), ("xi", 0.0), ("kappa_h", float("nan")), ("omega_bulk", 2.0)])
+def test_invalid_parameters_rejected_without_gpu(field, value):
+    from paper_2401_03041_amd import tcplb
+    lib = tcplb.load()
+    p = tcplb.Params()
+    assert lib.tcp_params_default(C.byref(p)) == 0
+    setattr(p, field, value)
+    h = C.c_void_p()
+    rc = lib.tcp_create(C.byref(p), None, None, C.byref(h))
+    assert rc == -1
+    assert not h.value
+    assert lib.tcp_last_error(None)
+
+
+def test_rk_stability_bound_rejected_without_gpu():
+    from paper_2401_03041_amd import tcplb
+    lib = tcplb.load()
+    p = tcplb.Params()
+    lib.tcp_params_default(C.byref(p))
+    p.thermal = 1
+    p.kappa_h = p.kappa_l = 0.4  # above 2/5.78 for RK2
+    h = C.c_void_p()
+    assert lib.tcp_create(C.byref(p), None, None, C.byref(h)) == -1
+    assert b"stability" in lib.tcp_last_error(None)
+    p.kappa_h = p.kappa_l = 2.25  # the capture channel's diffusivity needs the LB thermal solver
+    p.thermal = 2
+    assert lib.tcp_create(C.byref(p), None, None, C.byref(h)) == -1
+
+
+def test_error_strings():
+    from paper_2401_03041_amd import tcplb
+    lib = tcplb.load()
+    for code in range(-6, 1):
+        assert lib.tcp_error_string(code)

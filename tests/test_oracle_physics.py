@@ -138,6 +138,26 @@ def test_shear_wave_decay_gives_viscosity(phase, nu):
     assert nu_meas == pytest.approx(nu, rel=1e-2)
 
 
+def test_diagonal_shear_wave_uses_deviatoric_rates():
+    """A shear wave travelling along the lattice diagonal strains the diagonal
+    deviators (xx - yy) as well: it decays with the same nu only if those moments
+    relax with omega(phi) too."""
+    n, nu = 32, 0.05
+    cfg = W.make(shape=(n, n, 1), nu_h=nu, nu_l=nu)
+    k = 2 * np.pi / n
+    yy, xx = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    s = np.sin(k * (xx + yy))[None]
+    amp0 = 1e-4
+    u = [amp0 * s / np.sqrt(2), -amp0 * s / np.sqrt(2), np.zeros_like(s)]
+    d = oracle_domain(cfg, phi=np.ones((1, n, n)), u=u)
+    amp = []
+    for t in (20, 220):
+        d.step(t - (0 if not amp else 20))
+        amp.append(np.sum((d.get_field("ux") - d.get_field("uy")) * s))
+    nu_meas = np.log(amp[0] / amp[1]) / (2 * k * k * 200)
+    assert nu_meas == pytest.approx(nu, rel=1e-2)
+
+
 def test_poiseuille_body_force():
     """Channel flow driven by F_b = rho g between bounce-back walls at y = -1/2 and
     y = H - 1/2: parabola with u_max = g H^2 / (8 nu)."""
@@ -209,6 +229,22 @@ def test_hydrostatic_pressure_across_interface():
 # ---------------------------------------------------------------------------------------
 # Surface tension (Sec. 2.1 F_s, readings R4, R5, R6)
 # ---------------------------------------------------------------------------------------
+def test_flat_interface_has_no_pressure_structure():
+    """beta = 12 sigma/xi and k = 3 sigma xi/2 make mu_phi vanish on the tanh profile,
+    so a flat interface carries no force density and the pressure stays flat through
+    it: only an O(1/xi^2) spike of 0.08 sigma/xi at xi = 4 remains, where halving beta
+    leaves a bump of 0.375 sigma/xi)."""
+    ny, xi, sig = 64, 4.0, 2.5e-2
+    cfg = W.make(shape=(1, ny, 1), xi=xi, sigma_ref=sig, nu_h=0.2, nu_l=0.2)
+    y = np.arange(ny, dtype=np.float64)
+    phi0 = _tanh_layer(y, 16.0, 48.0, xi)
+    d = oracle_domain(cfg, phi=phi0[None, :, None])
+    d.step(2000)
+    p = d.get_field("p")[0, :, 0]
+    assert np.max(p) - np.min(p) < 0.15 * sig / xi
+
+
+
 @pytest.mark.parametrize("rho_l", [1.0, 0.1])
 def test_laplace_pressure_jump_cylinder(rho_l):
     """A cylindrical drop (2D box) of radius R holds the Laplace jump

@@ -98,6 +98,21 @@ def test_hydro_equilibrium_moments():
         assert np.allclose(M2, ps * CS2 * np.eye(3) + np.outer(u, u), atol=1e-16)
 
 
+def test_guo_source_moments():
+    """Guo's source in velocity form is defined by its moments: zero mass, first
+    moment a, second moment u a + a u (so its second central moments vanish)."""
+    e, w, _ = O.stencil(27)
+    rng = np.random.default_rng(7)
+    for _ in range(5):
+        u = rng.uniform(-0.1, 0.1, 3)
+        a = rng.uniform(-1e-3, 1e-3, 3)
+        S = O.guo_source(u, a)
+        assert abs(S.sum()) < 1e-17
+        assert np.allclose((S[:, None] * e).sum(0), a, atol=1e-17)
+        M2 = np.einsum("i,ia,ib->ab", S, e, e)
+        assert np.allclose(M2, np.outer(u, a) + np.outer(a, u), atol=1e-17)
+
+
 # ---------------------------------------------------------------------------------------
 # Central-moment collision (readings R13-R15)
 # ---------------------------------------------------------------------------------------
@@ -210,6 +225,30 @@ def test_isotropic_stencils_exact_on_polynomials():
     g, l = d.iso_grad_lap(quad, 4, 5, 3)
     assert np.allclose(g, [4 + 0.7 * 5, 2 * 2 * 5 + 0.7 * 4 - 0.1 * 3, -0.5 * 3 - 0.1 * 5], atol=1e-12)
     assert l == pytest.approx(1.0 + 4.0 - 0.5, abs=1e-12)
+
+
+def test_wall_ghosts_are_method_of_images():
+    """At a wall row the stencils see the field continued across the wall plane
+    y = -1/2: evenly for phi (mirror, zero normal derivative) and oddly about T_w for
+    the temperature (Dirichlet).  Compare with the same stencils on the explicitly
+    continued field in a periodic box of twice the height."""
+    nx, ny, nz = 5, 6, 4
+    rng = np.random.default_rng(3)
+    f = rng.uniform(0, 1, (nz, ny, nx))
+    tw_b, tw_t = 0.3, 0.8
+    walls = O.OracleDomain(W.make(shape=(nx, ny, nz), periodic_y=False, t_wall_bot=tw_b, t_wall_top=tw_t))
+    per = O.OracleDomain(W.make(shape=(nx, 2 * ny, nz)))
+    even = np.concatenate([f, f[:, ::-1, :]], axis=1)            # rows ny..2ny-1 mirror the fluid rows
+    odd_b = np.concatenate([f, 2 * tw_b - f[:, ::-1, :]], axis=1)  # continuation below the bottom wall
+    odd_t = np.concatenate([f, 2 * tw_t - f[:, ::-1, :]], axis=1)  # continuation above the top wall
+    for x, z in ((0, 0), (2, 3), (4, 1)):
+        for y in (0, ny - 1):
+            g1, l1 = walls.iso_grad_lap(f, x, y, z, "mirror")
+            g2, l2 = per.iso_grad_lap(even, x, y, z, "mirror")
+            assert np.allclose(g1, g2, atol=1e-14) and l1 == pytest.approx(l2, abs=1e-13)
+            g1, l1 = walls.iso_grad_lap(f, x, y, z, "dirichlet")
+            g2, l2 = per.iso_grad_lap(odd_b if y == 0 else odd_t, x, y, z, "mirror")
+            assert np.allclose(g1, g2, atol=1e-13) and l1 == pytest.approx(l2, abs=1e-12)
 
 
 # ---------------------------------------------------------------------------------------
