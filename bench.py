@@ -168,7 +168,10 @@ def main() -> int:
         copy_calibration()
         return 0
 
+    from paper_2401_03041_amd import tcplb
     from paper_2401_03041_amd import workloads as W
+    copy_gbs = tcplb.bandwidth_probe()
+    _log(f"streaming copy probe: {copy_gbs:.0f} GB/s")
     cfg = W.droplet_block(n=args.n, precision="fp32")
     fp32 = run_gpu(cfg, args.steps, args.warmup, "fp32")
     fp64_steps = args.steps // 2 if args.fp64_steps is None else args.fp64_steps
@@ -192,6 +195,7 @@ def main() -> int:
                                "D3Q15 phase field + D3Q27 hydro + D3Q7 thermal LB, shifted-FP32 storage",
                    "grid": [args.n] * 3, "precision": "fp32", "parallelism": "single GPU"},
         "roofline": roofline(fp32, "fp32"),
+        "copy_probe_GBs": round(copy_gbs, 1),
         "cpu_baseline": base,
         "step_bytes_per_cell": fp32["step_bytes_per_cell"],
         "effective_GBs": round(fp32["effective_GBs"], 1),

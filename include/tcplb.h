@@ -186,6 +186,12 @@ int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches);
  * read and written once, each scalar field read or written once). */
 int tcp_algorithmic_bytes(const tcp_domain *d, double *bytes_per_cell);
 
+/* Practical HBM ceiling: allocate two device buffers of `bytes` each, copy
+ * one into the other `reps` times with a 16-byte-per-lane streaming kernel on
+ * the default stream, and return the best copy rate (read + write bytes per
+ * second, in GB/s).  Synchronises; frees its buffers before returning. */
+int tcp_bandwidth_probe(size_t bytes, int reps, double *gbs);
+
 const char *tcp_error_string(int code);
 const char *tcp_last_error(const tcp_domain *d);
 

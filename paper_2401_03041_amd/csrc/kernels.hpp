@@ -6,10 +6,6 @@
 
 namespace tcp {
 
-// Threads of one work-group: 64 along x (one wavefront per row), 4 rows in y.
-constexpr int kBX = 64;
-constexpr int kBY = 4;
-
 // K1: conservative Allen-Cahn LB (Eq. lb_interface, Eq. phasefieldforce)
 struct PfArgs {
     Geometry geo;
@@ -129,5 +125,8 @@ void launch_read_pdfs(const void *src, int q, int64_t N, double t_shift, int is_
 constexpr int kReduceBlocks = 1024;
 template <typename S>
 void launch_reduce(const Geometry &g, const void *phi, double *partial, double *out4, hipStream_t s);
+
+// streaming copy of n16 16-byte words (bandwidth probe)
+void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);
 
 } // namespace tcp

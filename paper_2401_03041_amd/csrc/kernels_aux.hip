@@ -163,6 +163,12 @@ __global__ void __launch_bounds__(kThreads) k_reduce_final(const double *partial
         for (int k = 0; k < 4; ++k) out4[k] = sh[k][0];
 }
 
+__global__ void __launch_bounds__(kThreads) k_copy16(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
+        dst[i] = src[i];
+}
+
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
 
 } // namespace
@@ -211,6 +217,12 @@ void launch_reduce(const Geometry &g, const void *phi, double *partial, double *
     hipLaunchKernelGGL((k_reduce_partial<S>), dim3(kReduceBlocks), dim3(kThreads), 0, s, g,
                        static_cast<const S *>(phi), partial);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, s, partial, kReduceBlocks, out4);
+}
+
+void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_copy16, dim3(2048 * 8), dim3(kThreads), 0, s, static_cast<const float4 *>(src),
+                       static_cast<float4 *>(dst), n16);
 }
 
 #define TCP_AUX_INST(S)                                                                                      \

@@ -20,14 +20,9 @@
 
 namespace tcp {
 
-template <typename S, typename R>
-__global__ void __launch_bounds__(kBX *kBY) k_hydro(const HydroArgs a)
+template <typename S, typename R, bool WALL>
+__device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x;
-    const int y = blockIdx.y * kBY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.geo.nx || y >= a.geo.ny) return;
-    const Nbr nb(a.geo, x, y, z);
     const int64_t N = a.geo.N;
     const S *gs = static_cast<const S *>(a.g_src);
 
@@ -36,63 +31,67 @@ __global__ void __launch_bounds__(kBX *kBY) k_hydro(const HydroArgs a)
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        if (nb.ghost(-ey)) {
+        if (WALL && nb.ghost(-ey)) {
             const double *uw = ey > 0 ? a.uw_bot : a.uw_top;
-            const R eu = R(ex) * R(uw[0]) + R(ey) * R(uw[1]) + R(ez) * R(uw[2]);
-            g[i] = ld<R>(gs + opposite<27>(i) * N + nb.c) + R(6.0 * weight<27>(i)) * eu;
+            const double eu = ex * uw[0] + ey * uw[1] + ez * uw[2];
+            g[i] = ld<R>(elem(gs + opposite<27>(i) * N, nb.c)) + R(6.0 * weight<27>(i) * eu);
         } else {
-            g[i] = ld<R>(gs + i * N + nb.at(-ex, -ey, -ez));
+            g[i] = ld<R>(elem(gs + i * N, nb.at(-ex, -ey, -ez)));
         }
     }
-    // zeroth, first and second raw moments
-    R ps = R(0), u0[3] = {R(0), R(0), R(0)};
+    // zeroth, first and second raw moments from sums and differences of opposite pairs
+    R ps = g[0], u0[3] = {R(0), R(0), R(0)};
     R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);
 #pragma unroll
-    for (int i = 0; i < 27; ++i) {
+    for (int i = 1; i < 27; ++i) {
+        if (opposite<27>(i) < i) continue;
+        const int o = opposite<27>(i);
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        ps += g[i];
-        u0[0] += R(ex) * g[i];
-        u0[1] += R(ey) * g[i];
-        u0[2] += R(ez) * g[i];
-        mxx += R(ex * ex) * g[i];
-        myy += R(ey * ey) * g[i];
-        mzz += R(ez * ez) * g[i];
-        mxy += R(ex * ey) * g[i];
-        mxz += R(ex * ez) * g[i];
-        myz += R(ey * ez) * g[i];
+        const R sm = g[i] + g[o], df = g[i] - g[o];
+        ps += sm;
+        if (ex) u0[0] += R(ex) * df;
+        if (ey) u0[1] += R(ey) * df;
+        if (ez) u0[2] += R(ez) * df;
+        if (ex) mxx += sm;
+        if (ey) myy += sm;
+        if (ez) mzz += sm;
+        if (ex * ey) mxy += R(ex * ey) * sm;
+        if (ex * ez) mxz += R(ex * ez) * sm;
+        if (ey * ez) myz += R(ey * ez) * sm;
     }
 
     // phi^n: value, gradient, Laplacian; T^n: value, gradient
     const S *pp = static_cast<const S *>(a.phi);
     const S *tp = static_cast<const S *>(a.T);
-    const R phi = ld<R>(pp + nb.c);
-    const R T = ld<R>(tp + nb.c);
+    const R phi = ld<R>(elem(pp, nb.c));
+    const R T = ld<R>(elem(tp, nb.c));
     R gp[3] = {R(0), R(0), R(0)}, gT[3] = {R(0), R(0), R(0)}, lap = R(0);
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
         const R w = R(weight<27>(i));
-        const int64_t at = nb.at(ex, ey, ez);
-        const R pv = ld<R>(pp + at);
-        R tv = ld<R>(tp + at);
-        if (nb.ghost(ey)) {
+        const uint32_t at = nb.at(ex, ey, ez);
+        const R pv = ld<R>(elem(pp, at));
+        R tv = ld<R>(elem(tp, at));
+        if (WALL && nb.ghost(ey)) {
             const double *tw = ey < 0 ? a.twb : a.twt;
             tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;
         }
-        gp[0] += R(ex) * w * pv;
-        gp[1] += R(ey) * w * pv;
-        gp[2] += R(ez) * w * pv;
-        lap += w * (pv - phi);
-        gT[0] += R(ex) * w * tv;
-        gT[1] += R(ey) * w * tv;
-        gT[2] += R(ez) * w * tv;
+        if (ex) gp[0] += R(ex) * w * pv;
+        if (ey) gp[1] += R(ey) * w * pv;
+        if (ez) gp[2] += R(ez) * w * pv;
+        lap += w * pv;
+        if (ex) gT[0] += R(ex) * w * tv;
+        if (ey) gT[1] += R(ey) * w * tv;
+        if (ez) gT[2] += R(ez) * w * tv;
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         gp[k] *= R(3);
         gT[k] *= R(3);
     }
-    lap *= R(6);
+    // sum over the 26 neighbours of w (psi_nb - psi) = sum w psi_nb - (1 - w_0) psi
+    lap = R(6) * (lap - R(1.0 - weight<27>(0)) * phi);
 
     // material laws
     const R phic = fmin(fmax(phi, R(0)), R(1));
@@ -145,35 +144,71 @@ __global__ void __launch_bounds__(kBX *kBY) k_hydro(const HydroArgs a)
     const R cxx = third * (tr + d1 + d2), cyy = cxx - d1, czz = cxx - d2;
     const R cxy = om1 * pxy, cxz = om1 * pxz, cyz = om1 * pyz;
 
+    // inverse transform of the relaxed second-order moments: the correction of PDF
+    // (a, b, c) is sum_k Z.m_k[c] A_k[a][b]
     const Axis1D<R> X(u[0]), Y(u[1]), Z(u[2]);
+    R A0[3][3], A1[3][3], A2[3][3];
+#pragma unroll
+    for (int ia = 0; ia < 3; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < 3; ++ib) {
+            A0[ia][ib] = cxx * X.m2[ia] * Y.m0[ib] + cyy * X.m0[ia] * Y.m2[ib] + cxy * X.m1[ia] * Y.m1[ib];
+            A1[ia][ib] = cxz * X.m1[ia] * Y.m0[ib] + cyz * X.m0[ia] * Y.m1[ib];
+            A2[ia][ib] = czz * X.m0[ia] * Y.m0[ib];
+        }
+
+    // g_eq + S/2 = w [C + 3 e.u + 3/2 e.a + 9/2 e.u (e.u + e.a)]: opposite directions share
+    // the even part and flip the odd one
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     const R ua = u[0] * acc[0] + u[1] * acc[1] + u[2] * acc[2];
+    const R C = ps - R(1.5) * (uu + ua);
     S *gd = static_cast<S *>(a.g_dst);
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        const int ia = ex + 1, ib = ey + 1, ic = ez + 1;
-        const R w = R(weight<27>(i));
-        const R eu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
-        const R ea = R(ex) * acc[0] + R(ey) * acc[1] + R(ez) * acc[2];
-        const R geq = w * (ps + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-        const R src = w * (R(3) * (ea - ua) + R(9) * eu * ea);
-        const R dz0 = Z.m0[ic], dz1 = Z.m1[ic], dz2 = Z.m2[ic];
-        const R corr = dz0 * (cxx * X.m2[ia] * Y.m0[ib] + cyy * X.m0[ia] * Y.m2[ib] + cxy * X.m1[ia] * Y.m1[ib]) +
-                       dz1 * (cxz * X.m1[ia] * Y.m0[ib] + cyz * X.m0[ia] * Y.m1[ib]) +
-                       dz2 * (czz * X.m0[ia] * Y.m0[ib]);
-        st(gd + i * N + nb.c, geq + R(0.5) * src + corr);
+    {
+        const R corr = Z.m0[1] * A0[1][1] + Z.m1[1] * A1[1][1] + Z.m2[1] * A2[1][1];
+        st(elem(gd, nb.c), R(weight<27>(0)) * C + corr);
     }
 #pragma unroll
-    for (int k = 0; k < 3; ++k) st(static_cast<S *>(a.u[k]) + nb.c, u[k]);
+    for (int i = 1; i < 27; ++i) {
+        if (opposite<27>(i) < i) continue;
+        const int o = opposite<27>(i);
+        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+        const R w = R(weight<27>(i));
+        R eu = R(0), ea = R(0);
+        if (ex) { eu += R(ex) * u[0]; ea += R(ex) * acc[0]; }
+        if (ey) { eu += R(ey) * u[1]; ea += R(ey) * acc[1]; }
+        if (ez) { eu += R(ez) * u[2]; ea += R(ez) * acc[2]; }
+        const R even = w * C + R(4.5) * w * (eu * (eu + ea));
+        const R odd = R(3) * w * eu + R(1.5) * w * ea;
+        const int ia = ex + 1, ib = ey + 1, ic = ez + 1;
+        const int oa = 1 - ex, ob = 1 - ey, oc = 1 - ez;
+        const R ci = Z.m0[ic] * A0[ia][ib] + Z.m1[ic] * A1[ia][ib] + Z.m2[ic] * A2[ia][ib];
+        const R co = Z.m0[oc] * A0[oa][ob] + Z.m1[oc] * A1[oa][ob] + Z.m2[oc] * A2[oa][ob];
+        st(elem(gd + i * N, nb.c), even + odd + ci);
+        st(elem(gd + o * N, nb.c), even - odd + co);
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) st(elem(static_cast<S *>(a.u[k]), nb.c), u[k]);
+}
+
+// One thread per cell; rows next to a wall take the bounce-back and ghost paths
+// (a wavefront is one x-row, so the choice is uniform across it).
+template <typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_hydro(const HydroArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    if (nb.below || nb.above)
+        hydro_cell<S, R, true>(a, nb);
+    else
+        hydro_cell<S, R, false>(a, nb);
 }
 
 template <typename S, typename R>
 void launch_hydro(const HydroArgs &a, hipStream_t s)
 {
-    dim3 block(kBX, kBY, 1);
-    dim3 grid((a.geo.nx + kBX - 1) / kBX, (a.geo.ny + kBY - 1) / kBY, a.geo.nz);
-    hipLaunchKernelGGL((k_hydro<S, R>), grid, block, 0, s, a);
+    const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_hydro<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
 template void launch_hydro<double, double>(const HydroArgs &, hipStream_t);

@@ -12,14 +12,9 @@
 
 namespace tcp {
 
-template <int Q, typename S, typename R>
-__global__ void __launch_bounds__(kBX *kBY) k_phase_field(const PfArgs a)
+template <int Q, typename S, typename R, bool WALL>
+__device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x;
-    const int y = blockIdx.y * kBY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.geo.nx || y >= a.geo.ny) return;
-    const Nbr nb(a.geo, x, y, z);
     const int64_t N = a.geo.N;
     const S *hs = static_cast<const S *>(a.h_src);
 
@@ -28,18 +23,22 @@ __global__ void __launch_bounds__(kBX *kBY) k_phase_field(const PfArgs a)
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
-        if (nb.ghost(-ey))
-            h[i] = ld<R>(hs + opposite<Q>(i) * N + nb.c);
+        if (WALL && nb.ghost(-ey))
+            h[i] = ld<R>(elem(hs + opposite<Q>(i) * N, nb.c));
         else
-            h[i] = ld<R>(hs + i * N + nb.at(-ex, -ey, -ez));
+            h[i] = ld<R>(elem(hs + i * N, nb.at(-ex, -ey, -ez)));
     }
-    R phi = R(0), j[3] = {R(0), R(0), R(0)};
+    // zeroth and first moments from sums and differences of opposite pairs
+    R phi = h[0], j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        phi += h[i];
-        j[0] += R(vel<Q>(i, 0)) * h[i];
-        j[1] += R(vel<Q>(i, 1)) * h[i];
-        j[2] += R(vel<Q>(i, 2)) * h[i];
+    for (int i = 1; i < Q; ++i) {
+        if (opposite<Q>(i) < i) continue;
+        const int o = opposite<Q>(i);
+        const R df = h[i] - h[o];
+        phi += h[i] + h[o];
+        if (vel<Q>(i, 0)) j[0] += R(vel<Q>(i, 0)) * df;
+        if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
+        if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
     }
 
     // interface normal from the isotropic gradient of phi^n (mirror ghosts)
@@ -48,7 +47,7 @@ __global__ void __launch_bounds__(kBX *kBY) k_phase_field(const PfArgs a)
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        const R v = R(weight<27>(i)) * ld<R>(po + nb.at(ex, ey, ez));
+        const R v = R(weight<27>(i)) * ld<R>(elem(po, nb.at(ex, ey, ez)));
         gr[0] += R(ex) * v;
         gr[1] += R(ey) * v;
         gr[2] += R(ez) * v;
@@ -62,7 +61,7 @@ __global__ void __launch_bounds__(kBX *kBY) k_phase_field(const PfArgs a)
 
     R u[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) u[k] = ld<R>(static_cast<const S *>(a.u[k]) + nb.c);
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
 
     // relaxed first-order central moment of h - h_eq + S/2
     const R om1 = R(1) - R(a.omega_phi);
@@ -81,17 +80,30 @@ __global__ void __launch_bounds__(kBX *kBY) k_phase_field(const PfArgs a)
         const R eu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
         const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
         const R heq = phi * w * (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-        st(hd + i * N + nb.c, heq + R(0.5) * w * eF + d[i]);
+        st(elem(hd + i * N, nb.c), heq + R(0.5) * w * eF + d[i]);
     }
-    st(static_cast<S *>(a.phi_new) + nb.c, phi);
+    st(elem(static_cast<S *>(a.phi_new), nb.c), phi);
+}
+
+// One thread per cell; rows next to a wall take the bounce-back path (a
+// wavefront is one x-row, so the choice is uniform across it).
+template <int Q, typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_phase_field(const PfArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    if (nb.below || nb.above)
+        phase_field_cell<Q, S, R, true>(a, nb);
+    else
+        phase_field_cell<Q, S, R, false>(a, nb);
 }
 
 template <int Q, typename S, typename R>
 void launch_pf(const PfArgs &a, hipStream_t s)
 {
-    dim3 block(kBX, kBY, 1);
-    dim3 grid((a.geo.nx + kBX - 1) / kBX, (a.geo.ny + kBY - 1) / kBY, a.geo.nz);
-    hipLaunchKernelGGL((k_phase_field<Q, S, R>), grid, block, 0, s, a);
+    const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_phase_field<Q, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
 template void launch_pf<15, double, double>(const PfArgs &, hipStream_t);

@@ -15,14 +15,9 @@
 
 namespace tcp {
 
-template <int Q, typename S, typename R>
-__global__ void __launch_bounds__(kBX *kBY) k_thermal(const ThermalArgs a)
+template <int Q, typename S, typename R, bool WALL>
+__device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb, int x, int y, int z)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x;
-    const int y = blockIdx.y * kBY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.geo.nx || y >= a.geo.ny) return;
-    const Nbr nb(a.geo, x, y, z);
     const int64_t N = a.geo.N;
     const S *fs = static_cast<const S *>(a.f_src);
     const R ts = R(a.t_shift);
@@ -31,27 +26,31 @@ __global__ void __launch_bounds__(kBX *kBY) k_thermal(const ThermalArgs a)
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
-        if (nb.ghost(-ey)) {
+        if (WALL && nb.ghost(-ey)) {
             const double *tw = ey > 0 ? a.twb : a.twt;
             const R w2 = R(2.0 * weight<Q>(i));
-            f[i] = w2 * (R(tw[nb.col(0, 0, a.geo)]) - ts) - ld<R>(fs + opposite<Q>(i) * N + nb.c);
+            f[i] = w2 * (R(tw[nb.col(0, 0, a.geo)]) - ts) - ld<R>(elem(fs + opposite<Q>(i) * N, nb.c));
         } else {
-            f[i] = ld<R>(fs + i * N + nb.at(-ex, -ey, -ez));
+            f[i] = ld<R>(elem(fs + i * N, nb.at(-ex, -ey, -ez)));
         }
     }
-    R Tp = R(0), j[3] = {R(0), R(0), R(0)};
+    // zeroth and first moments from sums and differences of opposite pairs
+    R Tp = f[0], j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        Tp += f[i];
-        j[0] += R(vel<Q>(i, 0)) * f[i];
-        j[1] += R(vel<Q>(i, 1)) * f[i];
-        j[2] += R(vel<Q>(i, 2)) * f[i];
+    for (int i = 1; i < Q; ++i) {
+        if (opposite<Q>(i) < i) continue;
+        const int o = opposite<Q>(i);
+        const R df = f[i] - f[o];
+        Tp += f[i] + f[o];
+        if (vel<Q>(i, 0)) j[0] += R(vel<Q>(i, 0)) * df;
+        if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
+        if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
     }
     const R T = Tp + ts;
     R u[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) u[k] = ld<R>(static_cast<const S *>(a.u[k]) + nb.c);
-    const R phic = fmin(fmax(ld<R>(static_cast<const S *>(a.phi) + nb.c), R(0)), R(1));
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
+    const R phic = fmin(fmax(ld<R>(elem(static_cast<const S *>(a.phi), nb.c)), R(0)), R(1));
     const R kap = R(a.kappa_l) + phic * R(a.dkappa);
     const R om1 = R(1) - R(1) / (R(0.5) + R(3) * kap);
     const R v[3] = {om1 * (j[0] - T * u[0]), om1 * (j[1] - T * u[1]), om1 * (j[2] - T * u[2])};
@@ -65,42 +64,49 @@ __global__ void __launch_bounds__(kBX *kBY) k_thermal(const ThermalArgs a)
         const R w = R(weight<Q>(i));
         const R eu = R(vel<Q>(i, 0)) * u[0] + R(vel<Q>(i, 1)) * u[1] + R(vel<Q>(i, 2)) * u[2];
         const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
-        st(fd + i * N + nb.c, w * (Tp * (R(1) + zeta) + ts * zeta) + d[i] + w * q);
+        st(elem(fd + i * N, nb.c), w * (Tp * (R(1) + zeta) + ts * zeta) + d[i] + w * q);
     }
-    st(static_cast<S *>(a.T) + nb.c, T);
+    st(elem(static_cast<S *>(a.T), nb.c), T);
+}
+
+// One thread per cell; rows next to a wall take the anti-bounce-back path.
+template <int Q, typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_thermal(const ThermalArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    if (nb.below || nb.above)
+        thermal_cell<Q, S, R, true>(a, nb, x, y, z);
+    else
+        thermal_cell<Q, S, R, false>(a, nb, x, y, z);
 }
 
 template <int Q, typename S, typename R>
 void launch_thermal(const ThermalArgs &a, hipStream_t s)
 {
-    dim3 block(kBX, kBY, 1);
-    dim3 grid((a.geo.nx + kBX - 1) / kBX, (a.geo.ny + kBY - 1) / kBY, a.geo.nz);
-    hipLaunchKernelGGL((k_thermal<Q, S, R>), grid, block, 0, s, a);
+    const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_thermal<Q, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
-template <typename S, typename R>
-__global__ void __launch_bounds__(kBX *kBY) k_rk_stage(const RkArgs a)
+template <typename S, typename R, bool WALL>
+__device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb, int x, int y, int z)
 {
-    const int x = blockIdx.x * kBX + threadIdx.x;
-    const int y = blockIdx.y * kBY + threadIdx.y;
-    const int z = blockIdx.z;
-    if (x >= a.geo.nx || y >= a.geo.ny) return;
-    const Nbr nb(a.geo, x, y, z);
     const S *th = static_cast<const S *>(a.theta_in);
     const S *pp = static_cast<const S *>(a.phi);
-    const R tc = ld<R>(th + nb.c);
+    const R tc = ld<R>(elem(th, nb.c));
     R gt[3] = {R(0), R(0), R(0)}, gp[3] = {R(0), R(0), R(0)}, lap = R(0);
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
         const R w = R(weight<27>(i));
-        const int64_t at = nb.at(ex, ey, ez);
-        R tv = ld<R>(th + at);
-        if (nb.ghost(ey)) {
+        const uint32_t at = nb.at(ex, ey, ez);
+        R tv = ld<R>(elem(th, at));
+        if (WALL && nb.ghost(ey)) {
             const double *tw = ey < 0 ? a.twb : a.twt;
             tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;
         }
-        const R pv = ld<R>(pp + at);
+        const R pv = ld<R>(elem(pp, at));
         gt[0] += R(ex) * w * tv;
         gt[1] += R(ey) * w * tv;
         gt[2] += R(ez) * w * tv;
@@ -114,32 +120,43 @@ __global__ void __launch_bounds__(kBX *kBY) k_rk_stage(const RkArgs a)
     for (int k = 0; k < 3; ++k) {
         gt[k] *= R(3);
         gp[k] *= R(3);
-        u[k] = ld<R>(static_cast<const S *>(a.u[k]) + nb.c);
+        u[k] = ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
     }
     lap *= R(6);
-    const R phic = fmin(fmax(ld<R>(pp + nb.c), R(0)), R(1));
+    const R phic = fmin(fmax(ld<R>(elem(pp, nb.c)), R(0)), R(1));
     const R kap = R(a.kappa_l) + phic * R(a.dkappa);
     const R k = -(u[0] * gt[0] + u[1] * gt[1] + u[2] * gt[2]) +
                 R(a.dkappa) * (gp[0] * gt[0] + gp[1] * gt[1] + gp[2] * gt[2]) + kap * lap +
                 heat_source<R>(a.src, x, y, z);
     S *Tp = static_cast<S *>(a.T);
     S *ap = static_cast<S *>(a.acc);
-    const R T = ld<R>(Tp + nb.c);
-    const R acc = (a.first ? R(0) : ld<R>(ap + nb.c)) + R(a.w_acc) * k;
+    const R T = ld<R>(elem(Tp, nb.c));
+    const R acc = (a.first ? R(0) : ld<R>(elem(ap, nb.c))) + R(a.w_acc) * k;
     if (a.last) {
-        st(Tp + nb.c, T + acc);
+        st(elem(Tp, nb.c), T + acc);
     } else {
-        if (ap) st(ap + nb.c, acc);
-        st(static_cast<S *>(a.theta_out) + nb.c, T + R(a.a_next) * k);
+        if (ap) st(elem(ap, nb.c), acc);
+        st(elem(static_cast<S *>(a.theta_out), nb.c), T + R(a.a_next) * k);
     }
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_rk_stage(const RkArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    if (nb.below || nb.above)
+        rk_cell<S, R, true>(a, nb, x, y, z);
+    else
+        rk_cell<S, R, false>(a, nb, x, y, z);
 }
 
 template <typename S, typename R>
 void launch_rk(const RkArgs &a, hipStream_t s)
 {
-    dim3 block(kBX, kBY, 1);
-    dim3 grid((a.geo.nx + kBX - 1) / kBX, (a.geo.ny + kBY - 1) / kBY, a.geo.nz);
-    hipLaunchKernelGGL((k_rk_stage<S, R>), grid, block, 0, s, a);
+    const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_rk_stage<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
 #define TCP_THERMAL_INST(Q)                                                                                  \

