@@ -5,7 +5,8 @@ One step = phase-field LB (D3Q15) + hydrodynamic LB (D3Q27, all forces) +
 thermal LB (D3Q7) over the whole grid.  Default workload: the single-GPU
 droplet block, 512^3 periodic cells, 64 droplets (radii uniform in [10, 24],
 density ratio 100) in a smooth random temperature field, shifted-FP32
-storage; the same block in FP64 is timed after it.  Inputs are resident in
+storage; the same block in FP64, and with FP16 phase-field and thermal
+PDFs, is timed after it.  Inputs are resident in
 HBM before the timed region; the timed region is `steps` calls of the whole
 step bracketed by device synchronisations.
 
@@ -135,17 +136,13 @@ def cpu_baseline(cfg: dict, box: int, steps: int) -> dict:
                       f"{steps} steps, FP64, {el:.1f} s"}
 
 
-def copy_calibration(gib: float = 4.0, reps: int = 5) -> None:
-    """A plain device copy of known size, for scaling the HBM byte counters."""
-    import torch
-    n = int(gib * (1 << 30)) // 4
-    a = torch.empty(n, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    a.fill_(1.0)
-    for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    _log(f"copy calibration: {reps} copies of {n * 4} bytes")
+def copy_calibration(gib: float = 4.0, reps: int = 3) -> None:
+    """The library's streaming copy kernel on a buffer of known size, for
+    scaling the HBM byte counters: every dispatch reads and writes `gib` GiB."""
+    from paper_2401_03041_amd import tcplb
+    nbytes = int(gib * (1 << 30))
+    gbs = tcplb.bandwidth_probe(nbytes, reps)
+    _log(f"copy calibration: {reps + 1} dispatches, each reading and writing {nbytes} bytes; best {gbs:.0f} GB/s")
 
 
 def main() -> int:
@@ -155,6 +152,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=512, help="edge of the cubic droplet block")
     ap.add_argument("--fp64-steps", type=int, default=None, help="timed FP64 steps (default: steps/2; 0 skips)")
+    ap.add_argument("--fp16-steps", type=int, default=None,
+                    help="timed steps with FP16 phase-field/thermal PDFs (default: steps/2; 0 skips)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-box", type=int, default=64)
     ap.add_argument("--oracle-steps", type=int, default=8)
@@ -176,6 +175,8 @@ def main() -> int:
     fp32 = run_gpu(cfg, args.steps, args.warmup, "fp32")
     fp64_steps = args.steps // 2 if args.fp64_steps is None else args.fp64_steps
     fp64 = run_gpu(cfg, fp64_steps, max(2, args.warmup // 4), "fp64") if fp64_steps > 0 else None
+    fp16_steps = args.steps // 2 if args.fp16_steps is None else args.fp16_steps
+    fp16 = run_gpu(cfg, fp16_steps, max(2, args.warmup // 4), "fp16") if fp16_steps > 0 else None
     base = None if args.no_cpu_baseline else cpu_baseline(cfg, args.oracle_box, args.oracle_steps)
 
     line = {
@@ -207,6 +208,14 @@ def main() -> int:
                         "ms_per_step": round(fp64["ms_per_step"], 4), "dtype": "f64",
                         "roofline": roofline(fp64, "fp64"), "effective_GBs": round(fp64["effective_GBs"], 1),
                         "step_bytes_per_cell": fp64["step_bytes_per_cell"]}
+    if fp16 is not None:
+        line["fp16"] = {"value": round(fp16["mlups"], 2), "unit": "MLUPS", "steps": fp16_steps,
+                        "ms_per_step": round(fp16["ms_per_step"], 4),
+                        "dtype": "f32 arithmetic; f16 phase-field and thermal PDFs, f32 hydrodynamic PDFs",
+                        "effective_GBs": round(fp16["effective_GBs"], 1),
+                        "step_bytes_per_cell": fp16["step_bytes_per_cell"],
+                        "kernels": {k: {kk: round(vv, 5) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                                    for k, v in fp16["kernels"].items()}}
     print(json.dumps(line), flush=True)
     return 0
 

@@ -60,7 +60,14 @@ enum {
 enum { TCP_PDF_H = 0, TCP_PDF_G = 1, TCP_PDF_F = 2 };
 
 enum { TCP_THERMAL_LB = 0, TCP_THERMAL_RK2 = 1, TCP_THERMAL_RK4 = 2 };
-enum { TCP_FP64 = 0, TCP_FP32 = 1 };
+/* Storage and arithmetic precision (tcp_params.precision):
+ *  TCP_FP64  all PDFs and fields FP64, FP64 arithmetic;
+ *  TCP_FP32  all PDFs and fields FP32, FP32 arithmetic;
+ *  TCP_FP16  phase-field and thermal PDFs FP16 (stored shifted, see h_shift
+ *            and t_shift), hydrodynamic PDFs and all fields FP32, FP32
+ *            arithmetic.
+ * Reductions and read-back are FP64 in every mode. */
+enum { TCP_FP64 = 0, TCP_FP32 = 1, TCP_FP16 = 2 };
 
 /* Kernel kinds reported by tcp_kernel_times */
 enum { TCP_K_PHASE = 0, TCP_K_HYDRO = 1, TCP_K_THERMAL = 2, TCP_K_RK = 3, TCP_K_COUNT = 4 };
@@ -94,8 +101,7 @@ typedef struct {
     int32_t q_pf;           /* phase-field stencil: 15 or 27 */
     int32_t q_thermal;      /* thermal LB stencil: 7, 15, 19 or 27 */
     int32_t thermal;        /* TCP_THERMAL_LB, _RK2 or _RK4 */
-    int32_t precision;      /* TCP_FP64: FP64 storage and arithmetic;
-                               TCP_FP32: FP32 storage and arithmetic */
+    int32_t precision;      /* TCP_FP64, TCP_FP32 or TCP_FP16 (see above) */
     double rho_h, rho_l;    /* densities of the heavy (phi = 1) and light phase */
     double nu_h, nu_l;      /* kinematic viscosities (lattice units) */
     double mobility;        /* interface mobility M */
@@ -112,11 +118,12 @@ typedef struct {
     double t_wall_bot;      /* uniform wall temperatures; tcp_set_wall_temperature */
     double t_wall_top;      /*   overrides them with per-column values */
     double t_shift;         /* thermal PDFs are stored as f_i - w_i t_shift */
+    double h_shift;         /* phase-field PDFs are stored as h_i - w_i h_shift */
 } tcp_params;
 
 /* Fill *p with defaults: 32^3 periodic, D3Q15 phase field, D3Q7 thermal LB,
  * FP64, unit densities, nu = 1/6, M = 0.05, xi = 5, no surface tension,
- * kappa = 0.2, omega_bulk = 1, normal_eps = 1e-6. */
+ * kappa = 0.2, omega_bulk = 1, normal_eps = 1e-6, no storage shifts. */
 int tcp_params_default(tcp_params *p);
 
 /* Validate *p and allocate a domain.  Rejects (TCP_ERR_ARG) any relaxation

@@ -17,6 +17,7 @@ struct PfArgs {
     double omega_phi;    // 1 / (1/2 + M / c_s^2)
     double inv_xi;
     double eps2;         // normal_eps^2
+    double h_shift;      // h is stored as h_i - w_i h_shift
 };
 
 // K2: velocity-based D3Q27 central-moment hydrodynamics with forces (Sec. 2.1-2.2)
@@ -71,11 +72,13 @@ struct RkArgs {
     HeatSources src;
 };
 
-template <int Q, typename S, typename R>
+// Template parameters: P storage type of the phase-field / thermal PDFs, S
+// storage type of the hydrodynamic PDFs and of every field, R arithmetic type.
+template <int Q, typename P, typename S, typename R>
 void launch_pf(const PfArgs &a, hipStream_t s);
 template <typename S, typename R>
 void launch_hydro(const HydroArgs &a, hipStream_t s);
-template <int Q, typename S, typename R>
+template <int Q, typename P, typename S, typename R>
 void launch_thermal(const ThermalArgs &a, hipStream_t s);
 template <typename S, typename R>
 void launch_rk(const RkArgs &a, hipStream_t s);
@@ -100,9 +103,9 @@ struct InitArgs {
     const void *T;
     void *h, *g, *f;
     void *phi_other;
-    double t_shift;
+    double t_shift, h_shift;
 };
-template <typename S>
+template <typename S, typename P>
 void launch_init(const InitArgs &a, hipStream_t s);
 
 // which: 0 phi, 1..3 u, 4 T, 5 p, 6 p*, 7 rho
@@ -116,9 +119,9 @@ struct ReadArgs {
 };
 template <typename S>
 void launch_read(const ReadArgs &a, hipStream_t s);
-template <typename S>
-void launch_read_pdfs(const void *src, int q, int64_t N, double t_shift, int is_thermal, double *out,
-                      hipStream_t s);
+// PDFs of storage type P, stored as f_i - w_i shift, to unshifted FP64
+template <typename P>
+void launch_read_pdfs(const void *src, int q, int64_t N, double shift, double *out, hipStream_t s);
 
 // FP64 sums of phi, phi x, phi y, phi z in fixed order: partial sums per
 // work-group, then one work-group adds them up.

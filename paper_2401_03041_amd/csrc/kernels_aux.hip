@@ -48,19 +48,20 @@ __global__ void __launch_bounds__(kThreads) k_from_f64(const double *src, S *dst
     if (c < n) dst[c] = static_cast<S>(src[c]);
 }
 
-// equilibria with runtime stencil choice (set-up only)
-template <int Q, typename S>
-__device__ void store_scalar_eq(S *dst, int64_t N, int64_t c, double psi, double shift, const double u[3])
+// equilibria with runtime stencil choice (set-up only), stored shifted in type P
+template <int Q, typename P>
+__device__ void store_scalar_eq(P *dst, int64_t N, int64_t c, double psi, double shift, const double u[3])
 {
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int i = 0; i < Q; ++i) {
         const double eu = vel<Q>(i, 0) * u[0] + vel<Q>(i, 1) * u[1] + vel<Q>(i, 2) * u[2];
         const double w = weight<Q>(i);
-        dst[i * N + c] = static_cast<S>(psi * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) - w * shift);
+        dst[i * N + c] = static_cast<P>(psi * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) - w * shift);
     }
 }
 
-template <typename S>
+// S: hydrodynamic PDFs and fields; P: phase-field and thermal PDFs
+template <typename S, typename P>
 __global__ void __launch_bounds__(kThreads) k_init(const InitArgs a)
 {
     const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
@@ -70,9 +71,10 @@ __global__ void __launch_bounds__(kThreads) k_init(const InitArgs a)
     const double T = static_cast<double>(static_cast<const S *>(a.T)[c]);
     double u[3];
     for (int k = 0; k < 3; ++k) u[k] = static_cast<double>(static_cast<const S *>(a.u[k])[c]);
-    S *h = static_cast<S *>(a.h), *g = static_cast<S *>(a.g), *f = static_cast<S *>(a.f);
-    if (a.q_pf == 15) store_scalar_eq<15>(h, N, c, phi, 0.0, u);
-    else store_scalar_eq<27>(h, N, c, phi, 0.0, u);
+    P *h = static_cast<P *>(a.h), *f = static_cast<P *>(a.f);
+    S *g = static_cast<S *>(a.g);
+    if (a.q_pf == 15) store_scalar_eq<15>(h, N, c, phi, a.h_shift, u);
+    else store_scalar_eq<27>(h, N, c, phi, a.h_shift, u);
     // incompressible g_eq with p* = 0
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int i = 0; i < 27; ++i) {
@@ -112,8 +114,8 @@ __global__ void __launch_bounds__(kThreads) k_read(const ReadArgs a)
     a.out[c] = v;
 }
 
-template <int Q, typename S>
-__global__ void __launch_bounds__(kThreads) k_read_pdfs(const S *src, int64_t N, double shift, double *out)
+template <int Q, typename P>
+__global__ void __launch_bounds__(kThreads) k_read_pdfs(const P *src, int64_t N, double shift, double *out)
 {
     const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (c >= N) return;
@@ -185,10 +187,10 @@ void launch_from_f64(const double *src, void *dst, int64_t n, hipStream_t s)
     hipLaunchKernelGGL((k_from_f64<S>), dim3(blocks_for(n)), dim3(kThreads), 0, s, src, static_cast<S *>(dst), n);
 }
 
-template <typename S>
+template <typename S, typename P>
 void launch_init(const InitArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_init<S>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((k_init<S, P>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a);
 }
 
 template <typename S>
@@ -197,17 +199,16 @@ void launch_read(const ReadArgs &a, hipStream_t s)
     hipLaunchKernelGGL((k_read<S>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a);
 }
 
-template <typename S>
-void launch_read_pdfs(const void *src, int q, int64_t N, double t_shift, int is_thermal, double *out, hipStream_t s)
+template <typename P>
+void launch_read_pdfs(const void *src, int q, int64_t N, double shift, double *out, hipStream_t s)
 {
-    const S *p = static_cast<const S *>(src);
-    const double sh = is_thermal ? t_shift : 0.0;
+    const P *p = static_cast<const P *>(src);
     const dim3 gr(blocks_for(N)), bl(kThreads);
     switch (q) {
-    case 7: hipLaunchKernelGGL((k_read_pdfs<7, S>), gr, bl, 0, s, p, N, sh, out); break;
-    case 15: hipLaunchKernelGGL((k_read_pdfs<15, S>), gr, bl, 0, s, p, N, sh, out); break;
-    case 19: hipLaunchKernelGGL((k_read_pdfs<19, S>), gr, bl, 0, s, p, N, sh, out); break;
-    default: hipLaunchKernelGGL((k_read_pdfs<27, S>), gr, bl, 0, s, p, N, sh, out); break;
+    case 7: hipLaunchKernelGGL((k_read_pdfs<7, P>), gr, bl, 0, s, p, N, shift, out); break;
+    case 15: hipLaunchKernelGGL((k_read_pdfs<15, P>), gr, bl, 0, s, p, N, shift, out); break;
+    case 19: hipLaunchKernelGGL((k_read_pdfs<19, P>), gr, bl, 0, s, p, N, shift, out); break;
+    default: hipLaunchKernelGGL((k_read_pdfs<27, P>), gr, bl, 0, s, p, N, shift, out); break;
     }
 }
 
@@ -228,12 +229,14 @@ void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
 #define TCP_AUX_INST(S)                                                                                      \
     template void launch_droplets<S>(const Geometry &, const Droplets &, void *, hipStream_t);              \
     template void launch_from_f64<S>(const double *, void *, int64_t, hipStream_t);                         \
-    template void launch_init<S>(const InitArgs &, hipStream_t);                                            \
+    template void launch_init<S, S>(const InitArgs &, hipStream_t);                                         \
     template void launch_read<S>(const ReadArgs &, hipStream_t);                                            \
-    template void launch_read_pdfs<S>(const void *, int, int64_t, double, int, double *, hipStream_t);      \
+    template void launch_read_pdfs<S>(const void *, int, int64_t, double, double *, hipStream_t);           \
     template void launch_reduce<S>(const Geometry &, const void *, double *, double *, hipStream_t);
 TCP_AUX_INST(double)
 TCP_AUX_INST(float)
 #undef TCP_AUX_INST
+template void launch_init<float, _Float16>(const InitArgs &, hipStream_t);
+template void launch_read_pdfs<_Float16>(const void *, int, int64_t, double, double *, hipStream_t);
 
 } // namespace tcp

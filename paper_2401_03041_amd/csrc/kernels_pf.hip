@@ -8,15 +8,21 @@
 // Because the higher moments relax fully, the post-collision state is
 // h_eq + S/2 plus the inverse transform of the relaxed first-order moments
 // (FirstOrder<Q>), which is what the kernel evaluates.
+//
+// Storage: h_i is kept as h_i - w_i h_shift in type P (FP16 storage uses
+// h_shift = 1/2, which centres the stored range of both phases on zero).
+// Since sum_i w_i = 1 and sum_i w_i e_i = 0, the stored values sum to
+// phi - h_shift and give the first moment unchanged.
 #include "kernels.hpp"
 
 namespace tcp {
 
-template <int Q, typename S, typename R, bool WALL>
+template <int Q, typename P, typename S, typename R, bool WALL>
 __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
 {
     const int64_t N = a.geo.N;
-    const S *hs = static_cast<const S *>(a.h_src);
+    const P *hs = static_cast<const P *>(a.h_src);
+    const R hsh = R(a.h_shift);
 
     // pull; a link that crosses a wall returns the cell's own opposite PDF
     R h[Q];
@@ -29,17 +35,18 @@ __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
             h[i] = ld<R>(elem(hs + i * N, nb.at(-ex, -ey, -ez)));
     }
     // zeroth and first moments from sums and differences of opposite pairs
-    R phi = h[0], j[3] = {R(0), R(0), R(0)};
+    R php = h[0], j[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if (opposite<Q>(i) < i) continue;
         const int o = opposite<Q>(i);
         const R df = h[i] - h[o];
-        phi += h[i] + h[o];
+        php += h[i] + h[o];
         if (vel<Q>(i, 0)) j[0] += R(vel<Q>(i, 0)) * df;
         if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
         if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
     }
+    const R phi = php + hsh;
 
     // interface normal from the isotropic gradient of phi^n (mirror ghosts)
     const S *po = static_cast<const S *>(a.phi_old);
@@ -71,44 +78,48 @@ __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
     R d[Q];
     FirstOrder<Q, R>::apply(u, v, d);
 
+    // stored h_eq - w h_shift = w ((phi - h_shift)(1 + zeta) + h_shift zeta)
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    S *hd = static_cast<S *>(a.h_dst);
+    P *hd = static_cast<P *>(a.h_dst);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
         const R w = R(weight<Q>(i));
         const R eu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
         const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
-        const R heq = phi * w * (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu);
-        st(elem(hd + i * N, nb.c), heq + R(0.5) * w * eF + d[i]);
+        const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
+        st(elem(hd + i * N, nb.c), w * (php * (R(1) + zeta) + hsh * zeta + R(0.5) * eF) + d[i]);
     }
     st(elem(static_cast<S *>(a.phi_new), nb.c), phi);
 }
 
 // One thread per cell; rows next to a wall take the bounce-back path (a
 // wavefront is one x-row, so the choice is uniform across it).
-template <int Q, typename S, typename R>
+template <int Q, typename P, typename S, typename R>
 __global__ void __launch_bounds__(kTX *kTY) k_phase_field(const PfArgs a, const Tiling t)
 {
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
     const Nbr nb(a.geo, x, y, z);
     if (nb.below || nb.above)
-        phase_field_cell<Q, S, R, true>(a, nb);
+        phase_field_cell<Q, P, S, R, true>(a, nb);
     else
-        phase_field_cell<Q, S, R, false>(a, nb);
+        phase_field_cell<Q, P, S, R, false>(a, nb);
 }
 
-template <int Q, typename S, typename R>
+template <int Q, typename P, typename S, typename R>
 void launch_pf(const PfArgs &a, hipStream_t s)
 {
     const Tiling t = make_tiling(a.geo);
-    hipLaunchKernelGGL((k_phase_field<Q, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    hipLaunchKernelGGL((k_phase_field<Q, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
-template void launch_pf<15, double, double>(const PfArgs &, hipStream_t);
-template void launch_pf<27, double, double>(const PfArgs &, hipStream_t);
-template void launch_pf<15, float, float>(const PfArgs &, hipStream_t);
-template void launch_pf<27, float, float>(const PfArgs &, hipStream_t);
+#define TCP_PF_INST(Q)                                                                                       \
+    template void launch_pf<Q, double, double, double>(const PfArgs &, hipStream_t);                        \
+    template void launch_pf<Q, float, float, float>(const PfArgs &, hipStream_t);                           \
+    template void launch_pf<Q, _Float16, float, float>(const PfArgs &, hipStream_t);
+TCP_PF_INST(15)
+TCP_PF_INST(27)
+#undef TCP_PF_INST
 
 } // namespace tcp

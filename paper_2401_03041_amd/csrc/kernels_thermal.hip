@@ -4,7 +4,8 @@
 // f_i = -f*_opp + 2 w_i T_w at the y walls, T = sum_i f_i, central-moment
 // collision about u^{n+1} with the first-order moments relaxed by
 // omega_T = 1/(1/2 + kappa(phi)/c_s^2) and all higher ones with rate one, then
-// the source w_i q_T (Eq. HeatSource).  Storage is shifted: f_i - w_i t_shift.
+// the source w_i q_T (Eq. HeatSource).  Storage is shifted: f_i - w_i t_shift,
+// in type P (FP16 in the mixed mode).
 //
 // RK stages (Eq. rk2 as the midpoint rule, Eq. rk4): each stage evaluates
 //   R(theta) = -u . grad theta + (kappa_H - kappa_L) grad phi . grad theta
@@ -15,11 +16,11 @@
 
 namespace tcp {
 
-template <int Q, typename S, typename R, bool WALL>
+template <int Q, typename P, typename S, typename R, bool WALL>
 __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb, int x, int y, int z)
 {
     const int64_t N = a.geo.N;
-    const S *fs = static_cast<const S *>(a.f_src);
+    const P *fs = static_cast<const P *>(a.f_src);
     const R ts = R(a.t_shift);
 
     R f[Q];
@@ -58,7 +59,7 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
     FirstOrder<Q, R>::apply(u, v, d);
     const R q = heat_source<R>(a.src, x, y, z);
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    S *fd = static_cast<S *>(a.f_dst);
+    P *fd = static_cast<P *>(a.f_dst);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const R w = R(weight<Q>(i));
@@ -70,23 +71,23 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
 }
 
 // One thread per cell; rows next to a wall take the anti-bounce-back path.
-template <int Q, typename S, typename R>
+template <int Q, typename P, typename S, typename R>
 __global__ void __launch_bounds__(kTX *kTY) k_thermal(const ThermalArgs a, const Tiling t)
 {
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
     const Nbr nb(a.geo, x, y, z);
     if (nb.below || nb.above)
-        thermal_cell<Q, S, R, true>(a, nb, x, y, z);
+        thermal_cell<Q, P, S, R, true>(a, nb, x, y, z);
     else
-        thermal_cell<Q, S, R, false>(a, nb, x, y, z);
+        thermal_cell<Q, P, S, R, false>(a, nb, x, y, z);
 }
 
-template <int Q, typename S, typename R>
+template <int Q, typename P, typename S, typename R>
 void launch_thermal(const ThermalArgs &a, hipStream_t s)
 {
     const Tiling t = make_tiling(a.geo);
-    hipLaunchKernelGGL((k_thermal<Q, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    hipLaunchKernelGGL((k_thermal<Q, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
 template <typename S, typename R, bool WALL>
@@ -160,8 +161,9 @@ void launch_rk(const RkArgs &a, hipStream_t s)
 }
 
 #define TCP_THERMAL_INST(Q)                                                                                  \
-    template void launch_thermal<Q, double, double>(const ThermalArgs &, hipStream_t);                     \
-    template void launch_thermal<Q, float, float>(const ThermalArgs &, hipStream_t);
+    template void launch_thermal<Q, double, double, double>(const ThermalArgs &, hipStream_t);             \
+    template void launch_thermal<Q, float, float, float>(const ThermalArgs &, hipStream_t);                \
+    template void launch_thermal<Q, _Float16, float, float>(const ThermalArgs &, hipStream_t);
 TCP_THERMAL_INST(7)
 TCP_THERMAL_INST(15)
 TCP_THERMAL_INST(19)

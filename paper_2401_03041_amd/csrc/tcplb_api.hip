@@ -26,7 +26,8 @@ struct tcp_domain {
     tcp_allocator A{};
     bool own_alloc = true;
     hipStream_t stream = nullptr;
-    size_t sb = 8; // bytes per stored value
+    size_t sb = 8; // bytes per stored field value and hydrodynamic PDF
+    size_t pb = 8; // bytes per stored phase-field or thermal PDF
 
     void *h[2]{}, *g[2]{}, *f[2]{}, *phi[2]{}, *u[3]{}, *T = nullptr;
     void *rk[3]{}; // theta_a, theta_b, acc
@@ -142,7 +143,7 @@ struct KernelTimer {
 };
 
 // ---- per-step schedule ------------------------------------------------------
-template <typename S>
+template <typename S, typename Pdf>
 void phase_step(tcp_domain *d)
 {
     PfArgs a{};
@@ -155,9 +156,10 @@ void phase_step(tcp_domain *d)
     a.omega_phi = d->omega_phi;
     a.inv_xi = 1.0 / d->P.xi;
     a.eps2 = d->P.normal_eps * d->P.normal_eps;
+    a.h_shift = d->P.h_shift;
     KernelTimer t(d, TCP_K_PHASE);
-    if (d->P.q_pf == 15) launch_pf<15, S, S>(a, d->stream);
-    else launch_pf<27, S, S>(a, d->stream);
+    if (d->P.q_pf == 15) launch_pf<15, Pdf, S, S>(a, d->stream);
+    else launch_pf<27, Pdf, S, S>(a, d->stream);
 }
 
 template <typename S>
@@ -191,7 +193,7 @@ void hydro_step(tcp_domain *d)
     launch_hydro<S, S>(a, d->stream);
 }
 
-template <typename S>
+template <typename S, typename Pdf>
 void thermal_step(tcp_domain *d)
 {
     const tcp_params &P = d->P;
@@ -211,10 +213,10 @@ void thermal_step(tcp_domain *d)
         a.src = d->src;
         KernelTimer t(d, TCP_K_THERMAL);
         switch (P.q_thermal) {
-        case 7: launch_thermal<7, S, S>(a, d->stream); break;
-        case 15: launch_thermal<15, S, S>(a, d->stream); break;
-        case 19: launch_thermal<19, S, S>(a, d->stream); break;
-        default: launch_thermal<27, S, S>(a, d->stream); break;
+        case 7: launch_thermal<7, Pdf, S, S>(a, d->stream); break;
+        case 15: launch_thermal<15, Pdf, S, S>(a, d->stream); break;
+        case 19: launch_thermal<19, Pdf, S, S>(a, d->stream); break;
+        default: launch_thermal<27, Pdf, S, S>(a, d->stream); break;
         }
         return;
     }
@@ -267,12 +269,14 @@ void thermal_step(tcp_domain *d)
     }
 }
 
-template <typename S>
+// S: hydrodynamic PDFs and fields (also the arithmetic type); Pdf: phase-field
+// and thermal PDFs
+template <typename S, typename Pdf>
 void one_step(tcp_domain *d)
 {
-    phase_step<S>(d);
+    phase_step<S, Pdf>(d);
     hydro_step<S>(d);
-    thermal_step<S>(d);
+    thermal_step<S, Pdf>(d);
     d->cur = 1 - d->cur;
 }
 
@@ -296,7 +300,9 @@ int validate(const tcp_params *p, std::string &why)
         why = "q_thermal must be 7, 15, 19 or 27"; return TCP_ERR_ARG;
     }
     if (p->thermal < 0 || p->thermal > 2) { why = "thermal must be LB, RK2 or RK4"; return TCP_ERR_ARG; }
-    if (p->precision != TCP_FP64 && p->precision != TCP_FP32) { why = "precision must be FP64 or FP32"; return TCP_ERR_ARG; }
+    if (p->precision != TCP_FP64 && p->precision != TCP_FP32 && p->precision != TCP_FP16) {
+        why = "precision must be TCP_FP64, TCP_FP32 or TCP_FP16"; return TCP_ERR_ARG;
+    }
     const double vals[] = {p->rho_h, p->rho_l, p->nu_h, p->nu_l, p->mobility, p->xi, p->kappa_h, p->kappa_l, p->omega_bulk};
     const char *names[] = {"rho_h", "rho_l", "nu_h", "nu_l", "mobility", "xi", "kappa_h", "kappa_l", "omega_bulk"};
     for (int k = 0; k < 9; ++k)
@@ -307,7 +313,7 @@ int validate(const tcp_params *p, std::string &why)
         }
     const double others[] = {p->sigma_ref, p->sigma_t, p->t_ref, p->g[0], p->g[1], p->g[2], p->normal_eps,
                              p->u_wall_bot[0], p->u_wall_bot[1], p->u_wall_bot[2], p->u_wall_top[0],
-                             p->u_wall_top[1], p->u_wall_top[2], p->t_wall_bot, p->t_wall_top, p->t_shift};
+                             p->u_wall_top[1], p->u_wall_top[2], p->t_wall_bot, p->t_wall_top, p->t_shift, p->h_shift};
     for (double v : others)
         if (!std::isfinite(v)) { why = "parameters must be finite"; return TCP_ERR_ARG; }
     if (p->omega_bulk >= 2.0) { why = "omega_bulk must lie in (0, 2)"; return TCP_ERR_ARG; }
@@ -358,11 +364,11 @@ struct Piece {
 };
 std::vector<Piece> state_pieces(const tcp_domain *d)
 {
-    const size_t N = (size_t)d->geo.N, sb = d->sb;
+    const size_t N = (size_t)d->geo.N, sb = d->sb, pb = d->pb;
     std::vector<Piece> v;
-    v.push_back({d->h[d->cur], N * d->P.q_pf * sb});
+    v.push_back({d->h[d->cur], N * d->P.q_pf * pb});
     v.push_back({d->g[d->cur], N * 27 * sb});
-    if (d->P.thermal == TCP_THERMAL_LB) v.push_back({d->f[d->cur], N * d->P.q_thermal * sb});
+    if (d->P.thermal == TCP_THERMAL_LB) v.push_back({d->f[d->cur], N * d->P.q_thermal * pb});
     v.push_back({d->phi[d->cur], N * sb});
     for (int k = 0; k < 3; ++k) v.push_back({d->u[k], N * sb});
     v.push_back({d->T, N * sb});
@@ -408,6 +414,7 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
     }
     d->stream = static_cast<hipStream_t>(stream);
     d->sb = p->precision == TCP_FP64 ? 8 : 4;
+    d->pb = p->precision == TCP_FP64 ? 8 : (p->precision == TCP_FP32 ? 4 : 2);
     d->geo.nx = p->nx;
     d->geo.ny = p->ny;
     d->geo.nz = p->nz;
@@ -417,12 +424,12 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
     d->omega_phi = 1.0 / (0.5 + 3.0 * p->mobility);
     d->tau_h = 3.0 * p->nu_h;
     d->tau_l = 3.0 * p->nu_l;
-    const size_t N = (size_t)d->geo.N, sb = d->sb;
+    const size_t N = (size_t)d->geo.N, sb = d->sb, pb = d->pb;
     bool ok = true;
     for (int b = 0; b < 2; ++b) {
-        ok = ok && (d->h[b] = own(d, N * p->q_pf * sb));
+        ok = ok && (d->h[b] = own(d, N * p->q_pf * pb));
         ok = ok && (d->g[b] = own(d, N * 27 * sb));
-        if (p->thermal == TCP_THERMAL_LB) ok = ok && (d->f[b] = own(d, N * p->q_thermal * sb));
+        if (p->thermal == TCP_THERMAL_LB) ok = ok && (d->f[b] = own(d, N * p->q_thermal * pb));
         ok = ok && (d->phi[b] = own(d, N * sb));
     }
     for (int k = 0; k < 3; ++k) ok = ok && (d->u[k] = own(d, N * sb));
@@ -574,8 +581,12 @@ int tcp_initialize(tcp_domain *d)
     a.f = d->P.thermal == TCP_THERMAL_LB ? d->f[d->cur] : nullptr;
     a.phi_other = d->phi[1 - d->cur];
     a.t_shift = d->P.t_shift;
-    if (d->sb == 8) launch_init<double>(a, d->stream);
-    else launch_init<float>(a, d->stream);
+    a.h_shift = d->P.h_shift;
+    switch (d->P.precision) {
+    case TCP_FP64: launch_init<double, double>(a, d->stream); break;
+    case TCP_FP32: launch_init<float, float>(a, d->stream); break;
+    default: launch_init<float, _Float16>(a, d->stream); break;
+    }
     int rc = check_launch(d);
     if (rc == TCP_OK) d->initialized = true;
     return rc;
@@ -588,8 +599,11 @@ int tcp_step(tcp_domain *d, int64_t nsteps)
     if (!d->initialized) return fail(d, TCP_ERR_STATE, "tcp_initialize must precede tcp_step");
     return guarded(d, [&]() -> int {
         for (int64_t n = 0; n < nsteps; ++n) {
-            if (d->sb == 8) one_step<double>(d);
-            else one_step<float>(d);
+            switch (d->P.precision) {
+            case TCP_FP64: one_step<double, double>(d); break;
+            case TCP_FP32: one_step<float, float>(d); break;
+            default: one_step<float, _Float16>(d); break;
+            }
         }
         return check_launch(d);
     });
@@ -631,18 +645,20 @@ int tcp_get_pdfs(tcp_domain *d, int which, double *host_out)
     if (!d || !host_out) return TCP_ERR_ARG;
     const void *src = nullptr;
     int q = 0;
-    if (which == TCP_PDF_H) { src = d->h[d->cur]; q = d->P.q_pf; }
-    else if (which == TCP_PDF_G) { src = d->g[d->cur]; q = 27; }
-    else if (which == TCP_PDF_F && d->P.thermal == TCP_THERMAL_LB) { src = d->f[d->cur]; q = d->P.q_thermal; }
+    size_t bytes = d->pb;
+    double shift = 0.0;
+    if (which == TCP_PDF_H) { src = d->h[d->cur]; q = d->P.q_pf; shift = d->P.h_shift; }
+    else if (which == TCP_PDF_G) { src = d->g[d->cur]; q = 27; bytes = d->sb; }
+    else if (which == TCP_PDF_F && d->P.thermal == TCP_THERMAL_LB) { src = d->f[d->cur]; q = d->P.q_thermal; shift = d->P.t_shift; }
     else return fail(d, TCP_ERR_ARG, "unknown PDF field for this configuration");
     return guarded(d, [&]() -> int {
         const int64_t N = d->geo.N;
         Scratch tmp(d, (size_t)N * q * sizeof(double));
         if (!tmp.p) return fail(d, TCP_ERR_OOM, "staging allocation failed");
-        if (d->sb == 8)
-            launch_read_pdfs<double>(src, q, N, d->P.t_shift, which == TCP_PDF_F, static_cast<double *>(tmp.p), d->stream);
-        else
-            launch_read_pdfs<float>(src, q, N, d->P.t_shift, which == TCP_PDF_F, static_cast<double *>(tmp.p), d->stream);
+        double *o = static_cast<double *>(tmp.p);
+        if (bytes == 8) launch_read_pdfs<double>(src, q, N, shift, o, d->stream);
+        else if (bytes == 4) launch_read_pdfs<float>(src, q, N, shift, o, d->stream);
+        else launch_read_pdfs<_Float16>(src, q, N, shift, o, d->stream);
         int rc = check_launch(d);
         if (rc != TCP_OK) return rc;
         TCP_HIP(d, hipMemcpyAsync(host_out, tmp.p, (size_t)N * q * sizeof(double), hipMemcpyDeviceToHost, d->stream));
@@ -742,10 +758,10 @@ int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches)
 int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
 {
     if (!d || !b) return TCP_ERR_ARG;
-    const double sb = (double)d->sb;
-    b[TCP_K_PHASE] = (2.0 * d->P.q_pf + 5.0) * sb;  // h in/out, phi^n in, phi^{n+1} out, u in
-    b[TCP_K_HYDRO] = (54.0 + 5.0) * sb;              // g in/out, phi^n, T^n in, u out
-    b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? (2.0 * d->P.q_thermal + 5.0) * sb : 0.0;
+    const double sb = (double)d->sb, pb = (double)d->pb;
+    b[TCP_K_PHASE] = 2.0 * d->P.q_pf * pb + 5.0 * sb; // h in/out, phi^n in, phi^{n+1} out, u in
+    b[TCP_K_HYDRO] = (54.0 + 5.0) * sb;                // g in/out, phi^n, T^n in, u out
+    b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * pb + 5.0 * sb : 0.0;
     b[TCP_K_RK] = d->P.thermal == TCP_THERMAL_RK2 ? 13.0 * sb : (d->P.thermal == TCP_THERMAL_RK4 ? 33.0 * sb : 0.0);
     return TCP_OK;
 }

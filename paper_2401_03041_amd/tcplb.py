@@ -19,7 +19,7 @@ PHI, UX, UY, UZ, T, P, PSTAR, RHO = range(8)
 FIELDS = {"phi": PHI, "ux": UX, "uy": UY, "uz": UZ, "T": T, "p": P, "pstar": PSTAR, "rho": RHO}
 PDFS = {"h": 0, "g": 1, "f": 2}
 THERMAL = {"lb": 0, "rk2": 1, "rk4": 2}
-PRECISION = {"fp64": 0, "fp32": 1}
+PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
 KERNELS = ("phase", "hydro", "thermal", "rk")
 
 # names of every entry point the header declares
@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("g", C.c_double * 3), ("omega_bulk", C.c_double), ("normal_eps", C.c_double),
         ("u_wall_bot", C.c_double * 3), ("u_wall_top", C.c_double * 3),
         ("t_wall_bot", C.c_double), ("t_wall_top", C.c_double), ("t_shift", C.c_double),
+        ("h_shift", C.c_double),
     ]
 
 
@@ -143,7 +144,11 @@ def params_from_config(cfg: dict) -> Params:
     p.normal_eps = float(cfg.get("normal_eps", 1e-6))
     p.t_wall_bot = float(cfg.get("t_wall_bot", 0.0))
     p.t_wall_top = float(cfg.get("t_wall_top", 0.0))
-    p.t_shift = float(cfg.get("t_shift", 0.0))
+    # FP16 storage keeps the phase-field PDFs about phi = 1/2 and the thermal
+    # PDFs about the reference temperature unless the workload says otherwise
+    fp16 = cfg.get("precision", "fp64") == "fp16"
+    p.t_shift = float(cfg.get("t_shift", cfg["t_ref"] if fp16 else 0.0))
+    p.h_shift = float(cfg.get("h_shift", 0.5 if fp16 else 0.0))
     return p
 
 

@@ -53,7 +53,7 @@ def test_params_layout_matches_header():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("nx", 0), ("q_pf", 19), ("q_thermal", 9), ("thermal", 3), ("precision", 2), ("nu_l", 0.0),
+    ("nx", 0), ("q_pf", 19), ("q_thermal", 9), ("thermal", 3), ("precision", 3), ("nu_l", 0.0),
     ("mobility", -1.0), ("xi", 0.0), ("kappa_h", float("nan")), ("omega_bulk", 2.0)])
 def test_invalid_parameters_rejected_without_gpu(field, value):
     from paper_2401_03041_amd import tcplb
