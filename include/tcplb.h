@@ -189,6 +189,14 @@ int tcp_synchronize(tcp_domain *d);
 int tcp_set_profiling(tcp_domain *d, int enabled);
 int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches);
 
+/* Step graphs.  On small grids a step's few-microsecond kernels are bound by
+ * host launch cost; tcp_step then captures 16 steps into one HIP graph (on
+ * first use, once per buffer parity) and replays it.  mode 0: never;
+ * 1 (default): grids of at most 2^21 cells; 2: always.  Results are bitwise
+ * identical to eager launches.  Graphs are not used while profiling is
+ * enabled, and are rebuilt after tcp_set_heat_sources. */
+int tcp_set_graphs(tcp_domain *d, int mode);
+
 /* Bytes each kernel kind moves per cell by the algorithmic model (each PDF
  * read and written once, each scalar field read or written once). */
 int tcp_algorithmic_bytes(const tcp_domain *d, double *bytes_per_cell);

@@ -40,6 +40,12 @@ struct tcp_domain {
     double omega_phi = 1.0, tau_h = 0.5, tau_l = 0.5;
     std::string err;
 
+    // step graphs: kGraphSteps steps captured once per parity of `cur` and
+    // replayed with one launch (graph_mode: 0 never, 1 small domains, 2 always)
+    int graph_mode = 1;
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t gexec[2]{};
+
     bool prof = false;
     std::vector<TimingRecord> records;
     std::vector<hipEvent_t> pool;
@@ -280,6 +286,70 @@ void one_step(tcp_domain *d)
     d->cur = 1 - d->cur;
 }
 
+void run_steps(tcp_domain *d, int64_t nsteps)
+{
+    for (int64_t n = 0; n < nsteps; ++n) {
+        switch (d->P.precision) {
+        case TCP_FP64: one_step<double, double>(d); break;
+        case TCP_FP32: one_step<float, float>(d); break;
+        default: one_step<float, _Float16>(d); break;
+        }
+    }
+}
+
+// ---- step graphs ------------------------------------------------------------
+// A step is 3-6 kernel launches; on small grids each kernel runs for a few
+// microseconds and the host-side launch cost dominates.  kGraphSteps steps are
+// then captured into one HIP graph and replayed with a single launch.  The
+// count is even, so a replay leaves the buffer parity `cur` where it found
+// it; one graph is kept per parity.  Kernel arguments are captured by value:
+// the graphs are dropped when the heat sources change.
+constexpr int kGraphSteps = 16;
+constexpr int64_t kGraphMaxCells = (int64_t)1 << 21;
+static_assert(kGraphSteps % 2 == 0, "a replay must leave the buffer parity unchanged");
+
+void drop_graphs(tcp_domain *d)
+{
+    for (auto &g : d->gexec) {
+        if (g) (void)hipGraphExecDestroy(g);
+        g = nullptr;
+    }
+}
+
+bool use_graphs(const tcp_domain *d, int64_t nsteps)
+{
+    if (d->prof || nsteps < kGraphSteps || d->graph_mode == 0) return false;
+    return d->graph_mode == 2 || d->geo.N <= kGraphMaxCells;
+}
+
+int build_graph(tcp_domain *d)
+{
+    if (!d->cap_stream) TCP_HIP(d, hipStreamCreateWithFlags(&d->cap_stream, hipStreamNonBlocking));
+    // capture on a stream of our own (the caller's may be the legacy default
+    // stream, which cannot be captured); the replay goes to the caller's stream
+    TCP_HIP(d, hipStreamBeginCapture(d->cap_stream, hipStreamCaptureModeThreadLocal));
+    const hipStream_t user = d->stream;
+    const int cur = d->cur;
+    d->stream = d->cap_stream;
+    run_steps(d, kGraphSteps); // an even number of buffer swaps: cur is unchanged
+    d->stream = user;
+    hipGraph_t graph = nullptr;
+    const hipError_t e_launch = hipGetLastError();
+    const hipError_t e_end = hipStreamEndCapture(d->cap_stream, &graph);
+    if (e_launch != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(d, "kernel launch during graph capture", e_launch);
+    }
+    if (e_end != hipSuccess) return hip_fail(d, "hipStreamEndCapture", e_end);
+    const hipError_t e_inst = hipGraphInstantiate(&d->gexec[cur], graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e_inst != hipSuccess) {
+        d->gexec[cur] = nullptr;
+        return hip_fail(d, "hipGraphInstantiate", e_inst);
+    }
+    return TCP_OK;
+}
+
 int validate(const tcp_params *p, std::string &why)
 {
     char buf[256];
@@ -469,6 +539,8 @@ int tcp_destroy(tcp_domain *d)
 {
     if (!d) return TCP_ERR_ARG;
     (void)hipStreamSynchronize(d->stream);
+    drop_graphs(d);
+    if (d->cap_stream) (void)hipStreamDestroy(d->cap_stream);
     for (auto &r : d->records) {
         (void)hipEventDestroy(r.start);
         (void)hipEventDestroy(r.stop);
@@ -553,6 +625,7 @@ int tcp_set_heat_sources(tcp_domain *d, const tcp_heat_source *s, int n)
         hs.dcut2[k] = s[k].d_cut > 0.0 ? s[k].d_cut * s[k].d_cut : 0.0;
     }
     d->src = hs;
+    drop_graphs(d); // captured launches hold the previous sources by value
     return TCP_OK;
 }
 
@@ -598,13 +671,17 @@ int tcp_step(tcp_domain *d, int64_t nsteps)
     if (nsteps < 0) return fail(d, TCP_ERR_ARG, "nsteps must be >= 0");
     if (!d->initialized) return fail(d, TCP_ERR_STATE, "tcp_initialize must precede tcp_step");
     return guarded(d, [&]() -> int {
-        for (int64_t n = 0; n < nsteps; ++n) {
-            switch (d->P.precision) {
-            case TCP_FP64: one_step<double, double>(d); break;
-            case TCP_FP32: one_step<float, float>(d); break;
-            default: one_step<float, _Float16>(d); break;
+        int64_t left = nsteps;
+        if (use_graphs(d, nsteps)) {
+            for (; left >= kGraphSteps; left -= kGraphSteps) {
+                if (!d->gexec[d->cur]) {
+                    const int rc = build_graph(d);
+                    if (rc != TCP_OK) return rc;
+                }
+                TCP_HIP(d, hipGraphLaunch(d->gexec[d->cur], d->stream));
             }
         }
+        run_steps(d, left);
         return check_launch(d);
     });
 }
@@ -731,6 +808,14 @@ int tcp_set_profiling(tcp_domain *d, int enabled)
 {
     if (!d) return TCP_ERR_ARG;
     d->prof = enabled != 0;
+    return TCP_OK;
+}
+
+int tcp_set_graphs(tcp_domain *d, int mode)
+{
+    if (!d) return TCP_ERR_ARG;
+    if (mode < 0 || mode > 2) return fail(d, TCP_ERR_ARG, "graph mode must be 0, 1 or 2");
+    d->graph_mode = mode;
     return TCP_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTS = (
     "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_droplets",
     "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_get_field",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
-    "tcp_set_profiling", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
+    "tcp_set_profiling", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
     "tcp_last_error",
 )
 
@@ -102,6 +102,7 @@ def load() -> C.CDLL:
         "tcp_load_state": [vp, vp],
         "tcp_synchronize": [vp],
         "tcp_set_profiling": [vp, C.c_int],
+        "tcp_set_graphs": [vp, C.c_int],
         "tcp_kernel_times": [vp, dp, C.POINTER(i64)],
         "tcp_algorithmic_bytes": [vp, dp],
         "tcp_bandwidth_probe": [C.c_size_t, C.c_int, dp],
@@ -304,6 +305,10 @@ class Domain:
     # -- measurement --------------------------------------------------------------------
     def set_profiling(self, on: bool) -> None:
         self._check(self._lib.tcp_set_profiling(self._h, int(bool(on))), "set_profiling")
+
+    def set_graphs(self, mode: int) -> None:
+        """Step graphs: 0 never, 1 grids up to 2^21 cells (default), 2 always."""
+        self._check(self._lib.tcp_set_graphs(self._h, int(mode)), "set_graphs")
 
     def kernel_times(self) -> dict:
         ms = np.zeros(4)
