@@ -17,7 +17,6 @@ struct PfArgs {
     double omega_phi;    // 1 / (1/2 + M / c_s^2)
     double inv_xi;
     double eps2;         // normal_eps^2
-    double h_shift;      // h is stored as h_i - w_i h_shift
 };
 
 // K2: velocity-based D3Q27 central-moment hydrodynamics with forces (Sec. 2.1-2.2)
@@ -45,6 +44,7 @@ struct ThermalArgs {
     void *f_dst;
     const void *phi;   // phi^{n+1} (local)
     const void *u[3];  // u^{n+1} (local)
+    const void *T_old; // T^n (pull sources; FP16 storage only)
     void *T;           // T^{n+1} (output)
     const double *twb;
     const double *twt;
@@ -55,12 +55,13 @@ struct ThermalArgs {
 
 // RK stage of the energy equation (Eq. rk2, Eq. rk4):
 //   k = R(theta_in);  acc = (first ? 0 : acc) + w_acc k;
-//   last ? T += acc : theta_out = T + a_next k
+//   last ? T_new = T + acc : theta_out = T + a_next k
 struct RkArgs {
     Geometry geo;
     const void *theta_in; // stage argument (stencil)
     void *theta_out;
-    void *T;
+    const void *T;        // T^n
+    void *T_new;          // T^{n+1} (last stage)
     void *acc;
     const void *phi;      // phi^{n+1} (stencil, grad kappa)
     const void *u[3];     // u^{n+1}
@@ -74,6 +75,17 @@ struct RkArgs {
 
 // Template parameters: P storage type of the phase-field / thermal PDFs, S
 // storage type of the hydrodynamic PDFs and of every field, R arithmetic type.
+//
+// With FP16 PDFs (P = _Float16) each phase-field and thermal PDF is stored as
+// its deviation from the rest equilibrium of its own cell, h*_i - w_i phi(x)
+// and f*_i - w_i T(x), where phi and T are the cell's new zeroth moments
+// (stored as FP32 fields).  The pull adds w_i phi (w_i T) of the source cell
+// back.  In the bulk the deviation is O(|u|) or zero, so FP16 rounding adds
+// no systematic drift to phi and T.  Otherwise the thermal PDFs are stored
+// as f_i - w_i t_shift and the phase-field PDFs unshifted.
+template <typename P>
+constexpr bool deviation_storage() { return sizeof(P) == 2; }
+
 template <int Q, typename P, typename S, typename R>
 void launch_pf(const PfArgs &a, hipStream_t s);
 template <typename S, typename R>
@@ -103,7 +115,7 @@ struct InitArgs {
     const void *T;
     void *h, *g, *f;
     void *phi_other;
-    double t_shift, h_shift;
+    double t_shift;
 };
 template <typename S, typename P>
 void launch_init(const InitArgs &a, hipStream_t s);
@@ -119,9 +131,11 @@ struct ReadArgs {
 };
 template <typename S>
 void launch_read(const ReadArgs &a, hipStream_t s);
-// PDFs of storage type P, stored as f_i - w_i shift, to unshifted FP64
-template <typename P>
-void launch_read_pdfs(const void *src, int q, int64_t N, double shift, double *out, hipStream_t s);
+// PDFs of storage type P, stored as f_i - w_i (shift + field(x)) (field of
+// type F, may be null), to unshifted FP64
+template <typename P, typename F>
+void launch_read_pdfs(const void *src, int q, int64_t N, double shift, const void *field, double *out,
+                      hipStream_t s);
 
 // FP64 sums of phi, phi x, phi y, phi z in fixed order: partial sums per
 // work-group, then one work-group adds them up.

@@ -48,7 +48,8 @@ __global__ void __launch_bounds__(kThreads) k_from_f64(const double *src, S *dst
     if (c < n) dst[c] = static_cast<S>(src[c]);
 }
 
-// equilibria with runtime stencil choice (set-up only), stored shifted in type P
+// equilibria with runtime stencil choice (set-up only), stored in type P as
+// f_eq - w shift, or as the deviation f_eq - w psi (deviation_storage)
 template <int Q, typename P>
 __device__ void store_scalar_eq(P *dst, int64_t N, int64_t c, double psi, double shift, const double u[3])
 {
@@ -56,7 +57,8 @@ __device__ void store_scalar_eq(P *dst, int64_t N, int64_t c, double psi, double
     for (int i = 0; i < Q; ++i) {
         const double eu = vel<Q>(i, 0) * u[0] + vel<Q>(i, 1) * u[1] + vel<Q>(i, 2) * u[2];
         const double w = weight<Q>(i);
-        dst[i * N + c] = static_cast<P>(psi * w * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu) - w * shift);
+        const double zeta = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
+        dst[i * N + c] = static_cast<P>(deviation_storage<P>() ? psi * w * zeta : psi * w * (1.0 + zeta) - w * shift);
     }
 }
 
@@ -73,8 +75,8 @@ __global__ void __launch_bounds__(kThreads) k_init(const InitArgs a)
     for (int k = 0; k < 3; ++k) u[k] = static_cast<double>(static_cast<const S *>(a.u[k])[c]);
     P *h = static_cast<P *>(a.h), *f = static_cast<P *>(a.f);
     S *g = static_cast<S *>(a.g);
-    if (a.q_pf == 15) store_scalar_eq<15>(h, N, c, phi, a.h_shift, u);
-    else store_scalar_eq<27>(h, N, c, phi, a.h_shift, u);
+    if (a.q_pf == 15) store_scalar_eq<15>(h, N, c, phi, 0.0, u);
+    else store_scalar_eq<27>(h, N, c, phi, 0.0, u);
     // incompressible g_eq with p* = 0
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int i = 0; i < 27; ++i) {
@@ -114,12 +116,14 @@ __global__ void __launch_bounds__(kThreads) k_read(const ReadArgs a)
     a.out[c] = v;
 }
 
-template <int Q, typename P>
-__global__ void __launch_bounds__(kThreads) k_read_pdfs(const P *src, int64_t N, double shift, double *out)
+template <int Q, typename P, typename F>
+__global__ void __launch_bounds__(kThreads) k_read_pdfs(const P *src, int64_t N, double shift, const F *field,
+                                                        double *out)
 {
     const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (c >= N) return;
-    for (int i = 0; i < Q; ++i) out[i * N + c] = static_cast<double>(src[i * N + c]) + weight<Q>(i) * shift;
+    const double sh = shift + (field ? static_cast<double>(field[c]) : 0.0);
+    for (int i = 0; i < Q; ++i) out[i * N + c] = static_cast<double>(src[i * N + c]) + weight<Q>(i) * sh;
 }
 
 template <typename S>
@@ -199,16 +203,18 @@ void launch_read(const ReadArgs &a, hipStream_t s)
     hipLaunchKernelGGL((k_read<S>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a);
 }
 
-template <typename P>
-void launch_read_pdfs(const void *src, int q, int64_t N, double shift, double *out, hipStream_t s)
+template <typename P, typename F>
+void launch_read_pdfs(const void *src, int q, int64_t N, double shift, const void *field, double *out,
+                      hipStream_t s)
 {
     const P *p = static_cast<const P *>(src);
+    const F *fl = static_cast<const F *>(field);
     const dim3 gr(blocks_for(N)), bl(kThreads);
     switch (q) {
-    case 7: hipLaunchKernelGGL((k_read_pdfs<7, P>), gr, bl, 0, s, p, N, shift, out); break;
-    case 15: hipLaunchKernelGGL((k_read_pdfs<15, P>), gr, bl, 0, s, p, N, shift, out); break;
-    case 19: hipLaunchKernelGGL((k_read_pdfs<19, P>), gr, bl, 0, s, p, N, shift, out); break;
-    default: hipLaunchKernelGGL((k_read_pdfs<27, P>), gr, bl, 0, s, p, N, shift, out); break;
+    case 7: hipLaunchKernelGGL((k_read_pdfs<7, P, F>), gr, bl, 0, s, p, N, shift, fl, out); break;
+    case 15: hipLaunchKernelGGL((k_read_pdfs<15, P, F>), gr, bl, 0, s, p, N, shift, fl, out); break;
+    case 19: hipLaunchKernelGGL((k_read_pdfs<19, P, F>), gr, bl, 0, s, p, N, shift, fl, out); break;
+    default: hipLaunchKernelGGL((k_read_pdfs<27, P, F>), gr, bl, 0, s, p, N, shift, fl, out); break;
     }
 }
 
@@ -231,12 +237,13 @@ void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
     template void launch_from_f64<S>(const double *, void *, int64_t, hipStream_t);                         \
     template void launch_init<S, S>(const InitArgs &, hipStream_t);                                         \
     template void launch_read<S>(const ReadArgs &, hipStream_t);                                            \
-    template void launch_read_pdfs<S>(const void *, int, int64_t, double, double *, hipStream_t);           \
+    template void launch_read_pdfs<S, S>(const void *, int, int64_t, double, const void *, double *, hipStream_t); \
     template void launch_reduce<S>(const Geometry &, const void *, double *, double *, hipStream_t);
 TCP_AUX_INST(double)
 TCP_AUX_INST(float)
 #undef TCP_AUX_INST
 template void launch_init<float, _Float16>(const InitArgs &, hipStream_t);
-template void launch_read_pdfs<_Float16>(const void *, int, int64_t, double, double *, hipStream_t);
+template void launch_read_pdfs<_Float16, float>(const void *, int, int64_t, double, const void *, double *,
+                                                hipStream_t);
 
 } // namespace tcp

@@ -9,10 +9,10 @@
 // h_eq + S/2 plus the inverse transform of the relaxed first-order moments
 // (FirstOrder<Q>), which is what the kernel evaluates.
 //
-// Storage: h_i is kept as h_i - w_i h_shift in type P (FP16 storage uses
-// h_shift = 1/2, which centres the stored range of both phases on zero).
-// Since sum_i w_i = 1 and sum_i w_i e_i = 0, the stored values sum to
-// phi - h_shift and give the first moment unchanged.
+// Storage in type P: unshifted, or (FP16) as the deviation h*_i - w_i phi(x)
+// from the rest equilibrium of the cell (deviation_storage).  The pull then
+// adds w_i phi^n of the source cell, which the kernel loads anyway for the
+// gradient of phi^n: phi^n(y) is the zeroth moment of the h* stored at y.
 #include "kernels.hpp"
 
 namespace tcp {
@@ -20,44 +20,46 @@ namespace tcp {
 template <int Q, typename P, typename S, typename R, bool WALL>
 __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
 {
+    constexpr bool dev = deviation_storage<P>();
     const int64_t N = a.geo.N;
     const P *hs = static_cast<const P *>(a.h_src);
-    const R hsh = R(a.h_shift);
+
+    // phi^n on the 3x3x3 neighbourhood (mirror ghosts across walls)
+    const S *po = static_cast<const S *>(a.phi_old);
+    R pn[27];
+#pragma unroll
+    for (int k = dev ? 0 : 1; k < 27; ++k) pn[k] = ld<R>(elem(po, nb.at(vel27(k, 0), vel27(k, 1), vel27(k, 2))));
 
     // pull; a link that crosses a wall returns the cell's own opposite PDF
     R h[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
-        if (WALL && nb.ghost(-ey))
-            h[i] = ld<R>(elem(hs + opposite<Q>(i) * N, nb.c));
-        else
-            h[i] = ld<R>(elem(hs + i * N, nb.at(-ex, -ey, -ez)));
+        const bool wall = WALL && nb.ghost(-ey);
+        h[i] = wall ? ld<R>(elem(hs + opposite<Q>(i) * N, nb.c)) : ld<R>(elem(hs + i * N, nb.at(-ex, -ey, -ez)));
+        if constexpr (dev) h[i] += R(weight<Q>(i)) * pn[wall ? 0 : opposite<27>(index27<Q>(i))];
     }
     // zeroth and first moments from sums and differences of opposite pairs
-    R php = h[0], j[3] = {R(0), R(0), R(0)};
+    R phi = h[0], j[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
         if (opposite<Q>(i) < i) continue;
         const int o = opposite<Q>(i);
         const R df = h[i] - h[o];
-        php += h[i] + h[o];
+        phi += h[i] + h[o];
         if (vel<Q>(i, 0)) j[0] += R(vel<Q>(i, 0)) * df;
         if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
         if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
     }
-    const R phi = php + hsh;
 
-    // interface normal from the isotropic gradient of phi^n (mirror ghosts)
-    const S *po = static_cast<const S *>(a.phi_old);
+    // interface normal from the isotropic gradient of phi^n
     R gr[3] = {R(0), R(0), R(0)};
 #pragma unroll
-    for (int i = 1; i < 27; ++i) {
-        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        const R v = R(weight<27>(i)) * ld<R>(elem(po, nb.at(ex, ey, ez)));
-        gr[0] += R(ex) * v;
-        gr[1] += R(ey) * v;
-        gr[2] += R(ez) * v;
+    for (int k = 1; k < 27; ++k) {
+        const R v = R(weight<27>(k)) * pn[k];
+        gr[0] += R(vel27(k, 0)) * v;
+        gr[1] += R(vel27(k, 1)) * v;
+        gr[2] += R(vel27(k, 2)) * v;
     }
     gr[0] *= R(3);
     gr[1] *= R(3);
@@ -78,7 +80,7 @@ __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
     R d[Q];
     FirstOrder<Q, R>::apply(u, v, d);
 
-    // stored h_eq - w h_shift = w ((phi - h_shift)(1 + zeta) + h_shift zeta)
+    // h* = w (phi (1 + zeta) + e.F / 2) + d, zeta the velocity part of h_eq / (w phi)
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     P *hd = static_cast<P *>(a.h_dst);
 #pragma unroll
@@ -88,7 +90,8 @@ __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
         const R eu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
         const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
         const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
-        st(elem(hd + i * N, nb.c), w * (php * (R(1) + zeta) + hsh * zeta + R(0.5) * eF) + d[i]);
+        const R rest = dev ? phi * zeta : phi * (R(1) + zeta); // minus w phi when stored as a deviation
+        st(elem(hd + i * N, nb.c), w * (rest + R(0.5) * eF) + d[i]);
     }
     st(elem(static_cast<S *>(a.phi_new), nb.c), phi);
 }

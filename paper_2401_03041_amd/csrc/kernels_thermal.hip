@@ -4,8 +4,10 @@
 // f_i = -f*_opp + 2 w_i T_w at the y walls, T = sum_i f_i, central-moment
 // collision about u^{n+1} with the first-order moments relaxed by
 // omega_T = 1/(1/2 + kappa(phi)/c_s^2) and all higher ones with rate one, then
-// the source w_i q_T (Eq. HeatSource).  Storage is shifted: f_i - w_i t_shift,
-// in type P (FP16 in the mixed mode).
+// the source w_i q_T (Eq. HeatSource).  Storage in type P: f_i - w_i t_shift,
+// or (FP16) the deviation f*_i - w_i T(x) from the rest equilibrium of the
+// cell, the pull adding w_i T^n of the source cell back.  T is double
+// buffered (T^n read, T^{n+1} written).
 //
 // RK stages (Eq. rk2 as the midpoint rule, Eq. rk4): each stage evaluates
 //   R(theta) = -u . grad theta + (kappa_H - kappa_L) grad phi . grad theta
@@ -19,20 +21,28 @@ namespace tcp {
 template <int Q, typename P, typename S, typename R, bool WALL>
 __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb, int x, int y, int z)
 {
+    constexpr bool dev = deviation_storage<P>();
     const int64_t N = a.geo.N;
     const P *fs = static_cast<const P *>(a.f_src);
-    const R ts = R(a.t_shift);
+    const S *to = static_cast<const S *>(a.T_old);
+    // stored value = f - w ts (constant shift) or f - w T^n(source) (deviation)
+    const R ts = dev ? R(0) : R(a.t_shift);
+    const R t_own = dev ? ld<R>(elem(to, nb.c)) : R(0);
 
     R f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        const R w = R(weight<Q>(i));
         if (WALL && nb.ghost(-ey)) {
+            // anti-bounce-back f_i = 2 w T_w - f*_opp(x); f[] holds f - w ts
             const double *tw = ey > 0 ? a.twb : a.twt;
-            const R w2 = R(2.0 * weight<Q>(i));
-            f[i] = w2 * (R(tw[nb.col(0, 0, a.geo)]) - ts) - ld<R>(elem(fs + opposite<Q>(i) * N, nb.c));
+            f[i] = R(2) * w * R(tw[nb.col(0, 0, a.geo)]) - ld<R>(elem(fs + opposite<Q>(i) * N, nb.c)) -
+                   w * (dev ? t_own : R(2) * ts);
         } else {
-            f[i] = ld<R>(elem(fs + i * N, nb.at(-ex, -ey, -ez)));
+            const uint32_t src = nb.at(-ex, -ey, -ez);
+            f[i] = ld<R>(elem(fs + i * N, src));
+            if constexpr (dev) f[i] += w * (i == 0 ? t_own : ld<R>(elem(to, src)));
         }
     }
     // zeroth and first moments from sums and differences of opposite pairs
@@ -65,7 +75,9 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
         const R w = R(weight<Q>(i));
         const R eu = R(vel<Q>(i, 0)) * u[0] + R(vel<Q>(i, 1)) * u[1] + R(vel<Q>(i, 2)) * u[2];
         const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
-        st(elem(fd + i * N, nb.c), w * (Tp * (R(1) + zeta) + ts * zeta) + d[i] + w * q);
+        // f* - w ts = w (T (1 + zeta) - ts) + d + w q;  f* - w T = w T zeta + d + w q
+        const R rest = dev ? T * zeta : Tp * (R(1) + zeta) + ts * zeta;
+        st(elem(fd + i * N, nb.c), w * rest + d[i] + w * q);
     }
     st(elem(static_cast<S *>(a.T), nb.c), T);
 }
@@ -129,12 +141,11 @@ __device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb, int x, i
     const R k = -(u[0] * gt[0] + u[1] * gt[1] + u[2] * gt[2]) +
                 R(a.dkappa) * (gp[0] * gt[0] + gp[1] * gt[1] + gp[2] * gt[2]) + kap * lap +
                 heat_source<R>(a.src, x, y, z);
-    S *Tp = static_cast<S *>(a.T);
     S *ap = static_cast<S *>(a.acc);
-    const R T = ld<R>(elem(Tp, nb.c));
+    const R T = ld<R>(elem(static_cast<const S *>(a.T), nb.c));
     const R acc = (a.first ? R(0) : ld<R>(elem(ap, nb.c))) + R(a.w_acc) * k;
     if (a.last) {
-        st(elem(Tp, nb.c), T + acc);
+        st(elem(static_cast<S *>(a.T_new), nb.c), T + acc);
     } else {
         if (ap) st(elem(ap, nb.c), acc);
         st(elem(static_cast<S *>(a.theta_out), nb.c), T + R(a.a_next) * k);

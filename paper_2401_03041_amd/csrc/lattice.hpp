@@ -26,11 +26,18 @@ __host__ __device__ constexpr int vel27(int i, int a)
     return t[i][a];
 }
 
-// D3Q15 maps its corner slots 7..14 onto D3Q27 slots 19..26
+// D3Q27 slot of direction i of a Q stencil: D3Q15 maps its corner slots 7..14
+// onto D3Q27 slots 19..26, the other stencils are prefixes of D3Q27
+template <int Q>
+__host__ __device__ constexpr int index27(int i)
+{
+    return (Q == 15 && i >= 7) ? i + 12 : i;
+}
+
 template <int Q>
 __host__ __device__ constexpr int vel(int i, int a)
 {
-    return vel27((Q == 15 && i >= 7) ? i + 12 : i, a);
+    return vel27(index27<Q>(i), a);
 }
 
 template <int Q>

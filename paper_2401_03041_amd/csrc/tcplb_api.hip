@@ -29,7 +29,7 @@ struct tcp_domain {
     size_t sb = 8; // bytes per stored field value and hydrodynamic PDF
     size_t pb = 8; // bytes per stored phase-field or thermal PDF
 
-    void *h[2]{}, *g[2]{}, *f[2]{}, *phi[2]{}, *u[3]{}, *T = nullptr;
+    void *h[2]{}, *g[2]{}, *f[2]{}, *phi[2]{}, *u[3]{}, *T[2]{}; // [cur]: time level n
     void *rk[3]{}; // theta_a, theta_b, acc
     double *twb = nullptr, *twt = nullptr;
     double *partial = nullptr, *out4 = nullptr;
@@ -162,7 +162,6 @@ void phase_step(tcp_domain *d)
     a.omega_phi = d->omega_phi;
     a.inv_xi = 1.0 / d->P.xi;
     a.eps2 = d->P.normal_eps * d->P.normal_eps;
-    a.h_shift = d->P.h_shift;
     KernelTimer t(d, TCP_K_PHASE);
     if (d->P.q_pf == 15) launch_pf<15, Pdf, S, S>(a, d->stream);
     else launch_pf<27, Pdf, S, S>(a, d->stream);
@@ -177,7 +176,7 @@ void hydro_step(tcp_domain *d)
     a.g_src = d->g[d->cur];
     a.g_dst = d->g[1 - d->cur];
     a.phi = d->phi[d->cur];
-    a.T = d->T;
+    a.T = d->T[d->cur];
     a.twb = d->twb;
     a.twt = d->twt;
     for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
@@ -210,7 +209,8 @@ void thermal_step(tcp_domain *d)
         a.f_dst = d->f[1 - d->cur];
         a.phi = d->phi[1 - d->cur];
         for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
-        a.T = d->T;
+        a.T_old = d->T[d->cur];
+        a.T = d->T[1 - d->cur];
         a.twb = d->twb;
         a.twt = d->twt;
         a.kappa_l = P.kappa_l;
@@ -228,7 +228,8 @@ void thermal_step(tcp_domain *d)
     }
     RkArgs a{};
     a.geo = d->geo;
-    a.T = d->T;
+    a.T = d->T[d->cur];
+    a.T_new = d->T[1 - d->cur];
     a.phi = d->phi[1 - d->cur];
     for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
     a.twb = d->twb;
@@ -237,8 +238,8 @@ void thermal_step(tcp_domain *d)
     a.dkappa = P.kappa_h - P.kappa_l;
     a.src = d->src;
     if (P.thermal == TCP_THERMAL_RK2) {
-        // theta = T + k1/2; T += R(theta)
-        a.theta_in = d->T;
+        // theta = T + k1/2; T_new = T + R(theta)
+        a.theta_in = d->T[d->cur];
         a.theta_out = d->rk[0];
         a.acc = nullptr;
         a.first = 1;
@@ -258,7 +259,7 @@ void thermal_step(tcp_domain *d)
         return;
     }
     // RK4: K1..K4, stage arguments T + K1/2, T + K2/2, T + K3
-    const void *in[4] = {d->T, d->rk[0], d->rk[1], d->rk[0]};
+    const void *in[4] = {d->T[d->cur], d->rk[0], d->rk[1], d->rk[0]};
     void *out[4] = {d->rk[0], d->rk[1], d->rk[0], nullptr};
     const double wacc[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
     const double anext[4] = {0.5, 0.5, 1.0, 0.0};
@@ -383,7 +384,7 @@ int validate(const tcp_params *p, std::string &why)
         }
     const double others[] = {p->sigma_ref, p->sigma_t, p->t_ref, p->g[0], p->g[1], p->g[2], p->normal_eps,
                              p->u_wall_bot[0], p->u_wall_bot[1], p->u_wall_bot[2], p->u_wall_top[0],
-                             p->u_wall_top[1], p->u_wall_top[2], p->t_wall_bot, p->t_wall_top, p->t_shift, p->h_shift};
+                             p->u_wall_top[1], p->u_wall_top[2], p->t_wall_bot, p->t_wall_top, p->t_shift};
     for (double v : others)
         if (!std::isfinite(v)) { why = "parameters must be finite"; return TCP_ERR_ARG; }
     if (p->omega_bulk >= 2.0) { why = "omega_bulk must lie in (0, 2)"; return TCP_ERR_ARG; }
@@ -441,7 +442,7 @@ std::vector<Piece> state_pieces(const tcp_domain *d)
     if (d->P.thermal == TCP_THERMAL_LB) v.push_back({d->f[d->cur], N * d->P.q_thermal * pb});
     v.push_back({d->phi[d->cur], N * sb});
     for (int k = 0; k < 3; ++k) v.push_back({d->u[k], N * sb});
-    v.push_back({d->T, N * sb});
+    v.push_back({d->T[d->cur], N * sb});
     return v;
 }
 } // namespace
@@ -501,9 +502,9 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
         ok = ok && (d->g[b] = own(d, N * 27 * sb));
         if (p->thermal == TCP_THERMAL_LB) ok = ok && (d->f[b] = own(d, N * p->q_thermal * pb));
         ok = ok && (d->phi[b] = own(d, N * sb));
+        ok = ok && (d->T[b] = own(d, N * sb));
     }
     for (int k = 0; k < 3; ++k) ok = ok && (d->u[k] = own(d, N * sb));
-    ok = ok && (d->T = own(d, N * sb));
     if (p->thermal != TCP_THERMAL_LB)
         for (int k = 0; k < (p->thermal == TCP_THERMAL_RK2 ? 1 : 3); ++k) ok = ok && (d->rk[k] = own(d, N * sb));
     const size_t ncol = (size_t)p->nx * p->nz;
@@ -523,7 +524,7 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
     }
     // zero the fields so that an uninitialised read is well defined
     for (int k = 0; k < 3 && e == hipSuccess; ++k) e = hipMemsetAsync(d->u[k], 0, N * sb, d->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(d->T, 0, N * sb, d->stream);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemsetAsync(d->T[b], 0, N * sb, d->stream);
     for (int b = 0; b < 2 && e == hipSuccess; ++b) e = hipMemsetAsync(d->phi[b], 0, N * sb, d->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(d->stream);
     if (e != hipSuccess) {
@@ -559,7 +560,7 @@ int tcp_set_field(tcp_domain *d, int which, const double *host, const void *dev)
     switch (which) {
     case TCP_PHI: dst = d->phi[d->cur]; break;
     case TCP_UX: case TCP_UY: case TCP_UZ: dst = d->u[which - TCP_UX]; break;
-    case TCP_T: dst = d->T; break;
+    case TCP_T: dst = d->T[d->cur]; break;
     default: return fail(d, TCP_ERR_ARG, "field cannot be set");
     }
     return guarded(d, [&]() -> int {
@@ -648,13 +649,12 @@ int tcp_initialize(tcp_domain *d)
     a.q_th = d->P.q_thermal;
     a.phi = d->phi[d->cur];
     for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
-    a.T = d->T;
+    a.T = d->T[d->cur];
     a.h = d->h[d->cur];
     a.g = d->g[d->cur];
     a.f = d->P.thermal == TCP_THERMAL_LB ? d->f[d->cur] : nullptr;
     a.phi_other = d->phi[1 - d->cur];
     a.t_shift = d->P.t_shift;
-    a.h_shift = d->P.h_shift;
     switch (d->P.precision) {
     case TCP_FP64: launch_init<double, double>(a, d->stream); break;
     case TCP_FP32: launch_init<float, float>(a, d->stream); break;
@@ -699,7 +699,7 @@ int tcp_get_field(tcp_domain *d, int which, double *host, void *dev)
         a.geo = d->geo;
         a.which = which; // TCP_PHI..TCP_RHO use the read-kernel codes 0..7
         a.phi = d->phi[d->cur];
-        a.T = d->T;
+        a.T = d->T[d->cur];
         a.g = d->g[d->cur];
         for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
         a.rho_l = d->P.rho_l;
@@ -724,18 +724,31 @@ int tcp_get_pdfs(tcp_domain *d, int which, double *host_out)
     int q = 0;
     size_t bytes = d->pb;
     double shift = 0.0;
-    if (which == TCP_PDF_H) { src = d->h[d->cur]; q = d->P.q_pf; shift = d->P.h_shift; }
-    else if (which == TCP_PDF_G) { src = d->g[d->cur]; q = 27; bytes = d->sb; }
-    else if (which == TCP_PDF_F && d->P.thermal == TCP_THERMAL_LB) { src = d->f[d->cur]; q = d->P.q_thermal; shift = d->P.t_shift; }
-    else return fail(d, TCP_ERR_ARG, "unknown PDF field for this configuration");
+    const void *field = nullptr; // FP16 PDFs are stored relative to w_i phi(x) or w_i T(x)
+    if (which == TCP_PDF_H) {
+        src = d->h[d->cur];
+        q = d->P.q_pf;
+        if (d->pb == 2) field = d->phi[d->cur];
+    } else if (which == TCP_PDF_G) {
+        src = d->g[d->cur];
+        q = 27;
+        bytes = d->sb;
+    } else if (which == TCP_PDF_F && d->P.thermal == TCP_THERMAL_LB) {
+        src = d->f[d->cur];
+        q = d->P.q_thermal;
+        if (d->pb == 2) field = d->T[d->cur];
+        else shift = d->P.t_shift;
+    } else {
+        return fail(d, TCP_ERR_ARG, "unknown PDF field for this configuration");
+    }
     return guarded(d, [&]() -> int {
         const int64_t N = d->geo.N;
         Scratch tmp(d, (size_t)N * q * sizeof(double));
         if (!tmp.p) return fail(d, TCP_ERR_OOM, "staging allocation failed");
         double *o = static_cast<double *>(tmp.p);
-        if (bytes == 8) launch_read_pdfs<double>(src, q, N, shift, o, d->stream);
-        else if (bytes == 4) launch_read_pdfs<float>(src, q, N, shift, o, d->stream);
-        else launch_read_pdfs<_Float16>(src, q, N, shift, o, d->stream);
+        if (bytes == 8) launch_read_pdfs<double, double>(src, q, N, shift, field, o, d->stream);
+        else if (bytes == 4) launch_read_pdfs<float, float>(src, q, N, shift, field, o, d->stream);
+        else launch_read_pdfs<_Float16, float>(src, q, N, shift, field, o, d->stream);
         int rc = check_launch(d);
         if (rc != TCP_OK) return rc;
         TCP_HIP(d, hipMemcpyAsync(host_out, tmp.p, (size_t)N * q * sizeof(double), hipMemcpyDeviceToHost, d->stream));
@@ -846,7 +859,8 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     const double sb = (double)d->sb, pb = (double)d->pb;
     b[TCP_K_PHASE] = 2.0 * d->P.q_pf * pb + 5.0 * sb; // h in/out, phi^n in, phi^{n+1} out, u in
     b[TCP_K_HYDRO] = (54.0 + 5.0) * sb;                // g in/out, phi^n, T^n in, u out
-    b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * pb + 5.0 * sb : 0.0;
+    // f in/out, u and phi^{n+1} in, T out; FP16 deviation storage also reads T^n
+    b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * pb + (d->pb == 2 ? 6.0 : 5.0) * sb : 0.0;
     b[TCP_K_RK] = d->P.thermal == TCP_THERMAL_RK2 ? 13.0 * sb : (d->P.thermal == TCP_THERMAL_RK4 ? 33.0 * sb : 0.0);
     return TCP_OK;
 }

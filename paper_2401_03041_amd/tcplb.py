@@ -42,7 +42,6 @@ class Params(C.Structure):
         ("g", C.c_double * 3), ("omega_bulk", C.c_double), ("normal_eps", C.c_double),
         ("u_wall_bot", C.c_double * 3), ("u_wall_top", C.c_double * 3),
         ("t_wall_bot", C.c_double), ("t_wall_top", C.c_double), ("t_shift", C.c_double),
-        ("h_shift", C.c_double),
     ]
 
 
@@ -145,11 +144,7 @@ def params_from_config(cfg: dict) -> Params:
     p.normal_eps = float(cfg.get("normal_eps", 1e-6))
     p.t_wall_bot = float(cfg.get("t_wall_bot", 0.0))
     p.t_wall_top = float(cfg.get("t_wall_top", 0.0))
-    # FP16 storage keeps the phase-field PDFs about phi = 1/2 and the thermal
-    # PDFs about the reference temperature unless the workload says otherwise
-    fp16 = cfg.get("precision", "fp64") == "fp16"
-    p.t_shift = float(cfg.get("t_shift", cfg["t_ref"] if fp16 else 0.0))
-    p.h_shift = float(cfg.get("h_shift", 0.5 if fp16 else 0.0))
+    p.t_shift = float(cfg.get("t_shift", 0.0))
     return p
 
 

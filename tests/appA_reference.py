@@ -33,9 +33,15 @@ def planar_channel(x, y, a, b, omega, T_h, T_c, T_0, sigma_t, mu_h, k_r=1.0, mu_
     wy = omega * y
     u = umax * ((C1 + omega * (C2 + C3 * y)) * np.cosh(wy) + (C3 + omega * C1 * y) * np.sinh(wy)) * np.sin(omega * x)
     v = -omega * umax * (C1 * y * np.cosh(wy) + (C2 + C3 * y) * np.sinh(wy)) * np.cos(omega * x)
-    lin = ((T_c - T_h) * y + k_r * T_c * b + T_h * a) / (a + k_r * b)
-    Tb = lin + T_0 * f * np.sinh(ar - wy) * np.cos(omega * x)
-    Ta = lin + T_0 * f * (np.sinh(ar) * np.cosh(wy) - k_r * np.sinh(wy) * np.cosh(ar)) * np.cos(omega * x)
+    # Conduction part (Ma -> 0), k_r = k_a / k_b.  Solving the Laplace equation in
+    # each layer with the wall values and continuity of T and k dT/dy at y = 0
+    # gives the appendix's two cosine terms with the layers exchanged (the k_r
+    # term belongs to the lower layer) and a lower-layer linear slope k_r times
+    # the upper one; for k_r = 1 both coincide with the printed form.
+    lin_a = ((T_c - T_h) * y + k_r * T_c * b + T_h * a) / (a + k_r * b)
+    lin_b = (k_r * (T_c - T_h) * y + k_r * T_c * b + T_h * a) / (a + k_r * b)
+    Ta = lin_a + T_0 * f * np.sinh(ar - wy) * np.cos(omega * x)
+    Tb = lin_b + T_0 * f * (np.sinh(ar) * np.cosh(wy) - k_r * np.sinh(wy) * np.cosh(ar)) * np.cos(omega * x)
     T = np.where(upper, Ta, Tb)
     return u, v, T
 

@@ -270,6 +270,30 @@ def test_laplace_pressure_jump_cylinder(rho_l):
 # ---------------------------------------------------------------------------------------
 # Thermocapillary stress (Sec. 2.1 Marangoni term of F_s): the paper's own verification
 # ---------------------------------------------------------------------------------------
+@pytest.mark.parametrize("k_r", [1.0, 0.2, 3.0])
+def test_appendix_a_temperature_solves_the_conduction_problem(k_r):
+    """The App. A reference temperature is harmonic in each layer, takes the wall
+    values, and is continuous with continuous heat flux k dT/dy across y = 0."""
+    from tests.appA_reference import planar_channel
+    a = b = 12.0
+    omega = 2 * np.pi / 24.0
+    x = np.linspace(0.0, 48.0, 11)
+
+    def T(xx, yy):
+        return planar_channel(xx, yy, a, b, omega, 20.0, 10.0, 4.0, -5e-4, 0.2, k_r=k_r)[2]
+    assert np.allclose(T(x, a), 10.0, atol=1e-12)
+    assert np.allclose(T(x, -b), 20.0 + 4.0 * np.cos(omega * x), atol=1e-12)
+    e = 1e-6
+    assert np.allclose(T(x, e), T(x, -e), atol=1e-8)
+    grad_a = (T(x, 2 * e) - T(x, e)) / e
+    grad_b = (T(x, -e) - T(x, -2 * e)) / e
+    assert np.allclose(k_r * grad_a, grad_b, atol=1e-5)
+    h = 1e-3
+    for y in (5.0, -5.0):
+        lap = (T(x + h, y) + T(x - h, y) + T(x, y + h) + T(x, y - h) - 4 * T(x, y)) / h ** 2
+        assert np.max(np.abs(lap)) < 1e-4
+
+
 def test_planar_heated_channel_matches_appendix_a():
     """Two layers between walls, lower wall at T_h + T_0 cos(omega x), upper at T_c
     (Sec. 3.1 set-up with the App. A closed form), at 1/8 of the paper's size.  The
