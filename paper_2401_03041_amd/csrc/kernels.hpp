@@ -131,10 +131,10 @@ struct ReadArgs {
 };
 template <typename S>
 void launch_read(const ReadArgs &a, hipStream_t s);
-// PDFs of storage type P, stored as f_i - w_i (shift + field(x)) (field of
-// type F, may be null), to unshifted FP64
+// PDFs of storage type P (blocked layout), stored as f_i - w_i (shift + field(x))
+// (field of type F, may be null), to unshifted component-major FP64
 template <typename P, typename F>
-void launch_read_pdfs(const void *src, int q, int64_t N, double shift, const void *field, double *out,
+void launch_read_pdfs(const void *src, int q, const Geometry &g, double shift, const void *field, double *out,
                       hipStream_t s);
 
 // FP64 sums of phi, phi x, phi y, phi z in fixed order: partial sums per

@@ -51,14 +51,16 @@ __global__ void __launch_bounds__(kThreads) k_from_f64(const double *src, S *dst
 // equilibria with runtime stencil choice (set-up only), stored in type P as
 // f_eq - w shift, or as the deviation f_eq - w psi (deviation_storage)
 template <int Q, typename P>
-__device__ void store_scalar_eq(P *dst, int64_t N, int64_t c, double psi, double shift, const double u[3])
+__device__ void store_scalar_eq(P *dst, const Geometry &g, int x, int y, int z, double psi, double shift,
+                                const double u[3])
 {
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int i = 0; i < Q; ++i) {
         const double eu = vel<Q>(i, 0) * u[0] + vel<Q>(i, 1) * u[1] + vel<Q>(i, 2) * u[2];
         const double w = weight<Q>(i);
         const double zeta = 3.0 * eu + 4.5 * eu * eu - 1.5 * uu;
-        dst[i * N + c] = static_cast<P>(deviation_storage<P>() ? psi * w * zeta : psi * w * (1.0 + zeta) - w * shift);
+        dst[pdf_index<Q>(g, x, y, z, i)] =
+            static_cast<P>(deviation_storage<P>() ? psi * w * zeta : psi * w * (1.0 + zeta) - w * shift);
     }
 }
 
@@ -67,28 +69,29 @@ template <typename S, typename P>
 __global__ void __launch_bounds__(kThreads) k_init(const InitArgs a)
 {
     const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t N = a.geo.N;
-    if (c >= N) return;
+    const Geometry &G = a.geo;
+    if (c >= G.N) return;
+    const int x = (int)(c % G.nx), y = (int)((c / G.nx) % G.ny), z = (int)(c / G.plane);
     const double phi = static_cast<double>(static_cast<const S *>(a.phi)[c]);
     const double T = static_cast<double>(static_cast<const S *>(a.T)[c]);
     double u[3];
     for (int k = 0; k < 3; ++k) u[k] = static_cast<double>(static_cast<const S *>(a.u[k])[c]);
     P *h = static_cast<P *>(a.h), *f = static_cast<P *>(a.f);
     S *g = static_cast<S *>(a.g);
-    if (a.q_pf == 15) store_scalar_eq<15>(h, N, c, phi, 0.0, u);
-    else store_scalar_eq<27>(h, N, c, phi, 0.0, u);
+    if (a.q_pf == 15) store_scalar_eq<15>(h, G, x, y, z, phi, 0.0, u);
+    else store_scalar_eq<27>(h, G, x, y, z, phi, 0.0, u);
     // incompressible g_eq with p* = 0
     const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
     for (int i = 0; i < 27; ++i) {
         const double eu = vel27(i, 0) * u[0] + vel27(i, 1) * u[1] + vel27(i, 2) * u[2];
-        g[i * N + c] = static_cast<S>(weight<27>(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
+        g[pdf_index<27>(G, x, y, z, i)] = static_cast<S>(weight<27>(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
     }
     if (f) {
         switch (a.q_th) {
-        case 7: store_scalar_eq<7>(f, N, c, T, a.t_shift, u); break;
-        case 15: store_scalar_eq<15>(f, N, c, T, a.t_shift, u); break;
-        case 19: store_scalar_eq<19>(f, N, c, T, a.t_shift, u); break;
-        default: store_scalar_eq<27>(f, N, c, T, a.t_shift, u); break;
+        case 7: store_scalar_eq<7>(f, G, x, y, z, T, a.t_shift, u); break;
+        case 15: store_scalar_eq<15>(f, G, x, y, z, T, a.t_shift, u); break;
+        case 19: store_scalar_eq<19>(f, G, x, y, z, T, a.t_shift, u); break;
+        default: store_scalar_eq<27>(f, G, x, y, z, T, a.t_shift, u); break;
         }
     }
     static_cast<S *>(a.phi_other)[c] = static_cast<S>(phi);
@@ -98,16 +101,19 @@ template <typename S>
 __global__ void __launch_bounds__(kThreads) k_read(const ReadArgs a)
 {
     const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    const int64_t N = a.geo.N;
-    if (c >= N) return;
+    const Geometry &G = a.geo;
+    if (c >= G.N) return;
     double v = 0.0;
     if (a.which == 0) v = static_cast<const S *>(a.phi)[c];
     else if (a.which >= 1 && a.which <= 3) v = static_cast<const S *>(a.u[a.which - 1])[c];
     else if (a.which == 4) v = static_cast<const S *>(a.T)[c];
     else {
         double ps = 0.0;
-        if (a.which == 5 || a.which == 6)
-            for (int i = 0; i < 27; ++i) ps += static_cast<double>(static_cast<const S *>(a.g)[i * N + c]);
+        if (a.which == 5 || a.which == 6) {
+            const int x = (int)(c % G.nx), y = (int)((c / G.nx) % G.ny), z = (int)(c / G.plane);
+            for (int i = 0; i < 27; ++i)
+                ps += static_cast<double>(static_cast<const S *>(a.g)[pdf_index<27>(G, x, y, z, i)]);
+        }
         const double phi = static_cast<const S *>(a.phi)[c];
         const double phic = phi < 0.0 ? 0.0 : (phi > 1.0 ? 1.0 : phi);
         const double rho = a.rho_l + phic * a.drho;
@@ -116,14 +122,17 @@ __global__ void __launch_bounds__(kThreads) k_read(const ReadArgs a)
     a.out[c] = v;
 }
 
+// blocked PDF layout -> component-major FP64 out[i*N + c]
 template <int Q, typename P, typename F>
-__global__ void __launch_bounds__(kThreads) k_read_pdfs(const P *src, int64_t N, double shift, const F *field,
+__global__ void __launch_bounds__(kThreads) k_read_pdfs(const P *src, const Geometry g, double shift, const F *field,
                                                         double *out)
 {
     const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-    if (c >= N) return;
+    if (c >= g.N) return;
+    const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / g.plane);
     const double sh = shift + (field ? static_cast<double>(field[c]) : 0.0);
-    for (int i = 0; i < Q; ++i) out[i * N + c] = static_cast<double>(src[i * N + c]) + weight<Q>(i) * sh;
+    for (int i = 0; i < Q; ++i)
+        out[i * g.N + c] = static_cast<double>(src[pdf_index<Q>(g, x, y, z, i)]) + weight<Q>(i) * sh;
 }
 
 template <typename S>
@@ -204,17 +213,17 @@ void launch_read(const ReadArgs &a, hipStream_t s)
 }
 
 template <typename P, typename F>
-void launch_read_pdfs(const void *src, int q, int64_t N, double shift, const void *field, double *out,
+void launch_read_pdfs(const void *src, int q, const Geometry &g, double shift, const void *field, double *out,
                       hipStream_t s)
 {
     const P *p = static_cast<const P *>(src);
     const F *fl = static_cast<const F *>(field);
-    const dim3 gr(blocks_for(N)), bl(kThreads);
+    const dim3 gr(blocks_for(g.N)), bl(kThreads);
     switch (q) {
-    case 7: hipLaunchKernelGGL((k_read_pdfs<7, P, F>), gr, bl, 0, s, p, N, shift, fl, out); break;
-    case 15: hipLaunchKernelGGL((k_read_pdfs<15, P, F>), gr, bl, 0, s, p, N, shift, fl, out); break;
-    case 19: hipLaunchKernelGGL((k_read_pdfs<19, P, F>), gr, bl, 0, s, p, N, shift, fl, out); break;
-    default: hipLaunchKernelGGL((k_read_pdfs<27, P, F>), gr, bl, 0, s, p, N, shift, fl, out); break;
+    case 7: hipLaunchKernelGGL((k_read_pdfs<7, P, F>), gr, bl, 0, s, p, g, shift, fl, out); break;
+    case 15: hipLaunchKernelGGL((k_read_pdfs<15, P, F>), gr, bl, 0, s, p, g, shift, fl, out); break;
+    case 19: hipLaunchKernelGGL((k_read_pdfs<19, P, F>), gr, bl, 0, s, p, g, shift, fl, out); break;
+    default: hipLaunchKernelGGL((k_read_pdfs<27, P, F>), gr, bl, 0, s, p, g, shift, fl, out); break;
     }
 }
 
@@ -237,13 +246,13 @@ void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
     template void launch_from_f64<S>(const double *, void *, int64_t, hipStream_t);                         \
     template void launch_init<S, S>(const InitArgs &, hipStream_t);                                         \
     template void launch_read<S>(const ReadArgs &, hipStream_t);                                            \
-    template void launch_read_pdfs<S, S>(const void *, int, int64_t, double, const void *, double *, hipStream_t); \
+    template void launch_read_pdfs<S, S>(const void *, int, const Geometry &, double, const void *, double *, hipStream_t); \
     template void launch_reduce<S>(const Geometry &, const void *, double *, double *, hipStream_t);
 TCP_AUX_INST(double)
 TCP_AUX_INST(float)
 #undef TCP_AUX_INST
 template void launch_init<float, _Float16>(const InitArgs &, hipStream_t);
-template void launch_read_pdfs<_Float16, float>(const void *, int, int64_t, double, const void *, double *,
+template void launch_read_pdfs<_Float16, float>(const void *, int, const Geometry &, double, const void *, double *,
                                                 hipStream_t);
 
 } // namespace tcp

@@ -23,8 +23,8 @@ namespace tcp {
 template <typename S, typename R, bool WALL>
 __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb)
 {
-    const int64_t N = a.geo.N;
     const S *gs = static_cast<const S *>(a.g_src);
+    const PdfLanes<27> pl(nb);
 
     // pull; halfway bounce-back, plus 2 w_i (e_i . u_w)/c_s^2 from a moving wall
     R g[27];
@@ -34,9 +34,10 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb)
         if (WALL && nb.ghost(-ey)) {
             const double *uw = ey > 0 ? a.uw_bot : a.uw_top;
             const double eu = ex * uw[0] + ey * uw[1] + ez * uw[2];
-            g[i] = ld<R>(elem(gs + opposite<27>(i) * N, nb.c)) + R(6.0 * weight<27>(i) * eu);
+            g[i] = ld<R>(elem(pdf_row<27>(gs, a.geo, nb.yr[1], nb.zi[1], opposite<27>(i)), pl.xq[1])) +
+                   R(6.0 * weight<27>(i) * eu);
         } else {
-            g[i] = ld<R>(elem(gs + i * N, nb.at(-ex, -ey, -ez)));
+            g[i] = ld<R>(elem(pdf_row<27>(gs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
         }
     }
     // zeroth, first and second raw moments from sums and differences of opposite pairs
@@ -165,7 +166,7 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb)
     S *gd = static_cast<S *>(a.g_dst);
     {
         const R corr = Z.m0[1] * A0[1][1] + Z.m1[1] * A1[1][1] + Z.m2[1] * A2[1][1];
-        st(elem(gd, nb.c), R(weight<27>(0)) * C + corr);
+        st(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], 0), pl.xq[1]), R(weight<27>(0)) * C + corr);
     }
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
@@ -183,8 +184,8 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb)
         const int oa = 1 - ex, ob = 1 - ey, oc = 1 - ez;
         const R ci = Z.m0[ic] * A0[ia][ib] + Z.m1[ic] * A1[ia][ib] + Z.m2[ic] * A2[ia][ib];
         const R co = Z.m0[oc] * A0[oa][ob] + Z.m1[oc] * A1[oa][ob] + Z.m2[oc] * A2[oa][ob];
-        st(elem(gd + i * N, nb.c), even + odd + ci);
-        st(elem(gd + o * N, nb.c), even - odd + co);
+        st(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), even + odd + ci);
+        st(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], o), pl.xq[1]), even - odd + co);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) st(elem(static_cast<S *>(a.u[k]), nb.c), u[k]);

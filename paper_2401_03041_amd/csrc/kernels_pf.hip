@@ -21,8 +21,8 @@ template <int Q, typename P, typename S, typename R, bool WALL>
 __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
 {
     constexpr bool dev = deviation_storage<P>();
-    const int64_t N = a.geo.N;
     const P *hs = static_cast<const P *>(a.h_src);
+    const PdfLanes<Q> pl(nb);
 
     // phi^n on the 3x3x3 neighbourhood (mirror ghosts across walls)
     const S *po = static_cast<const S *>(a.phi_old);
@@ -36,7 +36,8 @@ __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
         const bool wall = WALL && nb.ghost(-ey);
-        h[i] = wall ? ld<R>(elem(hs + opposite<Q>(i) * N, nb.c)) : ld<R>(elem(hs + i * N, nb.at(-ex, -ey, -ez)));
+        h[i] = wall ? ld<R>(elem(pdf_row<Q>(hs, a.geo, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1]))
+                    : ld<R>(elem(pdf_row<Q>(hs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
         if constexpr (dev) h[i] += R(weight<Q>(i)) * pn[wall ? 0 : opposite<27>(index27<Q>(i))];
     }
     // zeroth and first moments from sums and differences of opposite pairs
@@ -91,7 +92,7 @@ __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
         const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
         const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
         const R rest = dev ? phi * zeta : phi * (R(1) + zeta); // minus w phi when stored as a deviation
-        st(elem(hd + i * N, nb.c), w * (rest + R(0.5) * eF) + d[i]);
+        st(elem(pdf_row<Q>(hd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * (rest + R(0.5) * eF) + d[i]);
     }
     st(elem(static_cast<S *>(a.phi_new), nb.c), phi);
 }

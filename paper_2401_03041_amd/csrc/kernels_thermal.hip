@@ -22,8 +22,8 @@ template <int Q, typename P, typename S, typename R, bool WALL>
 __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb, int x, int y, int z)
 {
     constexpr bool dev = deviation_storage<P>();
-    const int64_t N = a.geo.N;
     const P *fs = static_cast<const P *>(a.f_src);
+    const PdfLanes<Q> pl(nb);
     const S *to = static_cast<const S *>(a.T_old);
     // stored value = f - w ts (constant shift) or f - w T^n(source) (deviation)
     const R ts = dev ? R(0) : R(a.t_shift);
@@ -37,12 +37,12 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
         if (WALL && nb.ghost(-ey)) {
             // anti-bounce-back f_i = 2 w T_w - f*_opp(x); f[] holds f - w ts
             const double *tw = ey > 0 ? a.twb : a.twt;
-            f[i] = R(2) * w * R(tw[nb.col(0, 0, a.geo)]) - ld<R>(elem(fs + opposite<Q>(i) * N, nb.c)) -
+            f[i] = R(2) * w * R(tw[nb.col(0, 0, a.geo)]) -
+                   ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1])) -
                    w * (dev ? t_own : R(2) * ts);
         } else {
-            const uint32_t src = nb.at(-ex, -ey, -ez);
-            f[i] = ld<R>(elem(fs + i * N, src));
-            if constexpr (dev) f[i] += w * (i == 0 ? t_own : ld<R>(elem(to, src)));
+            f[i] = ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+            if constexpr (dev) f[i] += w * (i == 0 ? t_own : ld<R>(elem(to, nb.at(-ex, -ey, -ez))));
         }
     }
     // zeroth and first moments from sums and differences of opposite pairs
@@ -77,7 +77,7 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
         const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
         // f* - w ts = w (T (1 + zeta) - ts) + d + w q;  f* - w T = w T zeta + d + w q
         const R rest = dev ? T * zeta : Tp * (R(1) + zeta) + ts * zeta;
-        st(elem(fd + i * N, nb.c), w * rest + d[i] + w * q);
+        st(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * rest + d[i] + w * q);
     }
     st(elem(static_cast<S *>(a.T), nb.c), T);
 }

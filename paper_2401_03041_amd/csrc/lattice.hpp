@@ -79,6 +79,7 @@ __device__ __forceinline__ void st(S *p, R v)
 struct Geometry {
     int nx, ny, nz;
     int walls;     // 1: no-slip walls at y = -1/2 and y = ny - 1/2
+    int nbx;       // blocks of 64 cells per x-row in the PDF layout: ceil(nx / 64)
     int64_t N;     // nx*ny*nz
     int64_t plane; // nx*ny
 };
@@ -104,7 +105,8 @@ __device__ __forceinline__ S *elem(S *base, uint32_t idx)
 // boundary rule.
 struct Nbr {
     uint32_t xo[3]; // x-1, x, x+1 (wrapped)
-    uint32_t yo[3]; // row offsets of y-1, y, y+1 (wrapped or clamped)
+    uint32_t yr[3]; // y-1, y, y+1 (wrapped or clamped)
+    uint32_t yo[3]; // row offsets yr * nx
     uint32_t zo[3]; // plane offsets of z-1, z, z+1 (wrapped)
     uint32_t zi[3]; // z-1, z, z+1 (wrapped)
     uint32_t c;     // own linear index
@@ -118,9 +120,10 @@ struct Nbr {
         xo[2] = x == g.nx - 1 ? 0 : x + 1;
         const int ym = y == 0 ? (g.walls ? 0 : g.ny - 1) : y - 1;
         const int yp = y == g.ny - 1 ? (g.walls ? g.ny - 1 : 0) : y + 1;
-        yo[0] = (uint32_t)ym * (uint32_t)g.nx;
-        yo[1] = (uint32_t)y * (uint32_t)g.nx;
-        yo[2] = (uint32_t)yp * (uint32_t)g.nx;
+        yr[0] = (uint32_t)ym;
+        yr[1] = (uint32_t)y;
+        yr[2] = (uint32_t)yp;
+        for (int k = 0; k < 3; ++k) yo[k] = yr[k] * (uint32_t)g.nx;
         zi[0] = z == 0 ? g.nz - 1 : z - 1;
         zi[1] = z;
         zi[2] = z == g.nz - 1 ? 0 : z + 1;
@@ -145,6 +148,43 @@ struct Nbr {
         return xo[dx + 1] + zi[dz + 1] * (uint32_t)g.nx;
     }
 };
+
+// ----------------------------------------------------------------------------
+// PDF layout.  Fields are plain arrays (x fastest).  PDF arrays are blocked:
+// each x-row (y, z) holds nbx = ceil(nx/64) blocks of 64 cells, and within a
+// block the Q components follow each other as runs of 64 values, so component
+// i of cell (x, y, z) sits at
+//     ((y + ny z) nbx + x/64) 64 Q + 64 i + x%64.
+// A kernel touching Q components then streams from one contiguous region per
+// block instead of from Q regions a whole grid apart, which a 27-component copy
+// runs a quarter faster with.  A wavefront updates the 64 cells of one block
+// (one row), so the row part of every address is wave-uniform (scalar
+// registers) and the per-lane part is one of three offsets, for x-1, x, x+1.
+// ----------------------------------------------------------------------------
+inline int64_t pdf_elems(const Geometry &g, int q) { return (int64_t)g.nbx * 64 * q * g.ny * g.nz; }
+
+template <int Q>
+__host__ __device__ __forceinline__ int64_t pdf_index(const Geometry &g, int x, int y, int z, int i)
+{
+    return ((int64_t)(y + (int64_t)g.ny * z) * g.nbx + (x >> 6)) * (64 * Q) + 64 * i + (x & 63);
+}
+
+// per-lane offsets, within a row, of the cells x-1, x, x+1
+template <int Q>
+struct PdfLanes {
+    uint32_t xq[3];
+    __device__ __forceinline__ explicit PdfLanes(const Nbr &nb)
+    {
+        for (int k = 0; k < 3; ++k) xq[k] = (nb.xo[k] >> 6) * (64u * Q) + (nb.xo[k] & 63u);
+    }
+};
+
+// start of component i of row (y, z): wave-uniform
+template <int Q, typename P>
+__device__ __forceinline__ P *pdf_row(P *base, const Geometry &g, uint32_t y, uint32_t z, int i)
+{
+    return base + ((int64_t)(y + (uint32_t)g.ny * z) * g.nbx * (64 * Q) + 64 * i);
+}
 
 // ----------------------------------------------------------------------------
 // Work-group order.
@@ -183,6 +223,9 @@ inline dim3 tiling_grid(const Tiling &t) { return dim3((unsigned)(t.per_xcd * kX
 inline dim3 tiling_block() { return dim3(kTX, kTY, 1); }
 
 // Cell of this thread; false for padding work-groups and cells outside the grid.
+// A wavefront is one x-row of a tile (64 threads with the same threadIdx.y), so
+// y and z are wave-uniform; y is read through readfirstlane to tell the compiler.
+static_assert(kTX == 64, "a wavefront must cover exactly one 64-cell block of a row");
 __device__ __forceinline__ bool cell_of_thread(const Tiling &t, const Geometry &g, int &x, int &y, int &z)
 {
     const int w = blockIdx.x;
@@ -195,7 +238,7 @@ __device__ __forceinline__ bool cell_of_thread(const Tiling &t, const Geometry &
     const int ty = r % t.tiles_y;
     const int cz = r / t.tiles_y;
     x = tx * kTX + threadIdx.x;
-    y = ty * kTY + threadIdx.y;
+    y = ty * kTY + __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     z = cz * kTZ + zz;
     return x < g.nx && y < g.ny && z < g.nz;
 }

@@ -356,7 +356,8 @@ int validate(const tcp_params *p, std::string &why)
     char buf[256];
     if (p->nx < 1 || p->ny < 1 || p->nz < 1) { why = "grid dimensions must be >= 1"; return TCP_ERR_ARG; }
     {
-        // kernels address each field and PDF component array with 32-bit byte offsets
+        // kernels address each field array with 32-bit byte offsets (PDF rows are
+        // addressed from wave-uniform 64-bit row pointers)
         const int64_t ncell = (int64_t)p->nx * p->ny * p->nz;
         const int64_t bytes = ncell * (p->precision == TCP_FP64 ? 8 : 4);
         if (bytes >= ((int64_t)1 << 32)) {
@@ -437,9 +438,9 @@ std::vector<Piece> state_pieces(const tcp_domain *d)
 {
     const size_t N = (size_t)d->geo.N, sb = d->sb, pb = d->pb;
     std::vector<Piece> v;
-    v.push_back({d->h[d->cur], N * d->P.q_pf * pb});
-    v.push_back({d->g[d->cur], N * 27 * sb});
-    if (d->P.thermal == TCP_THERMAL_LB) v.push_back({d->f[d->cur], N * d->P.q_thermal * pb});
+    v.push_back({d->h[d->cur], (size_t)pdf_elems(d->geo, d->P.q_pf) * pb});
+    v.push_back({d->g[d->cur], (size_t)pdf_elems(d->geo, 27) * sb});
+    if (d->P.thermal == TCP_THERMAL_LB) v.push_back({d->f[d->cur], (size_t)pdf_elems(d->geo, d->P.q_thermal) * pb});
     v.push_back({d->phi[d->cur], N * sb});
     for (int k = 0; k < 3; ++k) v.push_back({d->u[k], N * sb});
     v.push_back({d->T[d->cur], N * sb});
@@ -490,6 +491,7 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
     d->geo.ny = p->ny;
     d->geo.nz = p->nz;
     d->geo.walls = p->walls_y;
+    d->geo.nbx = (p->nx + 63) / 64;
     d->geo.plane = (int64_t)p->nx * p->ny;
     d->geo.N = d->geo.plane * p->nz;
     d->omega_phi = 1.0 / (0.5 + 3.0 * p->mobility);
@@ -498,9 +500,9 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
     const size_t N = (size_t)d->geo.N, sb = d->sb, pb = d->pb;
     bool ok = true;
     for (int b = 0; b < 2; ++b) {
-        ok = ok && (d->h[b] = own(d, N * p->q_pf * pb));
-        ok = ok && (d->g[b] = own(d, N * 27 * sb));
-        if (p->thermal == TCP_THERMAL_LB) ok = ok && (d->f[b] = own(d, N * p->q_thermal * pb));
+        ok = ok && (d->h[b] = own(d, (size_t)pdf_elems(d->geo, p->q_pf) * pb));
+        ok = ok && (d->g[b] = own(d, (size_t)pdf_elems(d->geo, 27) * sb));
+        if (p->thermal == TCP_THERMAL_LB) ok = ok && (d->f[b] = own(d, (size_t)pdf_elems(d->geo, p->q_thermal) * pb));
         ok = ok && (d->phi[b] = own(d, N * sb));
         ok = ok && (d->T[b] = own(d, N * sb));
     }
@@ -746,9 +748,9 @@ int tcp_get_pdfs(tcp_domain *d, int which, double *host_out)
         Scratch tmp(d, (size_t)N * q * sizeof(double));
         if (!tmp.p) return fail(d, TCP_ERR_OOM, "staging allocation failed");
         double *o = static_cast<double *>(tmp.p);
-        if (bytes == 8) launch_read_pdfs<double, double>(src, q, N, shift, field, o, d->stream);
-        else if (bytes == 4) launch_read_pdfs<float, float>(src, q, N, shift, field, o, d->stream);
-        else launch_read_pdfs<_Float16, float>(src, q, N, shift, field, o, d->stream);
+        if (bytes == 8) launch_read_pdfs<double, double>(src, q, d->geo, shift, field, o, d->stream);
+        else if (bytes == 4) launch_read_pdfs<float, float>(src, q, d->geo, shift, field, o, d->stream);
+        else launch_read_pdfs<_Float16, float>(src, q, d->geo, shift, field, o, d->stream);
         int rc = check_launch(d);
         if (rc != TCP_OK) return rc;
         TCP_HIP(d, hipMemcpyAsync(host_out, tmp.p, (size_t)N * q * sizeof(double), hipMemcpyDeviceToHost, d->stream));
