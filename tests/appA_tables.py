@@ -1,6 +1,6 @@
 """Reproduce the App. A verification tables of Sec. 3.1 on the GPU.
 
-    python tests/appA_tables.py [--only 2D|3D] [--precision fp64|fp32] [--steps N]
+    python tests/appA_tables.py [--only 2D|3D] [--kstar K] [--precision fp64|fp32] [--steps N]
 
 Runs the 2D channel with the thermal LB (D3Q7), RK2 and RK4 schemes and the
 pseudo-3D channel (10 cells in z) with the D3Q7/15/19/27 thermal LB, for the
@@ -29,12 +29,13 @@ def main() -> int:
     ap.add_argument("--only", choices=("2D", "3D"), default=None)
     ap.add_argument("--precision", default="fp64")
     ap.add_argument("--steps", type=int, default=400_000)
+    ap.add_argument("--kstar", type=float, default=None, help="only this conductivity ratio")
     args = ap.parse_args()
     table = load_table(os.path.join(ROOT, "tests", "golden", "appA_planar_channel.txt"))
     print("| table | case | k* | l2 T | paper | l2 |u| | paper | s |")
     print("|---|---|---|---|---|---|---|---|")
     for (tab, case, ks), (pT, pu) in table.items():
-        if args.only and tab != args.only:
+        if (args.only and tab != args.only) or (args.kstar is not None and ks != args.kstar):
             continue
         thermal, q = CASES[case]
         t0 = time.perf_counter()
