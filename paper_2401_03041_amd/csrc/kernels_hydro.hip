@@ -166,7 +166,7 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb)
     S *gd = static_cast<S *>(a.g_dst);
     {
         const R corr = Z.m0[1] * A0[1][1] + Z.m1[1] * A1[1][1] + Z.m2[1] * A2[1][1];
-        st(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], 0), pl.xq[1]), R(weight<27>(0)) * C + corr);
+        st_pdf(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], 0), pl.xq[1]), R(weight<27>(0)) * C + corr);
     }
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
@@ -184,8 +184,8 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb)
         const int oa = 1 - ex, ob = 1 - ey, oc = 1 - ez;
         const R ci = Z.m0[ic] * A0[ia][ib] + Z.m1[ic] * A1[ia][ib] + Z.m2[ic] * A2[ia][ib];
         const R co = Z.m0[oc] * A0[oa][ob] + Z.m1[oc] * A1[oa][ob] + Z.m2[oc] * A2[oa][ob];
-        st(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), even + odd + ci);
-        st(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], o), pl.xq[1]), even - odd + co);
+        st_pdf(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), even + odd + ci);
+        st_pdf(elem(pdf_row<27>(gd, a.geo, nb.yr[1], nb.zi[1], o), pl.xq[1]), even - odd + co);
     }
 #pragma unroll
     for (int k = 0; k < 3; ++k) st(elem(static_cast<S *>(a.u[k]), nb.c), u[k]);

@@ -92,7 +92,7 @@ __device__ __forceinline__ void phase_field_cell(const PfArgs &a, const Nbr &nb)
         const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
         const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
         const R rest = dev ? phi * zeta : phi * (R(1) + zeta); // minus w phi when stored as a deviation
-        st(elem(pdf_row<Q>(hd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * (rest + R(0.5) * eF) + d[i]);
+        st_pdf(elem(pdf_row<Q>(hd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * (rest + R(0.5) * eF) + d[i]);
     }
     st(elem(static_cast<S *>(a.phi_new), nb.c), phi);
 }

@@ -77,7 +77,7 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
         const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
         // f* - w ts = w (T (1 + zeta) - ts) + d + w q;  f* - w T = w T zeta + d + w q
         const R rest = dev ? T * zeta : Tp * (R(1) + zeta) + ts * zeta;
-        st(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * rest + d[i] + w * q);
+        st_pdf(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * rest + d[i] + w * q);
     }
     st(elem(static_cast<S *>(a.T), nb.c), T);
 }
