@@ -188,7 +188,7 @@ def main() -> int:
                     help="timed steps with FP16 phase-field/thermal PDFs (default: steps/2; 0 skips)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-box", type=int, default=64)
-    ap.add_argument("--oracle-steps", type=int, default=40)
+    ap.add_argument("--oracle-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernel")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
