@@ -168,6 +168,43 @@ def cpu_baseline(cfg: dict, box: int, steps: int) -> dict:
                       f"{el:.1f} s"}
 
 
+# The paper's own per-GPU figures for its coupled FP64 step on a 512 x 256 x 256
+# block (D3Q27 phase field and hydrodynamics; one node of four GPUs in the weak
+# scaling figures of Sec. 5, MLUPS per GPU, an MI250 "GPU" being the module) and
+# for the thermal sub-step alone (Sec. 5 comparison of the thermal schemes, GLUPS).
+PAPER_COUPLED_MLUPS = {"A100": {"lb_d3q7": 1189.6, "rk2": 1190.9, "rk4": 1030.8},
+                       "MI250": {"lb_d3q7": 1626.7, "rk2": 1472.5, "rk4": 1244.7}}
+PAPER_THERMAL_GLUPS = {"A100": {"lb_d3q7": 9.058, "lb_d3q15": 4.785, "lb_d3q19": 3.949, "lb_d3q27": 2.859,
+                                "rk2": 7.781, "rk4": 3.573},
+                       "MI250": {"lb_d3q7": 13.544, "lb_d3q15": 7.352, "lb_d3q19": 5.850, "lb_d3q27": 3.712,
+                                 "rk2": 8.308, "rk4": 4.060}}
+
+
+def paper_block(steps: int, warmup: int) -> dict:
+    """The paper's per-GPU benchmark shape: 512 x 256 x 256 cells, FP64, D3Q27 phase
+    field + D3Q27 hydrodynamics + each thermal scheme (capture-channel workload:
+    walls, moving lid, heater, droplet; kappa = 0.2 so that the RK schemes are
+    stable).  Coupled-step MLUPS and the thermal sub-step alone in GLUPS."""
+    from paper_2401_03041_amd import workloads as W
+    coupled, thermal = {}, {}
+    for name, th, q in (("lb_d3q7", "lb", 7), ("lb_d3q15", "lb", 15), ("lb_d3q19", "lb", 19),
+                        ("lb_d3q27", "lb", 27), ("rk2", "rk2", 7), ("rk4", "rk4", 7)):
+        cfg = dict(W.capture(shape=(512, 256, 256), precision="fp64"), q_pf=27, thermal=th, q_thermal=q,
+                   kappa_h=0.2, kappa_l=0.2)
+        res = run_gpu(cfg, steps, warmup, "fp64")
+        n = 512 * 256 * 256
+        if name in ("lb_d3q7", "rk2", "rk4"):
+            coupled[name] = round(res["mlups"], 1)
+        k = res["kernels"]["thermal" if th == "lb" else "rk"]
+        per_step_ms = k["avg_ms"] * k["launches"] / steps
+        thermal[name] = round(n / (per_step_ms * 1e-3) / 1e9, 3)
+    return {"grid": [512, 256, 256], "dtype": "f64", "steps": steps,
+            "workload": "capture channel (walls, moving lid, heater, droplet), D3Q27 phase field + D3Q27 "
+                        "hydrodynamics + thermal scheme",
+            "coupled_MLUPS": coupled, "thermal_substep_GLUPS": thermal,
+            "paper_coupled_MLUPS_per_gpu": PAPER_COUPLED_MLUPS, "paper_thermal_substep_GLUPS": PAPER_THERMAL_GLUPS}
+
+
 def copy_calibration(gib: float = 4.0, reps: int = 3) -> None:
     """The library's streaming copy kernel on a buffer of known size, for
     scaling the HBM byte counters: every dispatch reads and writes `gib` GiB."""
@@ -187,6 +224,8 @@ def main() -> int:
     ap.add_argument("--fp16-steps", type=int, default=None,
                     help="timed steps with FP16 phase-field/thermal PDFs (default: steps/2; 0 skips)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-paper-block", action="store_true",
+                    help="skip the FP64 runs on the paper's 512 x 256 x 256 benchmark shape")
     ap.add_argument("--oracle-box", type=int, default=64)
     ap.add_argument("--oracle-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernel")
@@ -209,6 +248,7 @@ def main() -> int:
     fp64 = run_gpu(cfg, fp64_steps, max(2, args.warmup // 4), "fp64") if fp64_steps > 0 else None
     fp16_steps = args.steps // 2 if args.fp16_steps is None else args.fp16_steps
     fp16 = run_gpu(cfg, fp16_steps, max(2, args.warmup // 4), "fp16") if fp16_steps > 0 else None
+    pblock = None if args.no_paper_block else paper_block(10, 2)
     base = None if args.no_cpu_baseline else cpu_baseline(cfg, args.oracle_box, args.oracle_steps)
 
     line = {
@@ -240,6 +280,8 @@ def main() -> int:
                         "ms_per_step": round(fp64["ms_per_step"], 4), "dtype": "f64",
                         "roofline": roofline(fp64, "fp64"), "effective_GBs": round(fp64["effective_GBs"], 1),
                         "step_bytes_per_cell": fp64["step_bytes_per_cell"]}
+    if pblock is not None:
+        line["paper_block"] = pblock
     if fp16 is not None:
         line["fp16"] = {"value": round(fp16["mlups"], 2), "unit": "MLUPS", "steps": fp16_steps,
                         "ms_per_step": round(fp16["ms_per_step"], 4),
