@@ -29,24 +29,29 @@ if ROOT not in sys.path:
 
 METRIC = "MLUPS & % HBM roofline per coupled step, FP32 vs FP64; adjoint/forward cost"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_hydro_droplet_block_512.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_step_droplet_block_512.md")
 
 
 def _log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+KERNEL_SOURCES = ("kernels_step.hip", "cell_pf.hpp", "cell_hydro.hpp", "cell_thermal.hpp", "lattice.hpp",
+                  "kernels.hpp")
+
+
 def _kernel_sha() -> str:
     h = hashlib.sha256()
-    for name in ("kernels_hydro.hip", "lattice.hpp", "kernels.hpp"):
+    for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2401_03041_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
 def _traffic(precision: str):
-    """Measured HBM bytes per hydrodynamic launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
-    scaled by a copy kernel), if taken on the current kernel source."""
+    """Measured HBM bytes per launch of the fused step kernel (rocprofv3
+    FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel), if taken on the current
+    kernel source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -61,13 +66,14 @@ def _traffic(precision: str):
     return float(vals[key]) if key in vals else None
 
 
-def run_gpu(cfg: dict, steps: int, warmup: int, precision: str) -> dict:
+def run_gpu(cfg: dict, steps: int, warmup: int, precision: str, fuse: bool = True) -> dict:
     import torch
 
     from paper_2401_03041_amd import tcplb
     cfg = dict(cfg, precision=precision)
     t0 = time.perf_counter()
     d = tcplb.domain_from_workload(cfg)
+    d.set_fusion(fuse)
     torch.cuda.synchronize()
     _log(f"{precision}: set-up {time.perf_counter() - t0:.1f} s")
     d.step(warmup)
@@ -105,9 +111,9 @@ def run_gpu(cfg: dict, steps: int, warmup: int, precision: str) -> dict:
 
 
 def roofline(res: dict, precision: str) -> dict:
-    k = res["kernels"]["hydro"]
+    k = res["kernels"]["step"]
     achieved = k["achieved_GBs"]
-    return {"bound": "hbm", "kernel": "hydro (D3Q27 central-moment step with forces)",
+    return {"bound": "hbm", "kernel": "step (phase field D3Q15 + hydrodynamics D3Q27 + thermal D3Q7, fused)",
             "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": _traffic(precision),
             "algorithmic_bytes_per_launch": k["algorithmic_bytes_per_launch"],
@@ -184,16 +190,19 @@ def paper_block(steps: int, warmup: int) -> dict:
     """The paper's per-GPU benchmark shape: 512 x 256 x 256 cells, FP64, D3Q27 phase
     field + D3Q27 hydrodynamics + each thermal scheme (capture-channel workload:
     walls, moving lid, heater, droplet; kappa = 0.2 so that the RK schemes are
-    stable).  Coupled-step MLUPS and the thermal sub-step alone in GLUPS."""
+    stable).  Coupled-step MLUPS (the thermal LB step fused into one kernel) and
+    the thermal sub-step alone in GLUPS (timed with the kernels apart)."""
     from paper_2401_03041_amd import workloads as W
     coupled, thermal = {}, {}
+    n = 512 * 256 * 256
     for name, th, q in (("lb_d3q7", "lb", 7), ("lb_d3q15", "lb", 15), ("lb_d3q19", "lb", 19),
                         ("lb_d3q27", "lb", 27), ("rk2", "rk2", 7), ("rk4", "rk4", 7)):
         cfg = dict(W.capture(shape=(512, 256, 256), precision="fp64"), q_pf=27, thermal=th, q_thermal=q,
                    kappa_h=0.2, kappa_l=0.2)
-        res = run_gpu(cfg, steps, warmup, "fp64")
-        n = 512 * 256 * 256
-        if name in ("lb_d3q7", "rk2", "rk4"):
+        if name == "lb_d3q7":
+            coupled[name] = round(run_gpu(cfg, steps, warmup, "fp64")["mlups"], 1)
+        res = run_gpu(cfg, steps, warmup, "fp64", fuse=False)
+        if name in ("rk2", "rk4"):
             coupled[name] = round(res["mlups"], 1)
         k = res["kernels"]["thermal" if th == "lb" else "rk"]
         per_step_ms = k["avg_ms"] * k["launches"] / steps

@@ -70,8 +70,11 @@ enum { TCP_THERMAL_LB = 0, TCP_THERMAL_RK2 = 1, TCP_THERMAL_RK4 = 2 };
  * Reductions and read-back are FP64 in every mode. */
 enum { TCP_FP64 = 0, TCP_FP32 = 1, TCP_FP16 = 2 };
 
-/* Kernel kinds reported by tcp_kernel_times */
-enum { TCP_K_PHASE = 0, TCP_K_HYDRO = 1, TCP_K_THERMAL = 2, TCP_K_RK = 3, TCP_K_COUNT = 4 };
+/* Kernel kinds reported by tcp_kernel_times and tcp_algorithmic_bytes:
+ * the phase-field, hydrodynamic and thermal LB kernels, an RK stage, and the
+ * fused step (all three LB updates of a step in one kernel, see
+ * tcp_set_fusion). */
+enum { TCP_K_PHASE = 0, TCP_K_HYDRO = 1, TCP_K_THERMAL = 2, TCP_K_RK = 3, TCP_K_STEP = 4, TCP_K_COUNT = 5 };
 
 typedef struct tcp_domain tcp_domain;
 
@@ -188,6 +191,14 @@ int tcp_synchronize(tcp_domain *d);
  * of TCP_K_COUNT entries) and resets the counters. */
 int tcp_set_profiling(tcp_domain *d, int enabled);
 int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches);
+
+/* Fusion.  With the thermal LB (TCP_THERMAL_LB) a step runs as one kernel in
+ * which each thread updates its cell's phase field, hydrodynamics and
+ * temperature in turn (no thread reads what another writes within a step, so
+ * this is the same update as the three kernels of Algorithm 1, with fewer
+ * field reads).  enabled = 0 launches the three kernels instead (default 1).
+ * The RK schemes always run the separate kernels. */
+int tcp_set_fusion(tcp_domain *d, int enabled);
 
 /* Step graphs.  On small grids a step's few-microsecond kernels are bound by
  * host launch cost; tcp_step then captures 16 steps into one HIP graph (on

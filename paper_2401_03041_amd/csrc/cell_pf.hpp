@@ -1,0 +1,104 @@
+// cell_pf.hpp -- K1: conservative Allen-Cahn phase-field LB step
+// (Eq. lb_interface with the counter-term of Eq. phasefieldforce applied as a
+// source in collision space).  One thread per cell, pull streaming from the
+// post-collision PDFs of the previous step, halfway bounce-back at y walls.
+//
+// Collision: central moments about u^n on the moment basis of the stencil,
+// first-order moments relaxed with omega_phi, all higher ones with rate one.
+// Because the higher moments relax fully, the post-collision state is
+// h_eq + S/2 plus the inverse transform of the relaxed first-order moments
+// (FirstOrder<Q>), which is what the kernel evaluates.
+//
+// Storage in type P: unshifted, or (FP16) as the deviation h*_i - w_i phi(x)
+// from the rest equilibrium of the cell (deviation_storage).  The pull then
+// adds w_i phi^n of the source cell, which the kernel loads anyway for the
+// gradient of phi^n: phi^n(y) is the zeroth moment of the h* stored at y.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace tcp {
+
+// Update of one cell; returns phi^{n+1}.
+template <int Q, typename P, typename S, typename R, bool WALL>
+__device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
+{
+    constexpr bool dev = deviation_storage<P>();
+    const P *hs = static_cast<const P *>(a.h_src);
+    const PdfLanes<Q> pl(nb);
+
+    // phi^n on the 3x3x3 neighbourhood (mirror ghosts across walls)
+    const S *po = static_cast<const S *>(a.phi_old);
+    R pn[27];
+#pragma unroll
+    for (int k = dev ? 0 : 1; k < 27; ++k) pn[k] = ld<R>(elem(po, nb.at(vel27(k, 0), vel27(k, 1), vel27(k, 2))));
+
+    // pull; a link that crosses a wall returns the cell's own opposite PDF
+    R h[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        const bool wall = WALL && nb.ghost(-ey);
+        h[i] = wall ? ld<R>(elem(pdf_row<Q>(hs, a.geo, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1]))
+                    : ld<R>(elem(pdf_row<Q>(hs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+        if constexpr (dev) h[i] += R(weight<Q>(i)) * pn[wall ? 0 : opposite<27>(index27<Q>(i))];
+    }
+    // zeroth and first moments from sums and differences of opposite pairs
+    R phi = h[0], j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (opposite<Q>(i) < i) continue;
+        const int o = opposite<Q>(i);
+        const R df = h[i] - h[o];
+        phi += h[i] + h[o];
+        if (vel<Q>(i, 0)) j[0] += R(vel<Q>(i, 0)) * df;
+        if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
+        if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
+    }
+
+    // interface normal from the isotropic gradient of phi^n
+    R gr[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int k = 1; k < 27; ++k) {
+        const R v = R(weight<27>(k)) * pn[k];
+        gr[0] += R(vel27(k, 0)) * v;
+        gr[1] += R(vel27(k, 1)) * v;
+        gr[2] += R(vel27(k, 2)) * v;
+    }
+    gr[0] *= R(3);
+    gr[1] *= R(3);
+    gr[2] *= R(3);
+    const R inv = R(1) / sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + R(a.eps2));
+    const R lam = R(4) * phi * (R(1) - phi) * R(a.inv_xi);
+    const R F[3] = {lam * gr[0] * inv, lam * gr[1] * inv, lam * gr[2] * inv};
+
+    R u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
+
+    // relaxed first-order central moment of h - h_eq + S/2
+    const R om1 = R(1) - R(a.omega_phi);
+    const R sixth = R(1.0 / 6.0);
+    const R v[3] = {om1 * (j[0] - phi * u[0] + sixth * F[0]), om1 * (j[1] - phi * u[1] + sixth * F[1]),
+                    om1 * (j[2] - phi * u[2] + sixth * F[2])};
+    R d[Q];
+    FirstOrder<Q, R>::apply(u, v, d);
+
+    // h* = w (phi (1 + zeta) + e.F / 2) + d, zeta the velocity part of h_eq / (w phi)
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    P *hd = static_cast<P *>(a.h_dst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        const R w = R(weight<Q>(i));
+        const R eu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
+        const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
+        const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
+        const R rest = dev ? phi * zeta : phi * (R(1) + zeta); // minus w phi when stored as a deviation
+        st_pdf(elem(pdf_row<Q>(hd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * (rest + R(0.5) * eF) + d[i]);
+    }
+    st(elem(static_cast<S *>(a.phi_new), nb.c), phi);
+    return phi;
+}
+
+} // namespace tcp

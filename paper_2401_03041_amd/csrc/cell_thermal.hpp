@@ -1,0 +1,78 @@
+// cell_thermal.hpp -- K3, passive-scalar LB (Eq. lb_thermal): pull with
+// anti-bounce-back f_i = -f*_opp + 2 w_i T_w at the y walls, T = sum_i f_i,
+// central-moment collision about u^{n+1} with the first-order moments relaxed
+// by omega_T = 1/(1/2 + kappa(phi)/c_s^2) and all higher ones with rate one,
+// then the source w_i q_T (Eq. HeatSource).  Storage in type P: f_i - w_i t_shift,
+// or (FP16) the deviation f*_i - w_i T(x) from the rest equilibrium of the
+// cell, the pull adding w_i T^n of the source cell back.  T is double
+// buffered (T^n read, T^{n+1} written).
+#pragma once
+
+#include "kernels.hpp"
+
+namespace tcp {
+
+// Update of one cell at (x, y, z) given the cell's phi^{n+1} and u^{n+1}.
+template <int Q, typename P, typename S, typename R, bool WALL>
+__device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb, int x, int y, int z, R phi,
+                                             const R (&u)[3])
+{
+    constexpr bool dev = deviation_storage<P>();
+    const P *fs = static_cast<const P *>(a.f_src);
+    const PdfLanes<Q> pl(nb);
+    const S *to = static_cast<const S *>(a.T_old);
+    // stored value = f - w ts (constant shift) or f - w T^n(source) (deviation)
+    const R ts = dev ? R(0) : R(a.t_shift);
+    const R t_own = dev ? ld<R>(elem(to, nb.c)) : R(0);
+
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        const R w = R(weight<Q>(i));
+        if (WALL && nb.ghost(-ey)) {
+            // anti-bounce-back f_i = 2 w T_w - f*_opp(x); f[] holds f - w ts
+            const double *tw = ey > 0 ? a.twb : a.twt;
+            f[i] = R(2) * w * R(tw[nb.col(0, 0, a.geo)]) -
+                   ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1])) -
+                   w * (dev ? t_own : R(2) * ts);
+        } else {
+            f[i] = ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+            if constexpr (dev) f[i] += w * (i == 0 ? t_own : ld<R>(elem(to, nb.at(-ex, -ey, -ez))));
+        }
+    }
+    // zeroth and first moments from sums and differences of opposite pairs
+    R Tp = f[0], j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+        if (opposite<Q>(i) < i) continue;
+        const int o = opposite<Q>(i);
+        const R df = f[i] - f[o];
+        Tp += f[i] + f[o];
+        if (vel<Q>(i, 0)) j[0] += R(vel<Q>(i, 0)) * df;
+        if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
+        if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
+    }
+    const R T = Tp + ts;
+    const R phic = fmin(fmax(phi, R(0)), R(1));
+    const R kap = R(a.kappa_l) + phic * R(a.dkappa);
+    const R om1 = R(1) - R(1) / (R(0.5) + R(3) * kap);
+    const R v[3] = {om1 * (j[0] - T * u[0]), om1 * (j[1] - T * u[1]), om1 * (j[2] - T * u[2])};
+    R d[Q];
+    FirstOrder<Q, R>::apply(u, v, d);
+    const R q = heat_source<R>(a.src, x, y, z);
+    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    P *fd = static_cast<P *>(a.f_dst);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const R w = R(weight<Q>(i));
+        const R eu = R(vel<Q>(i, 0)) * u[0] + R(vel<Q>(i, 1)) * u[1] + R(vel<Q>(i, 2)) * u[2];
+        const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
+        // f* - w ts = w (T (1 + zeta) - ts) + d + w q;  f* - w T = w T zeta + d + w q
+        const R rest = dev ? T * zeta : Tp * (R(1) + zeta) + ts * zeta;
+        st_pdf(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * rest + d[i] + w * q);
+    }
+    st(elem(static_cast<S *>(a.T), nb.c), T);
+}
+
+} // namespace tcp

@@ -95,6 +95,15 @@ void launch_thermal(const ThermalArgs &a, hipStream_t s);
 template <typename S, typename R>
 void launch_rk(const RkArgs &a, hipStream_t s);
 
+// K1 + K2 + K3 (thermal LB) of one step fused into one kernel (kernels_step.hip)
+struct StepArgs {
+    PfArgs pf;
+    HydroArgs hy;
+    ThermalArgs th;
+};
+template <int QH, int QF, typename P, typename S, typename R>
+void launch_step(const StepArgs &a, hipStream_t s);
+
 // ---- set-up, read-back and diagnostics (kernels_aux.hip) -------------------
 struct Droplets {
     int n;

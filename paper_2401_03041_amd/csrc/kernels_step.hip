@@ -1,0 +1,81 @@
+// kernels_step.hip -- one coupled time step with the thermal LB as a single
+// kernel: K1 (phase field), K2 (hydrodynamics) and K3 (thermal LB) of one cell
+// run back to back in one thread, in the order of Algorithm 1.
+//
+// This is the same update as the three kernels of their own, arithmetic
+// included.  It is legal because, with the time levels used here, no thread
+// reads what another thread of the same step writes: K1 and K2 read phi^n, T^n
+// and the PDFs of step n, which live in buffers apart from the ones written
+// (phi^{n+1}, T^{n+1}, the new PDFs); the velocity is read (u^n by K1) and then
+// written (u^{n+1} by K2) only at the thread's own cell; and K3 needs
+// phi^{n+1} and u^{n+1} only at its own cell, where this thread has just
+// computed them.  Fusing saves the second HBM read of the phi^n stencil (K2
+// finds it in the caches), the re-reads of u and phi^{n+1} by K3 (field
+// traffic 10 instead of 15 values per cell) and two launches per step.
+#include "cell_hydro.hpp"
+#include "cell_pf.hpp"
+#include "cell_thermal.hpp"
+
+namespace tcp {
+
+// A copy of the neighbour offsets that the compiler cannot prove equal to the
+// original: otherwise it keeps the 26 neighbour offsets (and the PDF lane
+// offsets) the phases have in common live from the first phase to the last.
+__device__ __forceinline__ Nbr opaque(const Nbr &nb)
+{
+    Nbr o = nb;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(o.xo[k]));
+    return o;
+}
+
+template <int QH, int QF, typename P, typename S, typename R, bool WALL>
+__device__ __forceinline__ void step_cell(const StepArgs &a, const Nbr &nb, int x, int y, int z)
+{
+    const R phi_new = phase_field_cell<QH, P, S, R, WALL>(a.pf, opaque(nb));
+    // keep the phases apart: hoisting one phase's loads into the previous one
+    // holds both phases' PDFs in registers at once and costs occupancy
+    __builtin_amdgcn_sched_barrier(0);
+    R u[3];
+    hydro_cell<S, R, WALL>(a.hy, opaque(nb), u);
+    __builtin_amdgcn_sched_barrier(0);
+    thermal_cell<QF, P, S, R, WALL>(a.th, opaque(nb), x, y, z, phi_new, u);
+}
+
+// FP64 needs 174 registers per lane; capping it at 168 lets three wavefronts
+// share a SIMD instead of two, at the cost of a few spills (measured 4 % faster).
+template <int QH, int QF, typename P, typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1)))
+k_step(const StepArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.pf.geo, x, y, z)) return;
+    const Nbr nb(a.pf.geo, x, y, z);
+    if (nb.below || nb.above)
+        step_cell<QH, QF, P, S, R, true>(a, nb, x, y, z);
+    else
+        step_cell<QH, QF, P, S, R, false>(a, nb, x, y, z);
+}
+
+template <int QH, int QF, typename P, typename S, typename R>
+void launch_step(const StepArgs &a, hipStream_t s)
+{
+    const Tiling t = make_tiling(a.pf.geo);
+    hipLaunchKernelGGL((k_step<QH, QF, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+}
+
+#define TCP_STEP_INST(QH, QF)                                                                                \
+    template void launch_step<QH, QF, double, double, double>(const StepArgs &, hipStream_t);              \
+    template void launch_step<QH, QF, float, float, float>(const StepArgs &, hipStream_t);                 \
+    template void launch_step<QH, QF, _Float16, float, float>(const StepArgs &, hipStream_t);
+TCP_STEP_INST(15, 7)
+TCP_STEP_INST(15, 15)
+TCP_STEP_INST(15, 19)
+TCP_STEP_INST(15, 27)
+TCP_STEP_INST(27, 7)
+TCP_STEP_INST(27, 15)
+TCP_STEP_INST(27, 19)
+TCP_STEP_INST(27, 27)
+#undef TCP_STEP_INST
+
+} // namespace tcp

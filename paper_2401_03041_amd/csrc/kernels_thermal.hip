@@ -14,73 +14,9 @@
 //              + kappa(phi) lap theta + q_T
 // with the isotropic D3Q27 stencils, ghost 2 T_w - theta at walls and the
 // mirror ghost for phi.
-#include "kernels.hpp"
+#include "cell_thermal.hpp"
 
 namespace tcp {
-
-template <int Q, typename P, typename S, typename R, bool WALL>
-__device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb, int x, int y, int z)
-{
-    constexpr bool dev = deviation_storage<P>();
-    const P *fs = static_cast<const P *>(a.f_src);
-    const PdfLanes<Q> pl(nb);
-    const S *to = static_cast<const S *>(a.T_old);
-    // stored value = f - w ts (constant shift) or f - w T^n(source) (deviation)
-    const R ts = dev ? R(0) : R(a.t_shift);
-    const R t_own = dev ? ld<R>(elem(to, nb.c)) : R(0);
-
-    R f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
-        const R w = R(weight<Q>(i));
-        if (WALL && nb.ghost(-ey)) {
-            // anti-bounce-back f_i = 2 w T_w - f*_opp(x); f[] holds f - w ts
-            const double *tw = ey > 0 ? a.twb : a.twt;
-            f[i] = R(2) * w * R(tw[nb.col(0, 0, a.geo)]) -
-                   ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1])) -
-                   w * (dev ? t_own : R(2) * ts);
-        } else {
-            f[i] = ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
-            if constexpr (dev) f[i] += w * (i == 0 ? t_own : ld<R>(elem(to, nb.at(-ex, -ey, -ez))));
-        }
-    }
-    // zeroth and first moments from sums and differences of opposite pairs
-    R Tp = f[0], j[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        if (opposite<Q>(i) < i) continue;
-        const int o = opposite<Q>(i);
-        const R df = f[i] - f[o];
-        Tp += f[i] + f[o];
-        if (vel<Q>(i, 0)) j[0] += R(vel<Q>(i, 0)) * df;
-        if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
-        if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
-    }
-    const R T = Tp + ts;
-    R u[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
-    const R phic = fmin(fmax(ld<R>(elem(static_cast<const S *>(a.phi), nb.c)), R(0)), R(1));
-    const R kap = R(a.kappa_l) + phic * R(a.dkappa);
-    const R om1 = R(1) - R(1) / (R(0.5) + R(3) * kap);
-    const R v[3] = {om1 * (j[0] - T * u[0]), om1 * (j[1] - T * u[1]), om1 * (j[2] - T * u[2])};
-    R d[Q];
-    FirstOrder<Q, R>::apply(u, v, d);
-    const R q = heat_source<R>(a.src, x, y, z);
-    const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-    P *fd = static_cast<P *>(a.f_dst);
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const R w = R(weight<Q>(i));
-        const R eu = R(vel<Q>(i, 0)) * u[0] + R(vel<Q>(i, 1)) * u[1] + R(vel<Q>(i, 2)) * u[2];
-        const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
-        // f* - w ts = w (T (1 + zeta) - ts) + d + w q;  f* - w T = w T zeta + d + w q
-        const R rest = dev ? T * zeta : Tp * (R(1) + zeta) + ts * zeta;
-        st_pdf(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * rest + d[i] + w * q);
-    }
-    st(elem(static_cast<S *>(a.T), nb.c), T);
-}
 
 // One thread per cell; rows next to a wall take the anti-bounce-back path.
 template <int Q, typename P, typename S, typename R>
@@ -89,10 +25,14 @@ __global__ void __launch_bounds__(kTX *kTY) k_thermal(const ThermalArgs a, const
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
     const Nbr nb(a.geo, x, y, z);
+    const R phi = ld<R>(elem(static_cast<const S *>(a.phi), nb.c));
+    R u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
     if (nb.below || nb.above)
-        thermal_cell<Q, P, S, R, true>(a, nb, x, y, z);
+        thermal_cell<Q, P, S, R, true>(a, nb, x, y, z, phi, u);
     else
-        thermal_cell<Q, P, S, R, false>(a, nb, x, y, z);
+        thermal_cell<Q, P, S, R, false>(a, nb, x, y, z, phi, u);
 }
 
 template <int Q, typename P, typename S, typename R>

@@ -43,6 +43,7 @@ struct tcp_domain {
     // step graphs: kGraphSteps steps captured once per parity of `cur` and
     // replayed with one launch (graph_mode: 0 never, 1 small domains, 2 always)
     int graph_mode = 1;
+    bool fuse = true; // thermal LB: one fused kernel per step (tcp_set_fusion)
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2]{};
 
@@ -117,6 +118,9 @@ struct Scratch {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+constexpr size_t kArenaAlign = (size_t)2 << 20;
+constexpr size_t kArenaStagger = 0;
+
 // ---- timing ---------------------------------------------------------------
 struct KernelTimer {
     tcp_domain *d;
@@ -149,8 +153,7 @@ struct KernelTimer {
 };
 
 // ---- per-step schedule ------------------------------------------------------
-template <typename S, typename Pdf>
-void phase_step(tcp_domain *d)
+PfArgs pf_args(const tcp_domain *d)
 {
     PfArgs a{};
     a.geo = d->geo;
@@ -162,13 +165,19 @@ void phase_step(tcp_domain *d)
     a.omega_phi = d->omega_phi;
     a.inv_xi = 1.0 / d->P.xi;
     a.eps2 = d->P.normal_eps * d->P.normal_eps;
+    return a;
+}
+
+template <typename S, typename Pdf>
+void phase_step(tcp_domain *d)
+{
+    const PfArgs a = pf_args(d);
     KernelTimer t(d, TCP_K_PHASE);
     if (d->P.q_pf == 15) launch_pf<15, Pdf, S, S>(a, d->stream);
     else launch_pf<27, Pdf, S, S>(a, d->stream);
 }
 
-template <typename S>
-void hydro_step(tcp_domain *d)
+HydroArgs hydro_args(const tcp_domain *d)
 {
     const tcp_params &P = d->P;
     HydroArgs a{};
@@ -194,8 +203,35 @@ void hydro_step(tcp_domain *d)
         a.uw_top[k] = P.u_wall_top[k];
     }
     a.omega_bulk = P.omega_bulk;
+    return a;
+}
+
+template <typename S>
+void hydro_step(tcp_domain *d)
+{
+    const HydroArgs a = hydro_args(d);
     KernelTimer t(d, TCP_K_HYDRO);
     launch_hydro<S, S>(a, d->stream);
+}
+
+ThermalArgs thermal_args(const tcp_domain *d)
+{
+    const tcp_params &P = d->P;
+    ThermalArgs a{};
+    a.geo = d->geo;
+    a.f_src = d->f[d->cur];
+    a.f_dst = d->f[1 - d->cur];
+    a.phi = d->phi[1 - d->cur];
+    for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+    a.T_old = d->T[d->cur];
+    a.T = d->T[1 - d->cur];
+    a.twb = d->twb;
+    a.twt = d->twt;
+    a.kappa_l = P.kappa_l;
+    a.dkappa = P.kappa_h - P.kappa_l;
+    a.t_shift = P.t_shift;
+    a.src = d->src;
+    return a;
 }
 
 template <typename S, typename Pdf>
@@ -203,20 +239,7 @@ void thermal_step(tcp_domain *d)
 {
     const tcp_params &P = d->P;
     if (P.thermal == TCP_THERMAL_LB) {
-        ThermalArgs a{};
-        a.geo = d->geo;
-        a.f_src = d->f[d->cur];
-        a.f_dst = d->f[1 - d->cur];
-        a.phi = d->phi[1 - d->cur];
-        for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
-        a.T_old = d->T[d->cur];
-        a.T = d->T[1 - d->cur];
-        a.twb = d->twb;
-        a.twt = d->twt;
-        a.kappa_l = P.kappa_l;
-        a.dkappa = P.kappa_h - P.kappa_l;
-        a.t_shift = P.t_shift;
-        a.src = d->src;
+        const ThermalArgs a = thermal_args(d);
         KernelTimer t(d, TCP_K_THERMAL);
         switch (P.q_thermal) {
         case 7: launch_thermal<7, Pdf, S, S>(a, d->stream); break;
@@ -276,14 +299,39 @@ void thermal_step(tcp_domain *d)
     }
 }
 
+// K1 + K2 + K3 (thermal LB) in one kernel
+template <int QH, typename S, typename Pdf>
+void fused_step_q(tcp_domain *d, const StepArgs &a)
+{
+    switch (d->P.q_thermal) {
+    case 7: launch_step<QH, 7, Pdf, S, S>(a, d->stream); break;
+    case 15: launch_step<QH, 15, Pdf, S, S>(a, d->stream); break;
+    case 19: launch_step<QH, 19, Pdf, S, S>(a, d->stream); break;
+    default: launch_step<QH, 27, Pdf, S, S>(a, d->stream); break;
+    }
+}
+
+template <typename S, typename Pdf>
+void fused_step(tcp_domain *d)
+{
+    const StepArgs a{pf_args(d), hydro_args(d), thermal_args(d)};
+    KernelTimer t(d, TCP_K_STEP);
+    if (d->P.q_pf == 15) fused_step_q<15, S, Pdf>(d, a);
+    else fused_step_q<27, S, Pdf>(d, a);
+}
+
 // S: hydrodynamic PDFs and fields (also the arithmetic type); Pdf: phase-field
 // and thermal PDFs
 template <typename S, typename Pdf>
 void one_step(tcp_domain *d)
 {
-    phase_step<S, Pdf>(d);
-    hydro_step<S>(d);
-    thermal_step<S, Pdf>(d);
+    if (d->fuse && d->P.thermal == TCP_THERMAL_LB) {
+        fused_step<S, Pdf>(d);
+    } else {
+        phase_step<S, Pdf>(d);
+        hydro_step<S>(d);
+        thermal_step<S, Pdf>(d);
+    }
     d->cur = 1 - d->cur;
 }
 
@@ -498,22 +546,41 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
     d->tau_h = 3.0 * p->nu_h;
     d->tau_l = 3.0 * p->nu_l;
     const size_t N = (size_t)d->geo.N, sb = d->sb, pb = d->pb;
-    bool ok = true;
-    for (int b = 0; b < 2; ++b) {
-        ok = ok && (d->h[b] = own(d, (size_t)pdf_elems(d->geo, p->q_pf) * pb));
-        ok = ok && (d->g[b] = own(d, (size_t)pdf_elems(d->geo, 27) * sb));
-        if (p->thermal == TCP_THERMAL_LB) ok = ok && (d->f[b] = own(d, (size_t)pdf_elems(d->geo, p->q_thermal) * pb));
-        ok = ok && (d->phi[b] = own(d, N * sb));
-        ok = ok && (d->T[b] = own(d, N * sb));
-    }
-    for (int k = 0; k < 3; ++k) ok = ok && (d->u[k] = own(d, N * sb));
-    if (p->thermal != TCP_THERMAL_LB)
-        for (int k = 0; k < (p->thermal == TCP_THERMAL_RK2 ? 1 : 3); ++k) ok = ok && (d->rk[k] = own(d, N * sb));
     const size_t ncol = (size_t)p->nx * p->nz;
-    ok = ok && (d->twb = static_cast<double *>(own(d, ncol * sizeof(double))));
-    ok = ok && (d->twt = static_cast<double *>(own(d, ncol * sizeof(double))));
-    ok = ok && (d->partial = static_cast<double *>(own(d, 4 * kReduceBlocks * sizeof(double))));
-    ok = ok && (d->out4 = static_cast<double *>(own(d, 4 * sizeof(double))));
+    // All device state lives in one allocation, every buffer starting on a
+    // kArenaAlign boundary (plus kArenaStagger bytes per buffer index).
+    std::vector<std::pair<void **, size_t>> req;
+    for (int b = 0; b < 2; ++b) {
+        req.push_back({&d->h[b], (size_t)pdf_elems(d->geo, p->q_pf) * pb});
+        req.push_back({&d->g[b], (size_t)pdf_elems(d->geo, 27) * sb});
+        if (p->thermal == TCP_THERMAL_LB) req.push_back({&d->f[b], (size_t)pdf_elems(d->geo, p->q_thermal) * pb});
+        req.push_back({&d->phi[b], N * sb});
+        req.push_back({&d->T[b], N * sb});
+    }
+    for (int k = 0; k < 3; ++k) req.push_back({&d->u[k], N * sb});
+    if (p->thermal != TCP_THERMAL_LB)
+        for (int k = 0; k < (p->thermal == TCP_THERMAL_RK2 ? 1 : 3); ++k) req.push_back({&d->rk[k], N * sb});
+    void *twb = nullptr, *twt = nullptr, *partial = nullptr, *out4 = nullptr;
+    req.push_back({&twb, ncol * sizeof(double)});
+    req.push_back({&twt, ncol * sizeof(double)});
+    req.push_back({&partial, 4 * kReduceBlocks * sizeof(double)});
+    req.push_back({&out4, 4 * sizeof(double)});
+    size_t total = 0;
+    std::vector<size_t> offset;
+    for (size_t k = 0; k < req.size(); ++k) {
+        offset.push_back(total + k * kArenaStagger);
+        total += (req[k].second + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+    }
+    total += req.size() * kArenaStagger;
+    char *arena = static_cast<char *>(own(d, total));
+    bool ok = arena != nullptr;
+    if (ok) {
+        for (size_t k = 0; k < req.size(); ++k) *req[k].first = arena + offset[k];
+        d->twb = static_cast<double *>(twb);
+        d->twt = static_cast<double *>(twt);
+        d->partial = static_cast<double *>(partial);
+        d->out4 = static_cast<double *>(out4);
+    }
     if (!ok) {
         tcp_destroy(d);
         return fail(nullptr, TCP_ERR_OOM, "device allocation failed");
@@ -826,6 +893,14 @@ int tcp_set_profiling(tcp_domain *d, int enabled)
     return TCP_OK;
 }
 
+int tcp_set_fusion(tcp_domain *d, int enabled)
+{
+    if (!d) return TCP_ERR_ARG;
+    d->fuse = enabled != 0;
+    drop_graphs(d); // captured steps hold the launch sequence
+    return TCP_OK;
+}
+
 int tcp_set_graphs(tcp_domain *d, int mode)
 {
     if (!d) return TCP_ERR_ARG;
@@ -864,6 +939,10 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     // f in/out, u and phi^{n+1} in, T out; FP16 deviation storage also reads T^n
     b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * pb + (d->pb == 2 ? 6.0 : 5.0) * sb : 0.0;
     b[TCP_K_RK] = d->P.thermal == TCP_THERMAL_RK2 ? 13.0 * sb : (d->P.thermal == TCP_THERMAL_RK4 ? 33.0 * sb : 0.0);
+    // fused step: all PDFs in/out; phi^n, T^n, u^n in; phi^{n+1}, u^{n+1}, T^{n+1} out
+    b[TCP_K_STEP] = d->P.thermal == TCP_THERMAL_LB
+                        ? 2.0 * (d->P.q_pf + d->P.q_thermal) * pb + 54.0 * sb + 10.0 * sb
+                        : 0.0;
     return TCP_OK;
 }
 

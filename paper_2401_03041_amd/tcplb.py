@@ -20,14 +20,14 @@ FIELDS = {"phi": PHI, "ux": UX, "uy": UY, "uz": UZ, "T": T, "p": P, "pstar": PST
 PDFS = {"h": 0, "g": 1, "f": 2}
 THERMAL = {"lb": 0, "rk2": 1, "rk4": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
-KERNELS = ("phase", "hydro", "thermal", "rk")
+KERNELS = ("phase", "hydro", "thermal", "rk", "step")
 
 # names of every entry point the header declares
 EXPORTS = (
     "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_droplets",
     "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_get_field",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
-    "tcp_set_profiling", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
+    "tcp_set_profiling", "tcp_set_fusion", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
     "tcp_last_error",
 )
 
@@ -102,6 +102,7 @@ def load() -> C.CDLL:
         "tcp_synchronize": [vp],
         "tcp_set_profiling": [vp, C.c_int],
         "tcp_set_graphs": [vp, C.c_int],
+        "tcp_set_fusion": [vp, C.c_int],
         "tcp_kernel_times": [vp, dp, C.POINTER(i64)],
         "tcp_algorithmic_bytes": [vp, dp],
         "tcp_bandwidth_probe": [C.c_size_t, C.c_int, dp],
@@ -301,18 +302,22 @@ class Domain:
     def set_profiling(self, on: bool) -> None:
         self._check(self._lib.tcp_set_profiling(self._h, int(bool(on))), "set_profiling")
 
+    def set_fusion(self, on: bool) -> None:
+        """Thermal LB: one fused kernel per step (default) or the three kernels."""
+        self._check(self._lib.tcp_set_fusion(self._h, int(bool(on))), "set_fusion")
+
     def set_graphs(self, mode: int) -> None:
         """Step graphs: 0 never, 1 grids up to 2^21 cells (default), 2 always."""
         self._check(self._lib.tcp_set_graphs(self._h, int(mode)), "set_graphs")
 
     def kernel_times(self) -> dict:
-        ms = np.zeros(4)
-        n = (C.c_int64 * 4)()
+        ms = np.zeros(len(KERNELS))
+        n = (C.c_int64 * len(KERNELS))()
         self._check(self._lib.tcp_kernel_times(self._h, _dptr(ms), n), "kernel_times")
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(KERNELS)}
 
     def algorithmic_bytes(self) -> dict:
-        b = np.zeros(4)
+        b = np.zeros(len(KERNELS))
         self._check(self._lib.tcp_algorithmic_bytes(self._h, _dptr(b)), "algorithmic_bytes")
         return {k: float(b[i]) for i, k in enumerate(KERNELS)}
 

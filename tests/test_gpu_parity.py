@@ -181,6 +181,33 @@ def test_graph_replay_matches_eager(precision, thermal):
         assert np.array_equal(a[k], b[k]), ("new sources", k)
 
 
+@pytest.mark.parametrize("precision,q_pf,q_th", [("fp64", 15, 7), ("fp32", 27, 19), ("fp16", 15, 15),
+                                                 ("fp64", 27, 27)])
+def test_fused_step_matches_three_kernels(precision, q_pf, q_th):
+    """With the thermal LB a step runs as one fused kernel; it must agree with the
+    three kernels of their own (same arithmetic, no intra-step dependence
+    between threads; the compiler may round single operations differently in
+    the two kernels, which was measured at one unit in the last place after a
+    step), walls, moving lid and heater included."""
+    cfg = W.make(shape=(70, 22, 14), periodic_y=False, precision=precision, q_pf=q_pf, q_thermal=q_th,
+                 rho_h=1.0, rho_l=0.2, nu_h=0.15, nu_l=0.05, mobility=0.04, xi=4.0, sigma_ref=3e-3,
+                 sigma_t=-4e-4, t_ref=0.5, kappa_h=0.25, kappa_l=0.15, u_wall_top=(0.01, 0.0, 0.003),
+                 t_wall_bot=0.2, t_wall_top=1.0, droplets=[(30.3, 6.7, 4.1, 4.5), (52.4, 15.2, 9.6, 3.5)],
+                 heat_sources=[(0.02, 40.0, -0.5, 4.5, 6.0, 0.0)], t_init={"kind": "conduction"})
+    fused, split = gpu_domain(cfg), gpu_domain(cfg)
+    split.set_fusion(False)
+    tol = {"fp64": TOL64, "fp32": TOL32, "fp16": 1e-3}[precision]
+    for n in (1, 16, 23):
+        fused.step(n)
+        split.step(n)
+        errs = compare(fused, split, floor=1e-6)  # p starts at zero: compare against the 1e-6 scale
+        print(precision, q_pf, q_th, n, errs)
+        _report(errs, tol)
+    for which in ("h", "g", "f"):
+        a, b = fused.get_pdfs(which), split.get_pdfs(which)
+        assert np.max(np.abs(a - b)) <= tol * np.max(np.abs(b)), which
+
+
 def test_reduction_matches_host_sum():
     """FP64 mass and centroid against a host sum of the read-back phase field."""
     cfg = W.droplet_block(n=64, ndrop=4, radius=(6.0, 9.0), sigma_range=(6.0, 12.0), precision="fp32")
