@@ -72,7 +72,7 @@ def load() -> C.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+        raise ImportError(f"{LIB_PATH} is missing: build it with python paper_2401_03041_amd/csrc/build.py "
                           "(there is no CPU fallback)")
     # One process must hold one HIP runtime.  PyTorch ships its own libamdhip64
     # with the same soname as the system one; loading torch first makes the
