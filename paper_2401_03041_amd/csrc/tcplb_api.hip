@@ -80,7 +80,10 @@ void *dev_alloc(tcp_domain *d, size_t bytes)
     if (bytes == 0) bytes = 256;
     void *p = nullptr;
     if (d->own_alloc) {
-        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            (void)hipGetLastError(); // do not leave the failure for a later launch check to find
+            return nullptr;
+        }
     } else {
         p = d->A.alloc(bytes, d->A.ctx);
     }

@@ -83,6 +83,26 @@ def test_rk_stability_bound_rejected_without_gpu():
     assert lib.tcp_create(C.byref(p), None, None, C.byref(h)) == -1
 
 
+@pytest.mark.parametrize("shape,precision,expect", [
+    ((1024, 1024, 1024), 1, -2),   # one FP32 field of exactly 4 GiB: beyond 32-bit field offsets
+    ((1024, 1024, 512), 0, -2),    # FP64, 4 GiB
+    ((0, 8, 8), 1, -1),            # empty grid
+    ((8, 1, 8), 1, -1)])           # walls need two rows
+def test_grid_limits_rejected_without_gpu(shape, precision, expect):
+    """Grids whose field arrays reach 4 GiB are refused (TCP_ERR_UNSUPPORTED)
+    before any device work, as are empty grids (TCP_ERR_ARG)."""
+    from paper_2401_03041_amd import tcplb
+    lib = tcplb.load()
+    p = tcplb.Params()
+    lib.tcp_params_default(C.byref(p))
+    p.nx, p.ny, p.nz = shape
+    p.precision = precision
+    p.walls_y = 1
+    h = C.c_void_p()
+    assert lib.tcp_create(C.byref(p), None, None, C.byref(h)) == expect
+    assert not h.value
+
+
 def test_error_strings():
     from paper_2401_03041_amd import tcplb
     lib = tcplb.load()

@@ -220,6 +220,19 @@ def test_reduction_matches_host_sum():
     assert np.allclose(c, [(phi * x).sum() / m, (phi * y).sum() / m, (phi * z).sum() / m], rtol=1e-12)
 
 
+@pytest.mark.parametrize("use_torch", [True, False])
+def test_out_of_device_memory_reported(use_torch):
+    """A valid grid whose state does not fit in HBM (1024 x 1024 x 511 in FP64,
+    about 460 GB) is refused with TCP_ERR_OOM, and the GPU stays usable."""
+    from paper_2401_03041_amd import tcplb
+    cfg = W.make(shape=(1024, 1024, 511), precision="fp64")
+    with pytest.raises(tcplb.TcpError, match="device allocation failed"):
+        tcplb.Domain(cfg, use_torch=use_torch)
+    g = gpu_domain(W.static_droplet(16))
+    g.step(3)
+    assert np.isfinite(g.get_field("phi")).all()
+
+
 def test_nonfinite_detected():
     """NaN injected into phi from the host is reported by the reduction."""
     from paper_2401_03041_amd.tcplb import TcpError
