@@ -74,9 +74,8 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
         const R w = R(weight<27>(i));
-        const uint32_t at = nb.at(ex, ey, ez);
-        const R pv = ld<R>(elem(pp, at));
-        R tv = ld<R>(elem(tp, at));
+        const R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+        R tv = ld<R>(nb.ptr(tp, ex, ey, ez));
         if (WALL && nb.ghost(ey)) {
             const double *tw = ey < 0 ? a.twb : a.twt;
             tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;

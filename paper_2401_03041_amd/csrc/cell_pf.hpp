@@ -31,7 +31,7 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
     const S *po = static_cast<const S *>(a.phi_old);
     R pn[27];
 #pragma unroll
-    for (int k = dev ? 0 : 1; k < 27; ++k) pn[k] = ld<R>(elem(po, nb.at(vel27(k, 0), vel27(k, 1), vel27(k, 2))));
+    for (int k = dev ? 0 : 1; k < 27; ++k) pn[k] = ld<R>(nb.ptr(po, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
 
     // pull; a link that crosses a wall returns the cell's own opposite PDF
     R h[Q];

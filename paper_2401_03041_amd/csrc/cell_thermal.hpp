@@ -38,7 +38,7 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
                    w * (dev ? t_own : R(2) * ts);
         } else {
             f[i] = ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
-            if constexpr (dev) f[i] += w * (i == 0 ? t_own : ld<R>(elem(to, nb.at(-ex, -ey, -ez))));
+            if constexpr (dev) f[i] += w * (i == 0 ? t_own : ld<R>(nb.ptr(to, -ex, -ey, -ez)));
         }
     }
     // zeroth and first moments from sums and differences of opposite pairs

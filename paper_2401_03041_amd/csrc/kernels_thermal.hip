@@ -53,13 +53,12 @@ __device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb, int x, i
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
         const R w = R(weight<27>(i));
-        const uint32_t at = nb.at(ex, ey, ez);
-        R tv = ld<R>(elem(th, at));
+        R tv = ld<R>(nb.ptr(th, ex, ey, ez));
         if (WALL && nb.ghost(ey)) {
             const double *tw = ey < 0 ? a.twb : a.twt;
             tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;
         }
-        const R pv = ld<R>(elem(pp, at));
+        const R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
         gt[0] += R(ex) * w * tv;
         gt[1] += R(ey) * w * tv;
         gt[2] += R(ez) * w * tv;

@@ -148,6 +148,14 @@ struct Nbr {
     {
         return xo[dx + 1] + yo[dy + 1] + zo[dz + 1];
     }
+    // element of a field at offset (dx, dy, dz): a wave-uniform row pointer
+    // (y and z are the same across a wavefront) plus one of the three per-lane
+    // x offsets, so a 27-point stencil costs no per-lane address arithmetic
+    template <typename T>
+    __device__ __forceinline__ T *ptr(T *base, int dx, int dy, int dz) const
+    {
+        return elem(base + (yo[dy + 1] + zo[dz + 1]), xo[dx + 1]);
+    }
     // true when the offset dy leaves the fluid through a wall
     __device__ __forceinline__ bool ghost(int dy) const
     {
