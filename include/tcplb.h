@@ -64,9 +64,10 @@ enum { TCP_THERMAL_LB = 0, TCP_THERMAL_RK2 = 1, TCP_THERMAL_RK4 = 2 };
  *  TCP_FP64  all PDFs and fields FP64, FP64 arithmetic;
  *  TCP_FP32  all PDFs and fields FP32, FP32 arithmetic;
  *  TCP_FP16  phase-field and thermal PDFs FP16, hydrodynamic PDFs and all
- *            fields FP32, FP32 arithmetic.  Each FP16 PDF holds its deviation
- *            from the rest equilibrium of its own cell, h_i - w_i phi and
- *            f_i - w_i T (t_shift is not used).
+ *            fields FP32, FP32 arithmetic.
+ * In FP32 and FP16 each phase-field and thermal PDF holds its deviation from
+ * the rest equilibrium of its own cell, h_i - w_i phi and f_i - w_i T
+ * (t_shift is used in FP64 only).
  * Reductions and read-back are FP64 in every mode. */
 enum { TCP_FP64 = 0, TCP_FP32 = 1, TCP_FP16 = 2 };
 
@@ -121,7 +122,7 @@ typedef struct {
     double u_wall_top[3];
     double t_wall_bot;      /* uniform wall temperatures; tcp_set_wall_temperature */
     double t_wall_top;      /*   overrides them with per-column values */
-    double t_shift;         /* FP64/FP32: thermal PDFs are stored as f_i - w_i t_shift */
+    double t_shift;         /* FP64: thermal PDFs are stored as f_i - w_i t_shift */
 } tcp_params;
 
 /* Fill *p with defaults: 32^3 periodic, D3Q15 phase field, D3Q7 thermal LB,

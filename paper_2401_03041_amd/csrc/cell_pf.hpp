@@ -9,10 +9,11 @@
 // h_eq + S/2 plus the inverse transform of the relaxed first-order moments
 // (FirstOrder<Q>), which is what the kernel evaluates.
 //
-// Storage in type P: unshifted, or (FP16) as the deviation h*_i - w_i phi(x)
-// from the rest equilibrium of the cell (deviation_storage).  The pull then
-// adds w_i phi^n of the source cell, which the kernel loads anyway for the
-// gradient of phi^n: phi^n(y) is the zeroth moment of the h* stored at y.
+// Storage in type P: as is (FP64), or (FP32, FP16) as the deviation
+// h*_i - w_i phi(x) from the rest equilibrium of the cell (deviation_storage);
+// the pull then works with h_i - w_i phi^n(own), rebuilt from the stored value
+// and phi^n of the source and own cells, which the kernel loads anyway for the
+// gradient of phi^n.
 #pragma once
 
 #include "kernels.hpp"
@@ -41,9 +42,15 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
         const bool wall = WALL && nb.ghost(-ey);
         h[i] = wall ? ld<R>(elem(pdf_row<Q>(hs, a.geo, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1]))
                     : ld<R>(elem(pdf_row<Q>(hs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
-        if constexpr (dev) h[i] += R(weight<Q>(i)) * pn[wall ? 0 : opposite<27>(index27<Q>(i))];
+        // deviation storage: h - w phi^n(own) = stored + w (phi^n(source) - phi^n(own)),
+        // which is exactly zero in a uniform region at rest
+        if constexpr (dev) {
+            if (!wall) h[i] += R(weight<Q>(i)) * (pn[opposite<27>(index27<Q>(i))] - pn[0]);
+        }
     }
     // zeroth and first moments from sums and differences of opposite pairs
+    // (with deviation storage h[] holds h - w phi^n(own): sum_i w_i = 1 adds
+    // phi^n(own) to the zeroth moment, sum_i w_i e_i = 0 leaves the first)
     R phi = h[0], j[3] = {R(0), R(0), R(0)};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
@@ -55,6 +62,7 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
         if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
         if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
     }
+    if constexpr (dev) phi += pn[0];
 
     // interface normal from the isotropic gradient of phi^n
     R gr[3] = {R(0), R(0), R(0)};

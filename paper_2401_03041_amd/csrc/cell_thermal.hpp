@@ -2,9 +2,9 @@
 // anti-bounce-back f_i = -f*_opp + 2 w_i T_w at the y walls, T = sum_i f_i,
 // central-moment collision about u^{n+1} with the first-order moments relaxed
 // by omega_T = 1/(1/2 + kappa(phi)/c_s^2) and all higher ones with rate one,
-// then the source w_i q_T (Eq. HeatSource).  Storage in type P: f_i - w_i t_shift,
-// or (FP16) the deviation f*_i - w_i T(x) from the rest equilibrium of the
-// cell, the pull adding w_i T^n of the source cell back.  T is double
+// then the source w_i q_T (Eq. HeatSource).  Storage in type P: f_i - w_i t_shift
+// (FP64), or (FP32, FP16) the deviation f*_i - w_i T(x) from the rest
+// equilibrium of the cell, rebuilt in the pull around T^n of the own cell.  T is double
 // buffered (T^n read, T^{n+1} written).
 #pragma once
 
@@ -21,24 +21,26 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
     const P *fs = static_cast<const P *>(a.f_src);
     const PdfLanes<Q> pl(nb);
     const S *to = static_cast<const S *>(a.T_old);
-    // stored value = f - w ts (constant shift) or f - w T^n(source) (deviation)
     const R ts = dev ? R(0) : R(a.t_shift);
     const R t_own = dev ? ld<R>(elem(to, nb.c)) : R(0);
 
+    // f[] holds f - w ts (constant shift) or f - w T^n(own) (deviation storage:
+    // stored + w (T^n(source) - T^n(own)), exactly zero in a uniform region at rest)
     R f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
         const R w = R(weight<Q>(i));
         if (WALL && nb.ghost(-ey)) {
-            // anti-bounce-back f_i = 2 w T_w - f*_opp(x); f[] holds f - w ts
+            // anti-bounce-back f_i = 2 w T_w - f*_opp(x)
             const double *tw = ey > 0 ? a.twb : a.twt;
-            f[i] = R(2) * w * R(tw[nb.col(0, 0, a.geo)]) -
-                   ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1])) -
-                   w * (dev ? t_own : R(2) * ts);
+            f[i] = R(2) * w * (R(tw[nb.col(0, 0, a.geo)]) - (dev ? t_own : ts)) -
+                   ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1]));
         } else {
             f[i] = ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
-            if constexpr (dev) f[i] += w * (i == 0 ? t_own : ld<R>(nb.ptr(to, -ex, -ey, -ez)));
+            if constexpr (dev) {
+                if (i != 0) f[i] += w * (ld<R>(nb.ptr(to, -ex, -ey, -ez)) - t_own);
+            }
         }
     }
     // zeroth and first moments from sums and differences of opposite pairs
@@ -53,7 +55,7 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
         if (vel<Q>(i, 1)) j[1] += R(vel<Q>(i, 1)) * df;
         if (vel<Q>(i, 2)) j[2] += R(vel<Q>(i, 2)) * df;
     }
-    const R T = Tp + ts;
+    const R T = Tp + (dev ? t_own : ts);
     const R phic = fmin(fmax(phi, R(0)), R(1));
     const R kap = R(a.kappa_l) + phic * R(a.dkappa);
     const R om1 = R(1) - R(1) / (R(0.5) + R(3) * kap);

@@ -4,9 +4,9 @@
 // f_i = -f*_opp + 2 w_i T_w at the y walls, T = sum_i f_i, central-moment
 // collision about u^{n+1} with the first-order moments relaxed by
 // omega_T = 1/(1/2 + kappa(phi)/c_s^2) and all higher ones with rate one, then
-// the source w_i q_T (Eq. HeatSource).  Storage in type P: f_i - w_i t_shift,
-// or (FP16) the deviation f*_i - w_i T(x) from the rest equilibrium of the
-// cell, the pull adding w_i T^n of the source cell back.  T is double
+// the source w_i q_T (Eq. HeatSource).  Storage in type P: f_i - w_i t_shift
+// (FP64), or (FP32, FP16) the deviation f*_i - w_i T(x) from the rest
+// equilibrium of the cell, rebuilt in the pull around T^n of the own cell.  T is double
 // buffered (T^n read, T^{n+1} written).
 //
 // RK stages (Eq. rk2 as the midpoint rule, Eq. rk4): each stage evaluates

@@ -796,11 +796,11 @@ int tcp_get_pdfs(tcp_domain *d, int which, double *host_out)
     int q = 0;
     size_t bytes = d->pb;
     double shift = 0.0;
-    const void *field = nullptr; // FP16 PDFs are stored relative to w_i phi(x) or w_i T(x)
+    const void *field = nullptr; // FP32/FP16 PDFs are stored relative to w_i phi(x) or w_i T(x)
     if (which == TCP_PDF_H) {
         src = d->h[d->cur];
         q = d->P.q_pf;
-        if (d->pb == 2) field = d->phi[d->cur];
+        if (d->pb <= 4) field = d->phi[d->cur];
     } else if (which == TCP_PDF_G) {
         src = d->g[d->cur];
         q = 27;
@@ -808,7 +808,7 @@ int tcp_get_pdfs(tcp_domain *d, int which, double *host_out)
     } else if (which == TCP_PDF_F && d->P.thermal == TCP_THERMAL_LB) {
         src = d->f[d->cur];
         q = d->P.q_thermal;
-        if (d->pb == 2) field = d->T[d->cur];
+        if (d->pb <= 4) field = d->T[d->cur];
         else shift = d->P.t_shift;
     } else {
         return fail(d, TCP_ERR_ARG, "unknown PDF field for this configuration");
@@ -939,8 +939,8 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     const double sb = (double)d->sb, pb = (double)d->pb;
     b[TCP_K_PHASE] = 2.0 * d->P.q_pf * pb + 5.0 * sb; // h in/out, phi^n in, phi^{n+1} out, u in
     b[TCP_K_HYDRO] = (54.0 + 5.0) * sb;                // g in/out, phi^n, T^n in, u out
-    // f in/out, u and phi^{n+1} in, T out; FP16 deviation storage also reads T^n
-    b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * pb + (d->pb == 2 ? 6.0 : 5.0) * sb : 0.0;
+    // f in/out, u and phi^{n+1} in, T out; FP32/FP16 deviation storage also reads T^n
+    b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * pb + (d->pb <= 4 ? 6.0 : 5.0) * sb : 0.0;
     b[TCP_K_RK] = d->P.thermal == TCP_THERMAL_RK2 ? 13.0 * sb : (d->P.thermal == TCP_THERMAL_RK4 ? 33.0 * sb : 0.0);
     // fused step: all PDFs in/out; phi^n, T^n, u^n in; phi^{n+1}, u^{n+1}, T^{n+1} out
     b[TCP_K_STEP] = d->P.thermal == TCP_THERMAL_LB
