@@ -278,6 +278,7 @@ def main() -> int:
                    "grid": [args.n] * 3, "precision": "fp32", "parallelism": "single GPU"},
         "roofline": roofline(fp32, "fp32"),
         "copy_probe_GBs": round(copy_gbs, 1),
+        "step_kernel_frac_of_copy": round(fp32["kernels"]["step"]["achieved_GBs"] / copy_gbs, 4),
         "cpu_baseline": base,
         "step_bytes_per_cell": fp32["step_bytes_per_cell"],
         "effective_GBs": round(fp32["effective_GBs"], 1),

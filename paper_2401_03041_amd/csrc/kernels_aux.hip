@@ -178,10 +178,13 @@ __global__ void __launch_bounds__(kThreads) k_reduce_final(const double *partial
         for (int k = 0; k < 4; ++k) out4[k] = sh[k][0];
 }
 
-__global__ void __launch_bounds__(kThreads) k_copy16(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n)
+// One 16-byte word per thread with non-temporal hints: the fastest plain copy
+// measured on MI355X (6.3-6.6 TB/s for 4 GiB; a grid-stride loop reaches 4.9).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(kThreads) k_copy16(const f32x4 *__restrict__ src, f32x4 *__restrict__ dst, int64_t n)
 {
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads)
-        dst[i] = src[i];
+    const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (i < n) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 inline unsigned blocks_for(int64_t n) { return (unsigned)((n + kThreads - 1) / kThreads); }
@@ -237,8 +240,8 @@ void launch_reduce(const Geometry &g, const void *phi, double *partial, double *
 
 void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_copy16, dim3(2048 * 8), dim3(kThreads), 0, s, static_cast<const float4 *>(src),
-                       static_cast<float4 *>(dst), n16);
+    hipLaunchKernelGGL(k_copy16, dim3(blocks_for(n16)), dim3(kThreads), 0, s, static_cast<const f32x4 *>(src),
+                       static_cast<f32x4 *>(dst), n16);
 }
 
 #define TCP_AUX_INST(S)                                                                                      \
