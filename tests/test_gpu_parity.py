@@ -73,10 +73,14 @@ def test_variants_walls_heater_fp64(q_pf, q_th, thermal):
     _report(errs, TOL64)
 
 
-@pytest.mark.parametrize("q_pf,q_th", [(15, 7), (27, 19)])
-def test_post_collision_pdfs_fp64(q_pf, q_th):
-    """The stored post-collision PDFs h, g, f themselves agree with the oracle."""
-    cfg = W.make(shape=(20, 13, 11), q_pf=q_pf, q_thermal=q_th, rho_h=1.0, rho_l=0.3, nu_h=0.1, nu_l=0.04,
+@pytest.mark.parametrize("q_pf,q_th,precision", [(15, 7, "fp64"), (27, 19, "fp64"), (15, 15, "fp32")])
+def test_post_collision_pdfs(q_pf, q_th, precision):
+    """The stored post-collision PDFs h, g, f themselves agree with the oracle (in
+    FP32 the phase-field and thermal PDFs are read back from their deviation
+    storage)."""
+    tol = TOL64 if precision == "fp64" else TOL32
+    cfg = W.make(shape=(20, 13, 11), q_pf=q_pf, q_thermal=q_th, precision=precision, rho_h=1.0, rho_l=0.3,
+                 nu_h=0.1, nu_l=0.04,
                  sigma_ref=2e-3, sigma_t=-1e-4, xi=3.5, droplets=[(9.2, 6.1, 4.7, 3.8)],
                  t_init={"kind": "linear", "axis": 1, "origin": 6.0, "slope": 0.02, "value": 0.4},
                  u_init=(0.01, -0.004, 0.002))
@@ -85,7 +89,7 @@ def test_post_collision_pdfs_fp64(q_pf, q_th):
         a, b = g.get_pdfs(which), o.get_pdfs(which)
         assert a.shape == b.shape
         err = np.max(np.abs(a - b)) / np.max(np.abs(b))
-        assert err < TOL64, (which, err)
+        assert err < tol, (which, err)
 
 
 def test_degenerate_shapes_fp64():
