@@ -167,11 +167,35 @@ def cpu_baseline(cfg: dict, box: int, steps: int) -> dict:
     d.step(steps)
     el = time.perf_counter() - t0
     mlups = box ** 3 * steps / el / 1e6
-    _log(f"oracle: {mlups:.3f} MLUPS on {O.num_threads()} threads ({el:.1f} s)")
-    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": O.num_threads(), "kind": "oracle",
+    threads = O.num_threads()
+    _log(f"oracle: {mlups:.3f} MLUPS on {threads} threads ({el:.1f} s)")
+    # the same code on one thread, continuing the same run for a tenth of the steps
+    steps1 = max(1, steps // 10)
+    O.set_num_threads(1)
+    t0 = time.perf_counter()
+    d.step(steps1)
+    el1 = time.perf_counter() - t0
+    O.set_num_threads(threads)
+    mlups1 = box ** 3 * steps1 / el1 / 1e6
+    _log(f"oracle: {mlups1:.3f} MLUPS on 1 thread ({el1:.1f} s)")
+    d.close()
+    return {"value": round(mlups, 4), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{box}^3 window at {origin} of the {cfg['shape'][0]}^3 droplet block ({ninside} whole "
                       f"droplets, its temperature field, no droplet cut by the faces), {steps} steps, FP64, "
-                      f"{el:.1f} s"}
+                      f"{el:.1f} s",
+            "single_thread": {"value": round(mlups1, 4), "steps": steps1, "seconds": round(el1, 1)},
+            "host_cpu": _cpu_model(), "host_logical_cpus": os.cpu_count()}
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 # The paper's own per-GPU figures for its coupled FP64 step on a 512 x 256 x 256
