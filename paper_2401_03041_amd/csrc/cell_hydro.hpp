@@ -105,7 +105,7 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
     const R nu = tau * R(1.0 / 3.0);
     const R sig = R(a.sigma_ref) + R(a.sigma_t) * (T - R(a.t_ref));
     const R xi = R(a.xi);
-    const R beta = R(12) * sig / xi, kap = R(1.5) * sig * xi;
+    const R beta = R(a.twelve_inv_xi) * sig, kap = R(1.5) * sig * xi;
     const R mu = R(4) * beta * phi * (phi - R(1)) * (phi - R(0.5)) - kap * lap;
     const R gp2 = gp[0] * gp[0] + gp[1] * gp[1] + gp[2] * gp[2];
     const R gTgp = gT[0] * gp[0] + gT[1] * gp[1] + gT[2] * gp[2];
@@ -126,11 +126,12 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
     const R pfac = -ps * third * drho;
     const R vfac = nu * drho;
     R acc[3];
+    const R inv_rho = R(1) / rho;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const R Fs = mu * gp[k] + mar * (gp2 * gT[k] - gTgp * gp[k]);
         const R F = Fs + rho * R(a.g[k]) + pfac * gp[k] + vfac * Sgp[k];
-        acc[k] = F / rho;
+        acc[k] = F * inv_rho;
         u[k] = u0[k] + R(0.5) * acc[k];
     }
 

@@ -92,18 +92,28 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
     R d[Q];
     FirstOrder<Q, R>::apply(u, v, d);
 
-    // h* = w (phi (1 + zeta) + e.F / 2) + d, zeta the velocity part of h_eq / (w phi)
+    // h* = w (phi (1 + zeta) + e.F / 2) + d with zeta = 3 e.u + 9/2 (e.u)^2 - 3/2 u.u
+    // (minus w phi when stored as a deviation).  Opposite directions share the
+    // even part phi (1 - 3/2 u.u + 9/2 (e.u)^2) and flip the odd part
+    // 3 phi e.u + e.F / 2.
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const R base = phi * ((dev ? R(0) : R(1)) - R(1.5) * uu);
     P *hd = static_cast<P *>(a.h_dst);
+    st_pdf(elem(pdf_row<Q>(hd, a.geo, nb.yr[1], nb.zi[1], 0), pl.xq[1]), R(weight<Q>(0)) * base + d[0]);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
+        if (opposite<Q>(i) < i) continue;
+        const int o = opposite<Q>(i);
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
         const R w = R(weight<Q>(i));
-        const R eu = R(ex) * u[0] + R(ey) * u[1] + R(ez) * u[2];
-        const R eF = R(ex) * F[0] + R(ey) * F[1] + R(ez) * F[2];
-        const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
-        const R rest = dev ? phi * zeta : phi * (R(1) + zeta); // minus w phi when stored as a deviation
-        st_pdf(elem(pdf_row<Q>(hd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * (rest + R(0.5) * eF) + d[i]);
+        R eu = R(0), eF = R(0);
+        if (ex) { eu += R(ex) * u[0]; eF += R(ex) * F[0]; }
+        if (ey) { eu += R(ey) * u[1]; eF += R(ey) * F[1]; }
+        if (ez) { eu += R(ez) * u[2]; eF += R(ez) * F[2]; }
+        const R even = base + R(4.5) * phi * eu * eu;
+        const R odd = R(3) * phi * eu + R(0.5) * eF;
+        st_pdf(elem(pdf_row<Q>(hd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * (even + odd) + d[i]);
+        st_pdf(elem(pdf_row<Q>(hd, a.geo, nb.yr[1], nb.zi[1], o), pl.xq[1]), w * (even - odd) + d[o]);
     }
     st(elem(static_cast<S *>(a.phi_new), nb.c), phi);
     return phi;

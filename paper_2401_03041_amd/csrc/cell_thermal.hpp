@@ -63,16 +63,27 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
     R d[Q];
     FirstOrder<Q, R>::apply(u, v, d);
     const R q = heat_source<R>(a.src, x, y, z);
+    // f* - w c = w (T (1 + zeta) - c + q) + d with c = ts (constant shift) or T
+    // (deviation storage), zeta = 3 e.u + 9/2 (e.u)^2 - 3/2 u.u: opposite
+    // directions share the even part and flip 3 T e.u
     const R uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+    const R base = (dev ? R(0) : Tp) - R(1.5) * T * uu + q;
     P *fd = static_cast<P *>(a.f_dst);
+    st_pdf(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], 0), pl.xq[1]), R(weight<Q>(0)) * base + d[0]);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
+        if (opposite<Q>(i) < i) continue;
+        const int o = opposite<Q>(i);
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
         const R w = R(weight<Q>(i));
-        const R eu = R(vel<Q>(i, 0)) * u[0] + R(vel<Q>(i, 1)) * u[1] + R(vel<Q>(i, 2)) * u[2];
-        const R zeta = R(3) * eu + R(4.5) * eu * eu - R(1.5) * uu;
-        // f* - w ts = w (T (1 + zeta) - ts) + d + w q;  f* - w T = w T zeta + d + w q
-        const R rest = dev ? T * zeta : Tp * (R(1) + zeta) + ts * zeta;
-        st_pdf(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * rest + d[i] + w * q);
+        R eu = R(0);
+        if (ex) eu += R(ex) * u[0];
+        if (ey) eu += R(ey) * u[1];
+        if (ez) eu += R(ez) * u[2];
+        const R even = base + R(4.5) * T * eu * eu;
+        const R odd = R(3) * T * eu;
+        st_pdf(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], i), pl.xq[1]), w * (even + odd) + d[i]);
+        st_pdf(elem(pdf_row<Q>(fd, a.geo, nb.yr[1], nb.zi[1], o), pl.xq[1]), w * (even - odd) + d[o]);
     }
     st(elem(static_cast<S *>(a.T), nb.c), T);
 }

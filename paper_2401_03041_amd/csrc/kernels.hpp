@@ -32,6 +32,7 @@ struct HydroArgs {
     double rho_l, drho;  // rho(phi) = rho_l + phi_c drho
     double tau_l, dtau;  // tau(phi) = tau_l + phi_c dtau, tau = nu / c_s^2
     double sigma_ref, sigma_t, t_ref, xi;
+    double twelve_inv_xi; // 12 / xi (beta = 12 sigma / xi)
     double g[3];
     double omega_bulk;
     double uw_bot[3], uw_top[3];

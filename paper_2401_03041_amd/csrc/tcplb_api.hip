@@ -200,6 +200,7 @@ HydroArgs hydro_args(const tcp_domain *d)
     a.sigma_t = P.sigma_t;
     a.t_ref = P.t_ref;
     a.xi = P.xi;
+    a.twelve_inv_xi = 12.0 / P.xi;
     for (int k = 0; k < 3; ++k) {
         a.g[k] = P.g[k];
         a.uw_bot[k] = P.u_wall_bot[k];
