@@ -49,6 +49,7 @@ class _Params(C.Structure):
         ("u_wall_bot", C.c_double * 3), ("u_wall_top", C.c_double * 3),
         ("t_wall_bot", C.c_double), ("t_wall_top", C.c_double),
         ("normal_eps", C.c_double),
+        ("contact_angle_bot", C.c_double), ("contact_angle_top", C.c_double),
     ]
 
 
@@ -128,6 +129,8 @@ def make_params(cfg: dict) -> _Params:
     p.t_wall_bot = float(cfg.get("t_wall_bot", 0.0))
     p.t_wall_top = float(cfg.get("t_wall_top", 0.0))
     p.normal_eps = float(cfg.get("normal_eps", 1e-6))
+    p.contact_angle_bot = float(cfg.get("contact_angle_bot", 90.0))
+    p.contact_angle_top = float(cfg.get("contact_angle_top", 90.0))
     return p
 
 

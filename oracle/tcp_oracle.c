@@ -43,6 +43,9 @@
  *   R19 n = grad phi / sqrt(|grad phi|^2 + eps^2), eps = normal_eps (default 1e-6)
  *   R20 phi clamped to [0,1] only inside rho, tau and kappa
  *   R21 initial state: tanh droplets, PDFs at equilibrium with p* = 0
+ *   R22, R23 (the App. A reference solution and channel set-up: tests only)
+ *   R24 wetting: ghost phi across a wall from the contact-angle condition
+ *       n_w . grad phi = -cos(theta) 4 phi (1 - phi)/xi (mirror at 90 degrees)
  *
  * Parity unpinned (no test other than oracle-vs-GPU consistency fixes them):
  *   the relaxation rates of the third- and higher-order moments (R14), the
@@ -322,6 +325,7 @@ typedef struct {
     double u_wall_bot[3], u_wall_top[3];
     double t_wall_bot, t_wall_top;
     double normal_eps;
+    double contact_angle_bot, contact_angle_top; /* degrees, through the heavy phase (R24) */
 } ora_params;
 
 typedef struct {
@@ -338,6 +342,7 @@ typedef struct {
     double *u;      /* 3N, cell-major */
     double *T;
     double *Twb, *Twt; /* wall temperatures, nx*nz, x fastest */
+    double wet_bot, wet_top; /* (4/xi) cos(contact angle) of the two walls */
     double *rk[4];     /* RK work fields */
     int cur;
     int nsrc;
@@ -384,14 +389,24 @@ static double heat_source(const ora_domain *d, double x, double y, double z)
 /* ------------------------------------------------------------------------ */
 /* Scalar fields with wall ghosts and isotropic finite differences (R17)     */
 /* ------------------------------------------------------------------------ */
-/* phi with a mirror ghost across the y walls (reading R12) */
+/* phi with a wetting ghost across the y walls (reading R24): the wall normal
+ * derivative of phi is -cos(theta) |grad phi| with |grad phi| = 4 phi (1 - phi)/xi
+ * (the tanh interface), taken one-sided between the ghost and the adjacent
+ * cell: ghost = phi_adj + cos(theta) (4/xi) phi_adj (1 - phi_adj).  A contact
+ * angle of 90 degrees gives the mirror ghost (reading R12). */
 static double phi_at(const ora_domain *d, const double *phi, int x, int y, int z)
 {
     x = wrap(x, d->P.nx);
     z = wrap(z, d->P.nz);
     if (d->P.walls_y) {
-        if (y < 0) y = 0;
-        if (y >= d->P.ny) y = d->P.ny - 1;
+        if (y < 0) {
+            const double v = phi[cidx(d, x, 0, z)];
+            return v + d->wet_bot * v * (1.0 - v);
+        }
+        if (y >= d->P.ny) {
+            const double v = phi[cidx(d, x, d->P.ny - 1, z)];
+            return v + d->wet_top * v * (1.0 - v);
+        }
     } else {
         y = wrap(y, d->P.ny);
     }
@@ -715,6 +730,12 @@ static void step_thermal_rk(ora_domain *d)
 /* ------------------------------------------------------------------------ */
 void ora_destroy(ora_domain *d);
 
+/* cosine of an angle in degrees, exactly zero at 90 */
+static double cos_deg(double a)
+{
+    return a == 90.0 ? 0.0 : cos(a * (3.14159265358979323846 / 180.0));
+}
+
 ora_domain *ora_create(const ora_params *P)
 {
     init_stencils();
@@ -727,6 +748,8 @@ ora_domain *ora_create(const ora_params *P)
     d->P = *P;
     d->sh = get_stencil(P->q_pf);
     d->sg = get_stencil(27);
+    d->wet_bot = 4.0 / P->xi * cos_deg(P->contact_angle_bot);
+    d->wet_top = 4.0 / P->xi * cos_deg(P->contact_angle_top);
     d->sf = get_stencil(P->q_thermal);
     basis_monomials(P->q_pf, &d->Bh);
     basis_hydro(&d->Bg);

@@ -324,3 +324,47 @@ def test_planar_heated_channel_matches_appendix_a():
     assert l2(np.hypot(u, v), np.hypot(u_ref, v_ref)) < 0.35
     corr = np.sum(u * u_ref + v * v_ref) / np.sqrt(np.sum(u * u + v * v) * np.sum(u_ref ** 2 + v_ref ** 2))
     assert corr > 0.95
+
+
+def _contact_angle(phi):
+    """Contact angle (degrees, through the heavy phase) of a 2D cap phi[y, x] on
+    the wall y = -1/2: least-squares circle through the phi = 1/2 crossings."""
+    pts = []
+    ny, nx = phi.shape
+    for y in range(ny):
+        for x in range(nx - 1):
+            a, b = phi[y, x] - 0.5, phi[y, x + 1] - 0.5
+            if a * b < 0:
+                pts.append((x + a / (a - b), y))
+    for x in range(nx):
+        for y in range(ny - 1):
+            a, b = phi[y, x] - 0.5, phi[y + 1, x] - 0.5
+            if a * b < 0:
+                pts.append((x, y + a / (a - b)))
+    P = np.array(pts)
+    A = np.c_[2 * P[:, 0], 2 * P[:, 1], np.ones(len(P))]
+    cx, cy, c = np.linalg.lstsq(A, (P ** 2).sum(1), rcond=None)[0]
+    R = np.sqrt(c + cx ** 2 + cy ** 2)
+    return float(np.degrees(np.arccos(-(cy + 0.5) / R)))
+
+
+@pytest.mark.parametrize("theta", [60.0, 120.0])
+def test_wetting_boundary_sets_the_contact_angle(theta):
+    """Wetting wall (reading R24), 2D cap on the bottom wall of a 48 x 20 channel:
+    a circular cap started at the imposed angle keeps it (within 3 degrees over
+    1500 steps), and a hemisphere (90 degrees) moves towards it by more than 10
+    degrees in the same time.  A wrong sign or factor in the ghost fails both."""
+    nx, ny = 48, 20
+    base = dict(shape=(nx, ny, 1), periodic_y=False, rho_h=1.0, rho_l=1.0, nu_h=1 / 6, nu_l=1 / 6,
+                mobility=0.1, xi=4.0, sigma_ref=5e-3, contact_angle_bot=theta)
+    R = 9.0
+    yc = -0.5 - R * np.cos(np.radians(theta))
+    cap = oracle_domain(W.make(droplets=[(nx / 2 - 0.3, yc, 0.0, R)], **base))
+    cap.step(1500)
+    a_cap = _contact_angle(cap.get_field("phi")[0])
+    hemi = oracle_domain(W.make(droplets=[(nx / 2 - 0.3, -0.5, 0.0, 8.0)], **base))
+    hemi.step(1500)
+    a_hemi = _contact_angle(hemi.get_field("phi")[0])
+    print(theta, a_cap, a_hemi)
+    assert abs(a_cap - theta) < 3.0
+    assert abs(a_hemi - theta) < abs(90.0 - theta) - 10.0
