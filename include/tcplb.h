@@ -17,7 +17,10 @@
  *    host arrays are FP64 in that order.  Device arrays given to or taken
  *    from the library are FP64 in the same order.
  *  - The domain is periodic in x and z.  In y it is periodic, or bounded by
- *    no-slip walls at y = -1/2 and y = ny - 1/2 (halfway bounce-back).
+ *    no-slip walls at y = -1/2 and y = ny - 1/2 (halfway bounce-back).  At a
+ *    wall the phase field meets the contact angle theta of that wall: the
+ *    stencils see phi_adj + cos(theta) (4/xi) phi_adj (1 - phi_adj) beyond it
+ *    (n_w . grad phi = -cos(theta) |grad phi| for the tanh interface).
  *  - Every call returns an int: TCP_OK (0) or a negative TCP_ERR_* code; no
  *    C++ exception crosses this interface.  tcp_last_error() gives text.
  *  - Work is enqueued on the HIP stream given at creation; calls that return
@@ -123,11 +126,14 @@ typedef struct {
     double t_wall_bot;      /* uniform wall temperatures; tcp_set_wall_temperature */
     double t_wall_top;      /*   overrides them with per-column values */
     double t_shift;         /* FP64: thermal PDFs are stored as f_i - w_i t_shift */
+    double contact_angle_bot; /* wetting of the walls (walls_y = 1): contact angle in degrees,  */
+    double contact_angle_top; /*   measured through the heavy phase, in (0, 180); 90 = neutral */
 } tcp_params;
 
 /* Fill *p with defaults: 32^3 periodic, D3Q15 phase field, D3Q7 thermal LB,
  * FP64, unit densities, nu = 1/6, M = 0.05, xi = 5, no surface tension,
- * kappa = 0.2, omega_bulk = 1, normal_eps = 1e-6, t_shift = 0. */
+ * kappa = 0.2, omega_bulk = 1, normal_eps = 1e-6, t_shift = 0, contact angles
+ * 90 degrees. */
 int tcp_params_default(tcp_params *p);
 
 /* Validate *p and allocate a domain.  Rejects (TCP_ERR_ARG) any relaxation
@@ -162,6 +168,22 @@ int tcp_initialize(tcp_domain *d);
 
 /* Advance nsteps coupled time steps (asynchronous). */
 int tcp_step(tcp_domain *d, int64_t nsteps);
+
+/* Temperature initialisation by running the thermal solver on its own
+ * (Sec. 4.1: phi and u are set statically, T by iterating the thermal
+ * update until it settles).  Runs thermal updates (the LB of Eq. lb_thermal
+ * or the RK stages of Eq. rk2 / rk4, heat sources and wall temperatures
+ * included) with phi, u and the phase-field and hydrodynamic PDFs held,
+ * until the largest per-cell change of T over one update, measured after
+ * every check_every updates and after the last, is at most tol, or
+ * max_steps updates have run (tol = 0 runs exactly max_steps).  On return
+ * *steps_done holds the number of updates and *change the last measured
+ * change (0 if none ran); either pointer may be NULL.  Must follow
+ * tcp_initialize.  Synchronises at each check.  TCP_ERR_ARG for
+ * max_steps < 0, check_every < 1 or tol negative or not finite;
+ * TCP_ERR_NONFINITE if T becomes NaN or Inf. */
+int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t check_every,
+                         int64_t *steps_done, double *change);
 
 /* Read back one field as FP64 into host (synchronises) or dev (FP64 device
  * array of nx*ny*nz values, asynchronous); exactly one is non-NULL. */

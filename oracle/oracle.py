@@ -75,6 +75,7 @@ def _load():
     lib.ora_set_wall_temperature.argtypes = [vp, C.c_int, dp]
     lib.ora_initialize.argtypes = [vp]
     lib.ora_step.argtypes = [vp, C.c_int64]
+    lib.ora_warm_temperature.argtypes = [vp, C.c_int64, C.c_double, C.c_int64, C.POINTER(C.c_int64), dp]
     lib.ora_get_field.argtypes = [vp, C.c_int, dp]
     lib.ora_get_pdfs.argtypes = [vp, C.c_int, dp]
     lib.ora_set_pdfs.argtypes = [vp, C.c_int, dp]
@@ -189,6 +190,17 @@ class OracleDomain:
     def step(self, n: int = 1) -> None:
         if self._lib.ora_step(self._h, int(n)) != 0:
             raise RuntimeError("oracle collision matrix became singular")
+
+    def warm_temperature(self, max_steps: int, tol: float = 0.0, check_every: int = 100):
+        """Thermal updates alone (Sec. 4.1 temperature initialisation); returns
+        (updates run, last per-update change of T)."""
+        n = C.c_int64()
+        ch = np.zeros(1)
+        rc = self._lib.ora_warm_temperature(self._h, int(max_steps), float(tol), int(check_every), C.byref(n),
+                                            _dptr(ch))
+        if rc != 0:
+            raise RuntimeError(f"oracle warm-up failed ({rc})")
+        return int(n.value), float(ch[0])
 
     def get_field(self, name: str) -> np.ndarray:
         out = np.empty(self.shape3, dtype=np.float64)

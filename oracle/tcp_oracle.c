@@ -895,6 +895,53 @@ int ora_step(ora_domain *d, int64_t nsteps)
     return 0;
 }
 
+/* Temperature initialisation (Sec. 4.1): phi and u are imposed, T is found by
+ * running the thermal solver by itself until it settles.  Each update is the
+ * thermal part of a step with phi^{n+1} = phi^n and u held; the change is the
+ * largest |T_new - T_old| of one update, taken after every check_every updates
+ * and after the last; the loop ends once it is at most tol or after max_steps. */
+int ora_warm_temperature(ora_domain *d, int64_t max_steps, double tol, int64_t check_every, int64_t *steps_done,
+                         double *change)
+{
+    if (max_steps < 0 || check_every < 1 || !(tol >= 0.0)) return -1;
+    const int64_t N = d->N;
+    const int start = d->cur;
+    memcpy(d->phi[1 - start], d->phi[start], (size_t)N * sizeof(double));
+    double *prev = malloc((size_t)N * sizeof(double));
+    if (!prev) return -3;
+    int64_t n = 0;
+    double last = 0.0;
+    int err = 0;
+    while (n < max_steps) {
+        memcpy(prev, d->T, (size_t)N * sizeof(double));
+        if (d->P.thermal == 0) {
+            err |= step_thermal_lb(d);
+            d->cur = 1 - d->cur;
+        } else {
+            step_thermal_rk(d);
+        }
+        ++n;
+        if (n % check_every == 0 || n == max_steps) {
+            last = 0.0;
+            for (int64_t c = 0; c < N; ++c) {
+                const double dv = fabs(d->T[c] - prev[c]);
+                if (dv > last || dv != dv) last = dv;
+            }
+            if (last <= tol) break;
+        }
+    }
+    free(prev);
+    /* the thermal PDFs go back to the parity of the other PDFs */
+    if (d->cur != start) {
+        const int qf = d->sf->q;
+        memcpy(d->f[start], d->f[d->cur], (size_t)N * qf * sizeof(double));
+        d->cur = start;
+    }
+    if (steps_done) *steps_done = n;
+    if (change) *change = last;
+    return err ? -2 : 0;
+}
+
 /* which: 0 phi, 1 ux, 2 uy, 3 uz, 4 p, 5 p*, 6 T, 7 rho */
 int ora_get_field(const ora_domain *d, int which, double *out)
 {

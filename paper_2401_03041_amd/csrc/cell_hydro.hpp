@@ -6,7 +6,7 @@
 // mu_phi = 4 beta phi (phi-1)(phi-1/2) - k lap phi, beta = 12 sigma/xi,
 // k = 3 sigma xi / 2, sigma(T) = sigma_ref + sigma_T (T - T_ref), and the strain
 // rate taken from the non-equilibrium second moment of the pulled PDFs.
-// Gradients and the Laplacian use the isotropic D3Q27 stencil on phi^n (mirror
+// Gradients and the Laplacian use the isotropic D3Q27 stencil on phi^n (contact-angle
 // ghost at walls) and on T^n (ghost 2 T_w - T).
 //
 // Collision: central moments about u, the five deviatoric second-order
@@ -74,7 +74,8 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
         const R w = R(weight<27>(i));
-        const R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+        R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+        if (WALL && nb.ghost(ey)) pv = nb.phi_ghost(pv, ey, a.wet);
         R tv = ld<R>(nb.ptr(tp, ex, ey, ez));
         if (WALL && nb.ghost(ey)) {
             const double *tw = ey < 0 ? a.twb : a.twt;

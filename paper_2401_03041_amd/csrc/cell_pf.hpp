@@ -28,11 +28,14 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
     const P *hs = static_cast<const P *>(a.h_src);
     const PdfLanes<Q> pl(nb);
 
-    // phi^n on the 3x3x3 neighbourhood (mirror ghosts across walls)
+    // phi^n on the 3x3x3 neighbourhood (contact-angle ghosts across walls)
     const S *po = static_cast<const S *>(a.phi_old);
     R pn[27];
 #pragma unroll
-    for (int k = dev ? 0 : 1; k < 27; ++k) pn[k] = ld<R>(nb.ptr(po, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
+    for (int k = dev ? 0 : 1; k < 27; ++k) {
+        pn[k] = ld<R>(nb.ptr(po, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
+        if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);
+    }
 
     // pull; a link that crosses a wall returns the cell's own opposite PDF
     R h[Q];

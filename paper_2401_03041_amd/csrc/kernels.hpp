@@ -17,6 +17,7 @@ struct PfArgs {
     double omega_phi;    // 1 / (1/2 + M / c_s^2)
     double inv_xi;
     double eps2;         // normal_eps^2
+    double wet[2];       // (4/xi) cos(contact angle) of the bottom and top wall
 };
 
 // K2: velocity-based D3Q27 central-moment hydrodynamics with forces (Sec. 2.1-2.2)
@@ -36,6 +37,7 @@ struct HydroArgs {
     double g[3];
     double omega_bulk;
     double uw_bot[3], uw_top[3];
+    double wet[2];       // (4/xi) cos(contact angle) of the bottom and top wall
 };
 
 // K3: passive-scalar thermal LB (Eq. lb_thermal)
@@ -70,6 +72,7 @@ struct RkArgs {
     const double *twt;
     double kappa_l, dkappa;
     double a_next, w_acc;
+    double wet[2];        // (4/xi) cos(contact angle) of the bottom and top wall
     int first, last;
     HeatSources src;
 };
@@ -155,6 +158,11 @@ void launch_read_pdfs(const void *src, int q, const Geometry &g, double shift, c
 constexpr int kReduceBlocks = 1024;
 template <typename S>
 void launch_reduce(const Geometry &g, const void *phi, double *partial, double *out4, hipStream_t s);
+
+// max |a_c - b_c| over n values (NaN if any difference is NaN), in FP64: partial
+// maxima per work-group (kReduceBlocks of them), then one work-group
+template <typename S>
+void launch_maxdiff(int64_t n, const void *a, const void *b, double *partial, double *out, hipStream_t s);
 
 // streaming copy of n16 16-byte words (bandwidth probe)
 void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);

@@ -178,6 +178,39 @@ __global__ void __launch_bounds__(kThreads) k_reduce_final(const double *partial
         for (int k = 0; k < 4; ++k) out4[k] = sh[k][0];
 }
 
+// max |a - b| over the grid; a NaN anywhere makes the result NaN
+__device__ __forceinline__ double max_nan(double m, double v) { return (v > m || v != v) ? v : m; }
+
+template <typename S>
+__global__ void __launch_bounds__(kThreads) k_maxdiff_partial(int64_t n, const S *a, const S *b, double *partial)
+{
+    __shared__ double sh[kThreads];
+    double m = 0.0;
+    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < n; c += (int64_t)gridDim.x * kThreads)
+        m = max_nan(m, fabs(static_cast<double>(a[c]) - static_cast<double>(b[c])));
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+}
+
+__global__ void __launch_bounds__(kThreads) k_max_final(const double *partial, int nblocks, double *out)
+{
+    __shared__ double sh[kThreads];
+    double m = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kThreads) m = max_nan(m, partial[b]);
+    sh[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = kThreads / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] = max_nan(sh[threadIdx.x], sh[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sh[0];
+}
+
 // One 16-byte word per thread with non-temporal hints: the fastest plain copy
 // measured on MI355X (6.3-6.6 TB/s for 4 GiB; a grid-stride loop reaches 4.9).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -238,6 +271,14 @@ void launch_reduce(const Geometry &g, const void *phi, double *partial, double *
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kThreads), 0, s, partial, kReduceBlocks, out4);
 }
 
+template <typename S>
+void launch_maxdiff(int64_t n, const void *a, const void *b, double *partial, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_maxdiff_partial<S>), dim3(kReduceBlocks), dim3(kThreads), 0, s, n,
+                       static_cast<const S *>(a), static_cast<const S *>(b), partial);
+    hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kThreads), 0, s, partial, kReduceBlocks, out);
+}
+
 void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy16, dim3(blocks_for(n16)), dim3(kThreads), 0, s, static_cast<const f32x4 *>(src),
@@ -250,7 +291,8 @@ void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
     template void launch_init<S, S>(const InitArgs &, hipStream_t);                                         \
     template void launch_read<S>(const ReadArgs &, hipStream_t);                                            \
     template void launch_read_pdfs<S, S>(const void *, int, const Geometry &, double, const void *, double *, hipStream_t); \
-    template void launch_reduce<S>(const Geometry &, const void *, double *, double *, hipStream_t);
+    template void launch_reduce<S>(const Geometry &, const void *, double *, double *, hipStream_t);          \
+    template void launch_maxdiff<S>(int64_t, const void *, const void *, double *, double *, hipStream_t);
 TCP_AUX_INST(double)
 TCP_AUX_INST(float)
 #undef TCP_AUX_INST

@@ -13,7 +13,7 @@
 //   R(theta) = -u . grad theta + (kappa_H - kappa_L) grad phi . grad theta
 //              + kappa(phi) lap theta + q_T
 // with the isotropic D3Q27 stencils, ghost 2 T_w - theta at walls and the
-// mirror ghost for phi.
+// contact-angle ghost for phi.
 #include "cell_thermal.hpp"
 
 namespace tcp {
@@ -58,7 +58,8 @@ __device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb, int x, i
             const double *tw = ey < 0 ? a.twb : a.twt;
             tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;
         }
-        const R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+        R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+        if (WALL && nb.ghost(ey)) pv = nb.phi_ghost(pv, ey, a.wet);
         gt[0] += R(ex) * w * tv;
         gt[1] += R(ey) * w * tv;
         gt[2] += R(ez) * w * tv;

@@ -161,6 +161,13 @@ struct Nbr {
     {
         return (dy < 0 && below) || (dy > 0 && above);
     }
+    // phi beyond a wall (dy crossing it) from the wall-adjacent value v: the
+    // contact-angle ghost v + wet v (1 - v), wet = (4/xi) cos(theta) of that wall
+    template <typename R>
+    __device__ __forceinline__ R phi_ghost(R v, int dy, const double (&wet)[2]) const
+    {
+        return v + R(dy < 0 ? wet[0] : wet[1]) * v * (R(1) - v);
+    }
     // wall-column index x + nx*z of the neighbour at (dx, dz)
     __device__ __forceinline__ uint32_t col(int dx, int dz, const Geometry &g) const
     {

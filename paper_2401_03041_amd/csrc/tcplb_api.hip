@@ -121,6 +121,12 @@ struct Scratch {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// (4/xi) cos(theta) for a contact angle theta in degrees (exactly 0 at 90)
+double wetting(double degrees, double xi)
+{
+    return degrees == 90.0 ? 0.0 : 4.0 / xi * std::cos(degrees * (3.14159265358979323846 / 180.0));
+}
+
 constexpr size_t kArenaAlign = (size_t)2 << 20;
 constexpr size_t kArenaStagger = 0;
 
@@ -168,6 +174,8 @@ PfArgs pf_args(const tcp_domain *d)
     a.omega_phi = d->omega_phi;
     a.inv_xi = 1.0 / d->P.xi;
     a.eps2 = d->P.normal_eps * d->P.normal_eps;
+    a.wet[0] = wetting(d->P.contact_angle_bot, d->P.xi);
+    a.wet[1] = wetting(d->P.contact_angle_top, d->P.xi);
     return a;
 }
 
@@ -207,6 +215,8 @@ HydroArgs hydro_args(const tcp_domain *d)
         a.uw_top[k] = P.u_wall_top[k];
     }
     a.omega_bulk = P.omega_bulk;
+    a.wet[0] = wetting(P.contact_angle_bot, P.xi);
+    a.wet[1] = wetting(P.contact_angle_top, P.xi);
     return a;
 }
 
@@ -255,6 +265,8 @@ void thermal_step(tcp_domain *d)
     }
     RkArgs a{};
     a.geo = d->geo;
+    a.wet[0] = wetting(P.contact_angle_bot, P.xi);
+    a.wet[1] = wetting(P.contact_angle_top, P.xi);
     a.T = d->T[d->cur];
     a.T_new = d->T[1 - d->cur];
     a.phi = d->phi[1 - d->cur];
@@ -337,6 +349,26 @@ void one_step(tcp_domain *d)
         thermal_step<S, Pdf>(d);
     }
     d->cur = 1 - d->cur;
+}
+
+// thermal update alone (phase field and velocity held): the buffers of both
+// parities hold the same phi, so K3 sees it as phi^{n+1}
+template <typename S, typename Pdf>
+void thermal_only_step(tcp_domain *d)
+{
+    thermal_step<S, Pdf>(d);
+    d->cur = 1 - d->cur;
+}
+
+void run_thermal_steps(tcp_domain *d, int64_t nsteps)
+{
+    for (int64_t n = 0; n < nsteps; ++n) {
+        switch (d->P.precision) {
+        case TCP_FP64: thermal_only_step<double, double>(d); break;
+        case TCP_FP32: thermal_only_step<float, float>(d); break;
+        default: thermal_only_step<float, _Float16>(d); break;
+        }
+    }
 }
 
 void run_steps(tcp_domain *d, int64_t nsteps)
@@ -441,6 +473,8 @@ int validate(const tcp_params *p, std::string &why)
     for (double v : others)
         if (!std::isfinite(v)) { why = "parameters must be finite"; return TCP_ERR_ARG; }
     if (p->omega_bulk >= 2.0) { why = "omega_bulk must lie in (0, 2)"; return TCP_ERR_ARG; }
+    for (double a : {p->contact_angle_bot, p->contact_angle_top})
+        if (!(a > 0.0 && a < 180.0)) { why = "contact angles must lie in (0, 180) degrees"; return TCP_ERR_ARG; }
     for (const double *uw : {p->u_wall_bot, p->u_wall_top})
         if (std::sqrt(uw[0] * uw[0] + uw[1] * uw[1] + uw[2] * uw[2]) >= 0.1) {
             why = "wall speed must stay below 0.1"; return TCP_ERR_ARG;
@@ -518,6 +552,7 @@ int tcp_params_default(tcp_params *p)
     p->kappa_h = p->kappa_l = 0.2;
     p->omega_bulk = 1.0;
     p->normal_eps = 1e-6;
+    p->contact_angle_bot = p->contact_angle_top = 90.0;
     return TCP_OK;
 }
 
@@ -755,6 +790,53 @@ int tcp_step(tcp_domain *d, int64_t nsteps)
             }
         }
         run_steps(d, left);
+        return check_launch(d);
+    });
+}
+
+int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t check_every, int64_t *steps_done,
+                         double *change)
+{
+    if (!d) return TCP_ERR_ARG;
+    if (max_steps < 0) return fail(d, TCP_ERR_ARG, "max_steps must be >= 0");
+    if (check_every < 1) return fail(d, TCP_ERR_ARG, "check_every must be >= 1");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(d, TCP_ERR_ARG, "tol must be finite and >= 0");
+    if (!d->initialized) return fail(d, TCP_ERR_STATE, "tcp_initialize must precede tcp_warm_temperature");
+    return guarded(d, [&]() -> int {
+        const size_t nb = (size_t)d->geo.N * d->sb;
+        const int start = d->cur;
+        TCP_HIP(d, hipMemcpyAsync(d->phi[1 - start], d->phi[start], nb, hipMemcpyDeviceToDevice, d->stream));
+        int64_t done = 0;
+        double last = 0.0;
+        bool measured = false;
+        while (done < max_steps) {
+            const int64_t k = std::min(check_every - done % check_every, max_steps - done);
+            run_thermal_steps(d, k);
+            done += k;
+            if (done % check_every != 0 && done != max_steps) continue;
+            // T of the last two time levels sit in the two parities
+            if (d->sb == 8) launch_maxdiff<double>(d->geo.N, d->T[0], d->T[1], d->partial, d->out4, d->stream);
+            else launch_maxdiff<float>(d->geo.N, d->T[0], d->T[1], d->partial, d->out4, d->stream);
+            const int rc = check_launch(d);
+            if (rc != TCP_OK) return rc;
+            TCP_HIP(d, hipMemcpyAsync(&last, d->out4, sizeof last, hipMemcpyDeviceToHost, d->stream));
+            TCP_HIP(d, hipStreamSynchronize(d->stream));
+            measured = true;
+            if (!std::isfinite(last)) return fail(d, TCP_ERR_NONFINITE, "temperature holds NaN or Inf");
+            if (last <= tol) break;
+        }
+        // an odd count leaves the new thermal state in the other parity than the
+        // phase-field and hydrodynamic PDFs: move it back
+        if (d->cur != start) {
+            if (d->P.thermal == TCP_THERMAL_LB) {
+                const size_t fb = (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->pb;
+                TCP_HIP(d, hipMemcpyAsync(d->f[start], d->f[d->cur], fb, hipMemcpyDeviceToDevice, d->stream));
+            }
+            TCP_HIP(d, hipMemcpyAsync(d->T[start], d->T[d->cur], nb, hipMemcpyDeviceToDevice, d->stream));
+            d->cur = start;
+        }
+        if (steps_done) *steps_done = done;
+        if (change) *change = measured ? last : 0.0;
         return check_launch(d);
     });
 }

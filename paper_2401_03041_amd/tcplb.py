@@ -25,7 +25,7 @@ KERNELS = ("phase", "hydro", "thermal", "rk", "step")
 # names of every entry point the header declares
 EXPORTS = (
     "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_droplets",
-    "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_get_field",
+    "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_warm_temperature", "tcp_get_field",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
     "tcp_set_profiling", "tcp_set_fusion", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
     "tcp_last_error",
@@ -42,6 +42,7 @@ class Params(C.Structure):
         ("g", C.c_double * 3), ("omega_bulk", C.c_double), ("normal_eps", C.c_double),
         ("u_wall_bot", C.c_double * 3), ("u_wall_top", C.c_double * 3),
         ("t_wall_bot", C.c_double), ("t_wall_top", C.c_double), ("t_shift", C.c_double),
+        ("contact_angle_bot", C.c_double), ("contact_angle_top", C.c_double),
     ]
 
 
@@ -93,6 +94,7 @@ def load() -> C.CDLL:
         "tcp_set_wall_temperature": [vp, C.c_int, dp],
         "tcp_initialize": [vp],
         "tcp_step": [vp, i64],
+        "tcp_warm_temperature": [vp, i64, C.c_double, i64, C.POINTER(i64), dp],
         "tcp_get_field": [vp, C.c_int, dp, vp],
         "tcp_get_pdfs": [vp, C.c_int, dp],
         "tcp_reduce": [vp, dp, dp],
@@ -146,6 +148,8 @@ def params_from_config(cfg: dict) -> Params:
     p.t_wall_bot = float(cfg.get("t_wall_bot", 0.0))
     p.t_wall_top = float(cfg.get("t_wall_top", 0.0))
     p.t_shift = float(cfg.get("t_shift", 0.0))
+    p.contact_angle_bot = float(cfg.get("contact_angle_bot", 90.0))
+    p.contact_angle_top = float(cfg.get("contact_angle_top", 90.0))
     return p
 
 
@@ -252,6 +256,15 @@ class Domain:
 
     def step(self, n: int = 1) -> None:
         self._check(self._lib.tcp_step(self._h, int(n)), "step")
+
+    def warm_temperature(self, max_steps: int, tol: float = 0.0, check_every: int = 100):
+        """Thermal updates alone (phi, u held) until the per-update change of T is at
+        most tol or max_steps have run; returns (steps run, last change)."""
+        n = C.c_int64()
+        ch = np.zeros(1)
+        self._check(self._lib.tcp_warm_temperature(self._h, int(max_steps), float(tol), int(check_every),
+                                                   C.byref(n), _dptr(ch)), "warm_temperature")
+        return int(n.value), float(ch[0])
 
     # -- read-back ---------------------------------------------------------------------
     def get_field(self, name: str, out=None):

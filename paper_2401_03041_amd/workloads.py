@@ -34,7 +34,7 @@ DEFAULTS = dict(
     g=(0.0, 0.0, 0.0), omega_bulk=1.0, normal_eps=1e-6,
     u_wall_bot=(0.0, 0.0, 0.0), u_wall_top=(0.0, 0.0, 0.0), t_wall_bot=0.0, t_wall_top=0.0,
     droplets=[], heat_sources=[], t_init={"kind": "uniform", "value": 0.0},
-    u_init=(0.0, 0.0, 0.0),
+    u_init=(0.0, 0.0, 0.0), contact_angle_bot=90.0, contact_angle_top=90.0,
 )
 
 
@@ -114,11 +114,13 @@ def droplet_block(n: int = 512, ndrop: int = 64, seed: int = 0, precision: str =
                 droplets=drops, t_init={"kind": "gaussians", "list": gauss}, seed=seed, **kw)
 
 
-def capture(shape=(256, 128, 96), precision: str = "fp32", steps: int = 5000, **kw) -> dict:
+def capture(shape=(256, 128, 96), precision: str = "fp32", steps: int = 5000,
+            contact_angle: float = 90.0, **kw) -> dict:
     """Thermal-tweezer capture channel: hemisphere R = 12 on the bottom wall at
     x = 40, Gaussian heater (Q = 0.8, w = 16) on the bottom wall at x = 128,
     top wall moving at 0.02, both walls at T = 0.  Parameters follow the
-    paper's droplet study (Ma = 0.01, Ca = 0.16, Re = 0.08, xi = 4)."""
+    paper's droplet study (Ma = 0.01, Ca = 0.16, Re = 0.08, xi = 4); the bottom
+    wall's contact angle (degrees) is the parameter that study varies."""
     nx, ny, nz = shape
     R = 12.0 * nx / 256.0
     gamma = 0.02 / ny
@@ -134,7 +136,37 @@ def capture(shape=(256, 128, 96), precision: str = "fp32", steps: int = 5000, **
                 u_wall_top=(0.02, 0.0, 0.0), t_wall_bot=0.0, t_wall_top=0.0,
                 droplets=[(40.0 * nx / 256.0, -0.5, nz / 2.0, R)],
                 heat_sources=[(0.8, nx / 2.0, -0.5, nz / 2.0, 2.0 * 8.0 * nx / 256.0, 0.0)],
-                t_init={"kind": "uniform", "value": 0.0}, **kw)
+                t_init={"kind": "uniform", "value": 0.0}, contact_angle_bot=contact_angle, **kw)
+
+
+def laser_capture(dim: int = 3, R: float = 32.0, contact_angle: float = 90.0, q_s: float = 0.2,
+                  heaters: str = "single", shift: float = 0.5, precision: str = "fp32", **kw) -> dict:
+    """Droplet in shear flow meeting a laser-heated spot (Sec. 3.2 in 2D, Sec. 3.3
+    and App. C in 3D).  Channel 8R x 2R (2D, one cell in z) or 16R x 2R x 8R (3D)
+    between walls at T = 0, top wall moving at U_w = 2 gamma R; hemisphere of radius
+    R at rest on the bottom wall at x = 2R + 1 (z = 4R).  Heater(s) of amplitude
+    q_s, w_s = 6, d_s = 8 at x_s = 181, y_s = 21 (lengths quoted for R = 32 and
+    scaled with R), z_s = 4R ("single") or 4R +- shift R ("pair").  Ma = 0.01,
+    Ca = 0.16, Re = 0.08, k* = 1, sigma_ref = 5e-3, sigma_T = +2e-4, xi = 4, unit
+    ratios; U = gamma R gives U = sqrt(Ca sigma_ref Re / R), nu = U R / Re,
+    kappa = U R / Ma.  Dimensionless time t* = gamma t."""
+    if dim not in (2, 3) or heaters not in ("single", "pair"):
+        raise ValueError("dim must be 2 or 3 and heaters 'single' or 'pair'")
+    s = R / 32.0
+    nx, ny = int(round(16 * R if dim == 3 else 8 * R)), int(round(2 * R))
+    nz = int(round(8 * R)) if dim == 3 else 1
+    Re, Ca, Ma, sigma_ref = 0.08, 0.16, 0.01, 5e-3
+    U = float(np.sqrt(Ca * sigma_ref * Re / R))
+    nu, kappa, gamma = U * R / Re, U * R / Ma, U / R
+    zc = 4.0 * R if dim == 3 else 0.0
+    zs = [zc] if heaters == "single" or dim == 2 else [zc - shift * R, zc + shift * R]
+    src = [(q_s, 181.0 * s, 21.0 * s, z, 6.0 * s, 8.0 * s) for z in zs]
+    return make(name=f"laser_capture_{dim}d_R{R:g}_{heaters}_q{q_s:g}_theta{contact_angle:g}",
+                shape=(nx, ny, nz), periodic_y=False, precision=precision, rho_h=1.0, rho_l=1.0, nu_h=nu,
+                nu_l=nu, mobility=0.05, xi=4.0, sigma_ref=sigma_ref, sigma_t=2e-4, t_ref=0.0, kappa_h=kappa,
+                kappa_l=kappa, u_wall_top=(2.0 * gamma * R, 0.0, 0.0), t_wall_bot=0.0, t_wall_top=0.0,
+                droplets=[(2.0 * R + 1.0, -0.5, zc, R)], heat_sources=src, t_init={"kind": "uniform", "value": 0.0},
+                contact_angle_bot=contact_angle, gamma=gamma, **kw)
 
 
 # ---------------------------------------------------------------------------------------

@@ -108,3 +108,11 @@ def test_error_strings():
     lib = tcplb.load()
     for code in range(-6, 1):
         assert lib.tcp_error_string(code)
+
+
+def test_warm_temperature_rejects_bad_arguments_without_a_domain():
+    """A null domain is refused before anything touches the device."""
+    from paper_2401_03041_amd import tcplb
+    lib = tcplb.load()
+    n, ch = C.c_int64(), C.c_double()
+    assert lib.tcp_warm_temperature(None, 10, 0.0, 1, C.byref(n), C.byref(ch)) == -1  # TCP_ERR_ARG

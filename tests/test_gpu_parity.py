@@ -212,6 +212,92 @@ def test_fused_step_matches_three_kernels(precision, q_pf, q_th):
         assert np.max(np.abs(a - b)) <= tol * np.max(np.abs(b)), which
 
 
+@pytest.mark.parametrize("precision,q_pf,q_th,thermal,fuse", [
+    ("fp64", 15, 7, "lb", True), ("fp64", 27, 19, "lb", False), ("fp64", 15, 7, "rk2", True),
+    ("fp32", 15, 7, "lb", True), ("fp32", 27, 7, "rk4", False)])
+def test_wetting_walls(precision, q_pf, q_th, thermal, fuse):
+    """Contact angles of 60 degrees at the bottom wall and 120 at the top (the
+    wetting ghost of phi in the phase-field, hydrodynamic and Runge-Kutta
+    stencils): a cap on each wall, a moving lid and Marangoni stress, 60 steps,
+    fused and three-kernel paths, against the oracle."""
+    nx, ny, nz = 70, 22, 14
+    kap = 0.12 if thermal != "lb" else 0.25
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, precision=precision, q_pf=q_pf, q_thermal=q_th,
+                 thermal=thermal, rho_h=1.0, rho_l=0.3, nu_h=0.12, nu_l=0.06, mobility=0.05, xi=4.0,
+                 sigma_ref=3e-3, sigma_t=-4e-4, t_ref=0.5, kappa_h=kap, kappa_l=0.6 * kap,
+                 u_wall_top=(0.01, 0.0, 0.0), t_wall_bot=0.2, t_wall_top=1.0,
+                 droplets=[(20.4, 1.3, 6.6, 7.0), (50.7, 21.2, 7.3, 6.0)], t_init={"kind": "conduction"},
+                 contact_angle_bot=60.0, contact_angle_top=120.0)
+    g = gpu_domain(cfg)
+    g.set_fusion(fuse)
+    o = oracle_domain(cfg)
+    g.step(60)
+    o.step(60)
+    errs = compare(g, o, floor=1e-6)
+    du = max(float(np.max(np.abs(g.get_field(k) - o.get_field(k)))) for k in ("ux", "uy", "uz"))
+    errs["u"] = du / float(np.max(np.sqrt(sum(o.get_field(k) ** 2 for k in ("ux", "uy", "uz")))))
+    print("wetting", precision, q_pf, q_th, thermal, fuse, errs)
+    if precision == "fp64":
+        _report(errs, TOL64)
+    else:
+        _report(errs, TOL32, names=("phi", "u", "T", "p"))
+    # the angles act: the wall rows differ from those of a run with neutral (90 degree) walls
+    neutral = gpu_domain(dict(cfg, contact_angle_bot=90.0, contact_angle_top=90.0))
+    neutral.set_fusion(fuse)
+    neutral.step(60)
+    a, b = g.get_field("phi"), neutral.get_field("phi")
+    assert np.max(np.abs(a[:, 0] - b[:, 0])) > 1e-3 and np.max(np.abs(a[:, -1] - b[:, -1])) > 1e-3
+
+
+@pytest.mark.parametrize("precision,thermal,q_th,steps", [("fp64", "lb", 7, 301), ("fp64", "lb", 19, 300),
+                                                          ("fp64", "rk4", 7, 155), ("fp32", "lb", 7, 301)])
+def test_temperature_warmup(precision, thermal, q_th, steps):
+    """Thermal updates alone (Sec. 4.1 temperature initialisation) after a few
+    coupled steps, with a heater, a per-column wall temperature, conductivity
+    ratio 0.6 (so phi enters) and an odd or even count, then coupled steps again:
+    every field against the oracle, the reported change and count equal, and phi,
+    u, p and the hydrodynamic PDFs untouched by the warm-up."""
+    nx, ny, nz = 70, 22, 14
+    kap = 0.12 if thermal != "lb" else 0.25
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, precision=precision, thermal=thermal, q_thermal=q_th,
+                 rho_h=1.0, rho_l=0.3, nu_h=0.12, nu_l=0.06, xi=4.0, sigma_ref=3e-3, sigma_t=2e-4,
+                 kappa_h=kap, kappa_l=0.6 * kap, u_wall_top=(0.01, 0.0, 0.0), t_wall_top=0.5,
+                 droplets=[(30.3, 6.7, 4.1, 4.5)], heat_sources=[(0.02, 40.0, 6.0, 7.0, 6.0, 8.0)],
+                 contact_angle_bot=70.0)
+    tw = 0.1 * np.cos(2 * np.pi * np.arange(nx) / nx)[None, :] * np.ones((nz, 1))
+    g, o = _run_pair(cfg, 3, tw_bot=tw)
+    held = {k: g.get_field(k) for k in ("phi", "ux", "uy", "uz", "p")}
+    h0, g0 = g.get_pdfs("h"), g.get_pdfs("g")
+    ng, cg = g.warm_temperature(steps, 0.0, 100)
+    no, co = o.warm_temperature(steps, 0.0, 100)
+    assert ng == no == steps
+    tol = TOL64 if precision == "fp64" else TOL32
+    assert abs(cg - co) <= tol * float(np.max(np.abs(o.get_field("T"))))
+    for k, v in held.items():
+        assert np.array_equal(v, g.get_field(k)), k
+    assert np.array_equal(h0, g.get_pdfs("h")) and np.array_equal(g0, g.get_pdfs("g"))
+    errs = compare(g, o, names=("T",))
+    print("warm-up", precision, thermal, q_th, steps, errs, cg, co)
+    _report(errs, tol, names=("T",))
+    g.step(20)
+    o.step(20)
+    errs = compare(g, o, floor=1e-6)
+    print("after warm-up", errs)
+    _report(errs, tol, names=FIELDS if precision == "fp64" else ("phi", "T", "p"))
+
+
+def test_temperature_warmup_stops_at_tolerance():
+    """The stopping rule on the GPU: the count is a multiple of check_every, the
+    change at most tol, and one check earlier it was above tol."""
+    cfg = W.make(shape=(8, 24, 8), periodic_y=False, kappa_h=0.3, kappa_l=0.3, t_wall_bot=0.2, t_wall_top=1.0)
+    n, ch = gpu_domain(cfg).warm_temperature(100000, 1e-12, 50)
+    assert n % 50 == 0 and 0.0 < ch <= 1e-12
+    n2, ch2 = gpu_domain(cfg).warm_temperature(n - 50, 1e-12, 50)
+    assert n2 == n - 50 and ch2 > 1e-12
+    T = gpu_domain(cfg).get_field("T")
+    assert np.all(T == 0.0)
+
+
 def test_reduction_matches_host_sum():
     """FP64 mass and centroid against a host sum of the read-back phase field."""
     cfg = W.droplet_block(n=64, ndrop=4, radius=(6.0, 9.0), sigma_range=(6.0, 12.0), precision="fp32")

@@ -368,3 +368,50 @@ def test_wetting_boundary_sets_the_contact_angle(theta):
     print(theta, a_cap, a_hemi)
     assert abs(a_cap - theta) < 3.0
     assert abs(a_hemi - theta) < abs(90.0 - theta) - 10.0
+
+
+@pytest.mark.parametrize("thermal,q", [("lb", 7), ("lb", 19), ("rk2", 7), ("rk4", 7)])
+def test_temperature_warmup_reaches_conduction_profile(thermal, q):
+    """Temperature initialisation (Sec. 4.1) between walls at 0.2 and 1.0 from T = 0:
+    the thermal solver alone settles on the linear conduction profile (exact for
+    the anti-bounce-back walls and for the wall ghosts of the finite differences);
+    the loop stops at the first check with a change below tol."""
+    ny, kap, check = 24, 0.3, 50
+    cfg = W.make(shape=(1, ny, 1), periodic_y=False, thermal=thermal, q_thermal=q, kappa_h=kap, kappa_l=kap,
+                 t_wall_bot=0.2, t_wall_top=1.0)
+    o = oracle_domain(cfg)
+    n, change = o.warm_temperature(100000, 1e-13, check)
+    y = np.arange(ny)
+    T = o.get_field("T")[0, :, 0]
+    assert np.max(np.abs(T - (0.2 + 0.8 * (y + 0.5) / ny))) < 1e-9
+    assert n % check == 0 and 0.0 < change <= 1e-13
+    # one check earlier the change was still above tol
+    o2 = oracle_domain(cfg)
+    n2, change2 = o2.warm_temperature(n - check, 1e-13, check)
+    assert n2 == n - check and change2 > 1e-13
+    # tol = 0 runs exactly max_steps; max_steps = 0 does nothing
+    assert oracle_domain(cfg).warm_temperature(37, 0.0, 10)[0] == 37
+    assert oracle_domain(cfg).warm_temperature(0, 0.0, 10) == (0, 0.0)
+
+
+@pytest.mark.parametrize("thermal", ["lb", "rk2"])
+def test_temperature_warmup_with_uniform_source(thermal):
+    """A source so wide that it is uniform (w = 1e6) between cold walls, fluid at
+    rest with phi = 0.7 (kappa = kappa_l + 0.7 (kappa_h - kappa_l) = 0.24): at the
+    settled state the heat equation holds in the discrete form of each scheme,
+    kappa (T[y+1] - 2 T[y] + T[y-1]) = -Q in every interior row, and phi, u and
+    the hydrodynamic PDFs are untouched by the warm-up."""
+    ny, kap, Q = 24, 0.24, 1e-4
+    cfg = W.make(shape=(1, ny, 1), periodic_y=False, thermal=thermal, kappa_h=0.3, kappa_l=0.1,
+                 rho_l=0.5, xi=3.0, sigma_ref=1e-3, heat_sources=[(Q, 0.0, 5.0, 0.0, 1e6, 0.0)])
+    o = oracle_domain(cfg, phi=np.full((1, ny, 1), 0.7))
+    o.step(3)
+    before = {k: o.get_field(k) for k in ("phi", "ux", "uy", "p")}
+    g0 = o.get_pdfs("g")
+    n, change = o.warm_temperature(100000, 1e-15, 50)
+    T = o.get_field("T")[0, :, 0]
+    lap = T[2:] - 2 * T[1:-1] + T[:-2]
+    assert np.max(np.abs(kap * lap + Q)) < 1e-8 * Q
+    for k, v in before.items():
+        assert np.array_equal(v, o.get_field(k)), k
+    assert np.array_equal(g0, o.get_pdfs("g"))
