@@ -92,14 +92,16 @@ def run_gpu(cfg: dict, steps: int, warmup: int, precision: str, fuse: bool = Tru
     ncell = d.ncell
     bpc = d.algorithmic_bytes()
     kernels = {}
+    step_bytes = 0.0
     for k, (ms, n) in times.items():
         if n == 0:
             continue
         avg = ms / n
-        kernels[k] = {"avg_ms": avg, "launches": n,
-                      "algorithmic_bytes_per_launch": bpc[k] * ncell / (2 if k == "rk" else 1),
-                      "achieved_GBs": bpc[k] * ncell / (avg * 1e-3) / 1e9}
-    step_bytes = sum(bpc.values()) * ncell
+        # the byte model counts a whole step; the RK stages share it
+        per_launch = bpc[k] * ncell / (n / steps if k == "rk" else 1)
+        kernels[k] = {"avg_ms": avg, "launches": n, "algorithmic_bytes_per_launch": per_launch,
+                      "achieved_GBs": per_launch / (avg * 1e-3) / 1e9}
+        step_bytes += per_launch * n / steps
     d.close()
     del d
     torch.cuda.empty_cache()
@@ -108,6 +110,40 @@ def run_gpu(cfg: dict, steps: int, warmup: int, precision: str, fuse: bool = Tru
     return {"mlups": mlups, "ms_per_step": 1e3 * elapsed / steps, "kernels": kernels,
             "step_bytes_per_cell": step_bytes / ncell, "mass": mass,
             "effective_GBs": step_bytes * steps / elapsed / 1e9}
+
+
+def adjoint_cost(cfg: dict, updates: int, precision: str) -> dict:
+    """Thermal LB update with phi and u held (the temperature warm-up) against one
+    update of its adjoint (tcp_thermal_adjoint), per-kernel HIP-event times, on
+    the same domain."""
+    import numpy as np
+    import torch
+
+    from paper_2401_03041_amd import tcplb
+    d = tcplb.domain_from_workload(dict(cfg, precision=precision))
+    m = np.ones(d.shape3)
+    d.warm_temperature(2, 0.0, 10)
+    d.thermal_adjoint(2, m)
+    d.set_profiling(True)
+    d.kernel_times()
+    d.warm_temperature(updates, 0.0, updates + 1)
+    fwd = d.kernel_times()["thermal"]
+    d.thermal_adjoint(updates, m)
+    adj = d.kernel_times()["adjoint"]
+    d.set_profiling(False)
+    bpc = d.algorithmic_bytes()
+    ncell = d.ncell
+    d.close()
+    del d
+    torch.cuda.empty_cache()
+    f_ms, a_ms = fwd[0] / fwd[1], adj[0] / adj[1]
+    _log(f"{precision}: thermal update {f_ms:.3f} ms, adjoint update {a_ms:.3f} ms")
+    return {"kind": "thermal LB D3Q7 with phi and u held (temperature warm-up) and its adjoint",
+            "updates": updates, "forward_ms_per_update": round(f_ms, 4), "adjoint_ms_per_update": round(a_ms, 4),
+            "adjoint_over_forward": round(a_ms / f_ms, 3),
+            "forward_GBs": round(bpc["thermal"] * ncell / (f_ms * 1e-3) / 1e9, 1),
+            "adjoint_GBs": round(bpc["adjoint"] * ncell / (a_ms * 1e-3) / 1e9, 1),
+            "adjoint_bytes_per_cell": bpc["adjoint"]}
 
 
 def roofline(res: dict, precision: str) -> dict:
@@ -281,6 +317,8 @@ def main() -> int:
     fp64 = run_gpu(cfg, fp64_steps, max(2, args.warmup // 4), "fp64") if fp64_steps > 0 else None
     fp16_steps = args.steps // 2 if args.fp16_steps is None else args.fp16_steps
     fp16 = run_gpu(cfg, fp16_steps, max(2, args.warmup // 4), "fp16") if fp16_steps > 0 else None
+    adjoint = adjoint_cost(cfg, 20, "fp32")
+    adjoint["adjoint_update_over_coupled_step"] = round(adjoint["adjoint_ms_per_update"] / fp32["ms_per_step"], 3)
     pblock = None if args.no_paper_block else paper_block(10, 2)
     base = None if args.no_cpu_baseline else cpu_baseline(cfg, args.oracle_box, args.oracle_steps)
 
@@ -314,6 +352,7 @@ def main() -> int:
                         "ms_per_step": round(fp64["ms_per_step"], 4), "dtype": "f64",
                         "roofline": roofline(fp64, "fp64"), "effective_GBs": round(fp64["effective_GBs"], 1),
                         "step_bytes_per_cell": fp64["step_bytes_per_cell"]}
+    line["adjoint"] = adjoint
     if pblock is not None:
         line["paper_block"] = pblock
     if fp16 is not None:

@@ -75,10 +75,19 @@ enum { TCP_THERMAL_LB = 0, TCP_THERMAL_RK2 = 1, TCP_THERMAL_RK4 = 2 };
 enum { TCP_FP64 = 0, TCP_FP32 = 1, TCP_FP16 = 2 };
 
 /* Kernel kinds reported by tcp_kernel_times and tcp_algorithmic_bytes:
- * the phase-field, hydrodynamic and thermal LB kernels, an RK stage, and the
+ * the phase-field, hydrodynamic and thermal LB kernels, an RK stage, the
  * fused step (all three LB updates of a step in one kernel, see
- * tcp_set_fusion). */
-enum { TCP_K_PHASE = 0, TCP_K_HYDRO = 1, TCP_K_THERMAL = 2, TCP_K_RK = 3, TCP_K_STEP = 4, TCP_K_COUNT = 5 };
+ * tcp_set_fusion) and one update of the thermal adjoint
+ * (tcp_thermal_adjoint). */
+enum {
+    TCP_K_PHASE = 0,
+    TCP_K_HYDRO = 1,
+    TCP_K_THERMAL = 2,
+    TCP_K_RK = 3,
+    TCP_K_STEP = 4,
+    TCP_K_ADJOINT = 5,
+    TCP_K_COUNT = 6
+};
 
 typedef struct tcp_domain tcp_domain;
 
@@ -184,6 +193,24 @@ int tcp_step(tcp_domain *d, int64_t nsteps);
  * TCP_ERR_NONFINITE if T becomes NaN or Inf. */
 int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t check_every,
                          int64_t *steps_done, double *change);
+
+/* Adjoint of the temperature warm-up (thermal LB only).  With phi and u held
+ * at their current values, nsteps thermal LB updates (Eq. lb_thermal with the
+ * anti-bounce-back walls and the source of Eq. HeatSource) form an affine map
+ * from the heat-source amplitudes Q_k and the wall temperatures to T.  For
+ * the loss L = sum_x dL_dT[x] T(x) of the T reached after nsteps updates of
+ * tcp_warm_temperature, this returns dL/dQ_k (dL_dQ, one value per heat
+ * source in the order of tcp_set_heat_sources) and dL/dT_w of every column of
+ * the bottom and top walls (dL_dTw_bot, dL_dTw_top: nx*nz values, x fastest).
+ * The gradients do not depend on the current T or PDFs, which are left
+ * untouched.  dL_dT: host array of nx*ny*nz values (cell order x fastest);
+ * the three outputs are host arrays or NULL to skip.  One adjoint kernel per
+ * update, last to first, in the storage precision of the domain with FP64
+ * accumulation of the gradients; the workspace (two link-adjoint arrays of
+ * the thermal PDF size, three FP64 fields) is allocated on the first call and
+ * kept.  Synchronises.  TCP_ERR_UNSUPPORTED for the RK schemes. */
+int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dQ, double *dL_dTw_bot,
+                        double *dL_dTw_top);
 
 /* Read back one field as FP64 into host (synchronises) or dev (FP64 device
  * array of nx*ny*nz values, asynchronous); exactly one is non-NULL. */

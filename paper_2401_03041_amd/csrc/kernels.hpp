@@ -164,6 +164,36 @@ void launch_reduce(const Geometry &g, const void *phi, double *partial, double *
 template <typename S>
 void launch_maxdiff(int64_t n, const void *a, const void *b, double *partial, double *out, hipStream_t s);
 
+// Adjoint of the thermal LB update with phi and u held (one launch per update,
+// last to first).  mu_src holds dL/d(pulled PDFs) of the update being undone,
+// mu_dst receives that of the update before it; grad_q (one value per cell)
+// and grad_twb / grad_twt (one per wall column) accumulate in FP64.
+struct ThermalAdjointArgs {
+    Geometry geo;
+    const void *mu_src;
+    void *mu_dst;
+    const void *u[3];
+    const void *phi;
+    double kappa_l, dkappa;
+    double *grad_q;
+    double *grad_twb, *grad_twt;
+    int last; // the first forward update: no earlier output to propagate to
+};
+
+// mu of the last update: dL/dfp_j(x) = m(x) for the loss sum_x m(x) T(x)
+template <int Q, typename S>
+void launch_adjoint_seed(const Geometry &g, const double *m, void *mu, hipStream_t s);
+template <int Q, typename S, typename R>
+void launch_adjoint_step(const ThermalAdjointArgs &a, hipStream_t s);
+
+// dL/dQ_k = sum_x g_k(x) grad_q(x) for every heat source (g_k: the source's
+// profile at unit amplitude); partial sums per work-group in `partial`
+// (kMaxSources x kSourceGradBlocks values), then one work-group
+constexpr int kSourceGradBlocks = 256;
+static_assert(kMaxSources * kSourceGradBlocks <= 4 * kReduceBlocks, "shares the reduction's partial buffer");
+void launch_source_grad(const Geometry &g, const HeatSources &hs, const double *grad_q, double *partial,
+                        double *out, hipStream_t s);
+
 // streaming copy of n16 16-byte words (bandwidth probe)
 void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);
 

@@ -47,6 +47,12 @@ struct tcp_domain {
     hipStream_t cap_stream = nullptr;
     hipGraphExec_t gexec[2]{};
 
+    // thermal adjoint workspace, allocated on first use: link adjoints (two
+    // parities), loss weights, the per-cell source adjoint, the wall-column
+    // adjoints (bottom then top) and the per-source gradients
+    void *adj_mu[2]{};
+    double *adj_m = nullptr, *adj_g = nullptr, *adj_tw = nullptr, *adj_q = nullptr;
+
     bool prof = false;
     std::vector<TimingRecord> records;
     std::vector<hipEvent_t> pool;
@@ -534,6 +540,34 @@ std::vector<Piece> state_pieces(const tcp_domain *d)
 }
 } // namespace
 
+namespace {
+
+template <int Q, typename S>
+void run_thermal_adjoint(tcp_domain *d, int64_t nsteps)
+{
+    launch_adjoint_seed<Q, S>(d->geo, d->adj_m, d->adj_mu[0], d->stream);
+    ThermalAdjointArgs a{};
+    a.geo = d->geo;
+    for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+    a.phi = d->phi[d->cur];
+    a.kappa_l = d->P.kappa_l;
+    a.dkappa = d->P.kappa_h - d->P.kappa_l;
+    a.grad_q = d->adj_g;
+    a.grad_twb = d->adj_tw;
+    a.grad_twt = d->adj_tw + (size_t)d->P.nx * d->P.nz;
+    int b = 0;
+    for (int64_t n = nsteps; n >= 1; --n) {
+        a.mu_src = d->adj_mu[b];
+        a.mu_dst = d->adj_mu[1 - b];
+        a.last = n == 1;
+        KernelTimer t(d, TCP_K_ADJOINT);
+        launch_adjoint_step<Q, S, S>(a, d->stream);
+        b = 1 - b;
+    }
+}
+
+} // namespace
+
 extern "C" {
 
 int tcp_params_default(tcp_params *p)
@@ -841,6 +875,55 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
     });
 }
 
+int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dQ, double *dL_dTw_bot,
+                        double *dL_dTw_top)
+{
+    if (!d) return TCP_ERR_ARG;
+    if (nsteps < 0) return fail(d, TCP_ERR_ARG, "nsteps must be >= 0");
+    if (!dL_dT) return fail(d, TCP_ERR_ARG, "dL_dT (one value per cell) is required");
+    if (d->P.thermal != TCP_THERMAL_LB) return fail(d, TCP_ERR_UNSUPPORTED, "the adjoint covers the thermal LB only");
+    if (!d->initialized) return fail(d, TCP_ERR_STATE, "tcp_initialize must precede tcp_thermal_adjoint");
+    return guarded(d, [&]() -> int {
+        const size_t N = (size_t)d->geo.N, ncol = (size_t)d->P.nx * d->P.nz;
+        if (!d->adj_mu[0]) {
+            const size_t mb = (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->sb;
+            void *p[6] = {own(d, mb), own(d, mb), own(d, N * sizeof(double)), own(d, N * sizeof(double)),
+                          own(d, 2 * ncol * sizeof(double)), own(d, kMaxSources * sizeof(double))};
+            for (void *q : p)
+                if (!q) return fail(d, TCP_ERR_OOM, "device allocation failed (adjoint workspace)");
+            d->adj_mu[0] = p[0];
+            d->adj_mu[1] = p[1];
+            d->adj_m = static_cast<double *>(p[2]);
+            d->adj_g = static_cast<double *>(p[3]);
+            d->adj_tw = static_cast<double *>(p[4]);
+            d->adj_q = static_cast<double *>(p[5]);
+        }
+        TCP_HIP(d, hipMemcpyAsync(d->adj_m, dL_dT, N * sizeof(double), hipMemcpyHostToDevice, d->stream));
+        TCP_HIP(d, hipMemsetAsync(d->adj_g, 0, N * sizeof(double), d->stream));
+        TCP_HIP(d, hipMemsetAsync(d->adj_tw, 0, 2 * ncol * sizeof(double), d->stream));
+        const bool f64 = d->sb == 8;
+        switch (d->P.q_thermal) {
+        case 7: f64 ? run_thermal_adjoint<7, double>(d, nsteps) : run_thermal_adjoint<7, float>(d, nsteps); break;
+        case 15: f64 ? run_thermal_adjoint<15, double>(d, nsteps) : run_thermal_adjoint<15, float>(d, nsteps); break;
+        case 19: f64 ? run_thermal_adjoint<19, double>(d, nsteps) : run_thermal_adjoint<19, float>(d, nsteps); break;
+        default: f64 ? run_thermal_adjoint<27, double>(d, nsteps) : run_thermal_adjoint<27, float>(d, nsteps); break;
+        }
+        const int ns = d->src.n;
+        if (ns > 0) launch_source_grad(d->geo, d->src, d->adj_g, d->partial, d->adj_q, d->stream);
+        int rc = check_launch(d);
+        if (rc != TCP_OK) return rc;
+        if (dL_dQ && ns > 0)
+            TCP_HIP(d, hipMemcpyAsync(dL_dQ, d->adj_q, ns * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+        if (dL_dTw_bot)
+            TCP_HIP(d, hipMemcpyAsync(dL_dTw_bot, d->adj_tw, ncol * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+        if (dL_dTw_top)
+            TCP_HIP(d, hipMemcpyAsync(dL_dTw_top, d->adj_tw + ncol, ncol * sizeof(double), hipMemcpyDeviceToHost,
+                                      d->stream));
+        TCP_HIP(d, hipStreamSynchronize(d->stream));
+        return TCP_OK;
+    });
+}
+
 int tcp_get_field(tcp_domain *d, int which, double *host, void *dev)
 {
     if (!d) return TCP_ERR_ARG;
@@ -1029,6 +1112,8 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     b[TCP_K_STEP] = d->P.thermal == TCP_THERMAL_LB
                         ? 2.0 * (d->P.q_pf + d->P.q_thermal) * pb + 54.0 * sb + 10.0 * sb
                         : 0.0;
+    // link adjoints in/out, u and phi in, the FP64 source adjoint read and written
+    b[TCP_K_ADJOINT] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * sb + 4.0 * sb + 16.0 : 0.0;
     return TCP_OK;
 }
 

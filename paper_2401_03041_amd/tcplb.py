@@ -20,12 +20,12 @@ FIELDS = {"phi": PHI, "ux": UX, "uy": UY, "uz": UZ, "T": T, "p": P, "pstar": PST
 PDFS = {"h": 0, "g": 1, "f": 2}
 THERMAL = {"lb": 0, "rk2": 1, "rk4": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
-KERNELS = ("phase", "hydro", "thermal", "rk", "step")
+KERNELS = ("phase", "hydro", "thermal", "rk", "step", "adjoint")
 
 # names of every entry point the header declares
 EXPORTS = (
     "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_droplets",
-    "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_warm_temperature", "tcp_get_field",
+    "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_warm_temperature", "tcp_thermal_adjoint", "tcp_get_field",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
     "tcp_set_profiling", "tcp_set_fusion", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
     "tcp_last_error",
@@ -95,6 +95,7 @@ def load() -> C.CDLL:
         "tcp_initialize": [vp],
         "tcp_step": [vp, i64],
         "tcp_warm_temperature": [vp, i64, C.c_double, i64, C.POINTER(i64), dp],
+        "tcp_thermal_adjoint": [vp, i64, dp, dp, dp, dp],
         "tcp_get_field": [vp, C.c_int, dp, vp],
         "tcp_get_pdfs": [vp, C.c_int, dp],
         "tcp_reduce": [vp, dp, dp],
@@ -186,6 +187,7 @@ class Domain:
         self.cfg = dict(cfg)
         self.nx, self.ny, self.nz = (int(v) for v in cfg["shape"])
         self._p = params_from_config(cfg)
+        self.n_sources = 0
         self._alloc = None
         stream = None
         if use_torch:
@@ -246,6 +248,7 @@ class Domain:
         n = len(sources)
         arr = (HeatSource * max(n, 1))(*[HeatSource(*map(float, s)) for s in sources])
         self._check(self._lib.tcp_set_heat_sources(self._h, arr, n), "set_heat_sources")
+        self.n_sources = n
 
     def set_wall_temperature(self, wall: int, tw) -> None:
         a = np.ascontiguousarray(np.broadcast_to(np.asarray(tw, dtype=np.float64), (self.nz, self.nx)))
@@ -265,6 +268,18 @@ class Domain:
         self._check(self._lib.tcp_warm_temperature(self._h, int(max_steps), float(tol), int(check_every),
                                                    C.byref(n), _dptr(ch)), "warm_temperature")
         return int(n.value), float(ch[0])
+
+    def thermal_adjoint(self, nsteps: int, dL_dT):
+        """Gradients of L = sum(dL_dT * T), T after nsteps warm-up updates (phi, u
+        held), with respect to the heat-source amplitudes and the wall
+        temperatures: (dQ[n_sources], dTw_bot[nz, nx], dTw_top[nz, nx])."""
+        m = np.ascontiguousarray(np.broadcast_to(np.asarray(dL_dT, dtype=np.float64), self.shape3))
+        dq = np.zeros(16)
+        bot = np.zeros((self.nz, self.nx))
+        top = np.zeros((self.nz, self.nx))
+        self._check(self._lib.tcp_thermal_adjoint(self._h, int(nsteps), _dptr(m), _dptr(dq), _dptr(bot), _dptr(top)),
+                    "thermal_adjoint")
+        return dq[:self.n_sources], bot, top
 
     # -- read-back ---------------------------------------------------------------------
     def get_field(self, name: str, out=None):

@@ -1,0 +1,121 @@
+"""Adjoint of the temperature warm-up (thermal LB with phi and u held) through the
+C interface, against gradients the oracle gives by definition: the warm-up is
+linear in the source amplitudes and the wall temperatures once the initial T is
+zero, so dL/dQ_k is L with Q = e_k (all else zero) and dL/dT_w at one column is
+L with a unit wall temperature there."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2401_03041_amd import workloads as W
+from tests.helpers import gpu_domain
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(q, precision, nx=12, ny=10, nz=6):
+    rng = np.random.default_rng(7)
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, precision=precision, q_thermal=q, rho_l=0.5, xi=3.0,
+                 kappa_h=0.25, kappa_l=0.1, t_wall_bot=0.3, t_wall_top=0.8,
+                 droplets=[(5.3, 3.2, 2.7, 3.0)],
+                 heat_sources=[(0.02, 4.0, 2.0, 3.0, 3.0, 0.0), (0.01, 9.5, 7.0, 1.0, 2.0, 3.5)])
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    u = [0.02 * np.sin(2 * np.pi * (x / nx + 0.3 * k)) * np.cos(np.pi * (y + 0.5) / ny) for k in range(3)]
+    m = rng.uniform(-1.0, 1.0, (nz, ny, nx))
+    return cfg, u, m
+
+
+def _oracle_loss(cfg, phi, u, m, steps, sources, tw_bot, tw_top):
+    d = O.OracleDomain(dict(cfg, t_wall_bot=0.0, t_wall_top=0.0))
+    d.set_field("phi", phi)
+    for name, comp in zip(("ux", "uy", "uz"), u):
+        d.set_field(name, comp)
+    d.set_field("T", np.zeros_like(m))
+    d.set_heat_sources(sources)
+    d.set_wall_temperature(0, tw_bot)
+    d.set_wall_temperature(1, tw_top)
+    d.initialize()
+    d.warm_temperature(steps, 0.0, steps + 1)
+    L = float(np.sum(m * d.get_field("T")))
+    d.close()
+    return L
+
+
+def _oracle_gradient(cfg, phi, u, m, steps):
+    nx, ny, nz = cfg["shape"]
+    zero = np.zeros((nz, nx))
+    src = [list(s) for s in cfg["heat_sources"]]
+    dq = []
+    for k in range(len(src)):
+        unit = [[1.0 if j == k else 0.0] + s[1:] for j, s in enumerate(src)]
+        dq.append(_oracle_loss(cfg, phi, u, m, steps, unit, zero, zero))
+    off = [[0.0] + s[1:] for s in src]
+    tw = [np.zeros((nz, nx)), np.zeros((nz, nx))]
+    for wall in (0, 1):
+        for iz in range(nz):
+            for ix in range(nx):
+                e = np.zeros((nz, nx))
+                e[iz, ix] = 1.0
+                args = (e, zero) if wall == 0 else (zero, e)
+                tw[wall][iz, ix] = _oracle_loss(cfg, phi, u, m, steps, off, *args)
+    return np.array(dq), tw[0], tw[1]
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("precision,q", [("fp64", 7), ("fp64", 19), ("fp32", 7), ("fp32", 27)])
+def test_thermal_adjoint_matches_oracle_gradient(precision, q):
+    """Walls, two heaters (one cut off), conductivity ratio 2.5 across a droplet,
+    a held velocity field, random loss weights, 25 updates: dL/dQ and dL/dT_w
+    of both walls within 1e-11 (FP64) or 1e-5 (FP32) of the oracle's."""
+    steps = 25
+    cfg, u, m = _case(q, precision)
+    g = gpu_domain(cfg, u=u, T=np.full(m.shape, 0.4))
+    phi = g.get_field("phi")
+    dq, tb, tt = g.thermal_adjoint(steps, m)
+    oq, ob, ot = _oracle_gradient(cfg, phi, u, m, steps)
+    tol = 1e-11 if precision == "fp64" else 1e-5
+    errs = {"Q": _rel(dq, oq), "Tw_bot": _rel(tb, ob), "Tw_top": _rel(tt, ot)}
+    print(precision, q, errs, dq, oq)
+    assert all(v < tol for v in errs.values()), errs
+    # the state is untouched and a second call gives the same gradients
+    dq2, tb2, tt2 = g.thermal_adjoint(steps, m)
+    assert np.array_equal(dq, dq2) and np.array_equal(tb, tb2) and np.array_equal(tt, tt2)
+    assert np.array_equal(g.get_field("phi"), phi)
+
+
+def test_thermal_adjoint_against_gpu_forward():
+    """On a ragged 70 x 22 x 14 channel over 200 updates the adjoint's dL/dQ equals
+    the loss of the GPU's own warm-up at unit source amplitude from T = 0 (the map
+    is linear), in FP64; and the wall gradients sum to the loss of a unit
+    temperature on the whole wall."""
+    nx, ny, nz = 70, 22, 14
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_thermal=15, kappa_h=0.2, kappa_l=0.1, rho_l=0.5,
+                 xi=4.0, droplets=[(30.3, 6.7, 4.1, 4.5)],
+                 heat_sources=[(0.02, 40.0, 6.0, 7.0, 6.0, 8.0), (0.01, 12.0, 15.0, 2.0, 3.0, 0.0)])
+    rng = np.random.default_rng(3)
+    m = rng.uniform(0.0, 1.0, (nz, ny, nx))
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    u = [0.01 * np.cos(2 * np.pi * x / nx), 0.0 * x, 0.01 * np.sin(2 * np.pi * z / nz)]
+    g = gpu_domain(cfg, u=u)
+    dq, tb, tt = g.thermal_adjoint(200, m)
+
+    def loss(sources, wall_bot, wall_top):
+        c = dict(cfg, heat_sources=sources, t_wall_bot=wall_bot, t_wall_top=wall_top)
+        d = gpu_domain(c, u=u, T=np.zeros_like(m))
+        d.warm_temperature(200, 0.0, 1000)
+        return float(np.sum(m * d.get_field("T")))
+
+    src = [list(s) for s in cfg["heat_sources"]]
+    for k in range(2):
+        unit = [[1.0 if j == k else 0.0] + s[1:] for j, s in enumerate(src)]
+        ref = loss(unit, 0.0, 0.0)
+        assert abs(dq[k] - ref) <= 1e-11 * abs(ref), (k, dq[k], ref)
+    off = [[0.0] + s[1:] for s in src]
+    for wall, grad in ((0, tb), (1, tt)):
+        ref = loss(off, 1.0 if wall == 0 else 0.0, 1.0 if wall == 1 else 0.0)
+        assert abs(grad.sum() - ref) <= 1e-11 * abs(ref), (wall, grad.sum(), ref)

@@ -415,3 +415,28 @@ def test_temperature_warmup_with_uniform_source(thermal):
     for k, v in before.items():
         assert np.array_equal(v, o.get_field(k)), k
     assert np.array_equal(g0, o.get_pdfs("g"))
+
+
+def test_temperature_warmup_is_linear_in_sources_and_walls():
+    """From T = 0 the warm-up map is linear in the source amplitudes and the wall
+    temperatures (phi and u held): the T of a combined input is the sum of the
+    T of its parts.  This is what lets the adjoint test take gradients as the
+    loss at unit inputs."""
+    nx, ny, nz = 10, 8, 4
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_thermal=15, kappa_h=0.25, kappa_l=0.1, rho_l=0.5,
+                 xi=3.0, droplets=[(4.3, 3.2, 1.7, 2.5)])
+    u = [0.02 * np.sin(2 * np.pi * x / nx), 0.01 * np.cos(np.pi * (y + 0.5) / ny), 0.0 * x]
+
+    def run(q, tw):
+        d = oracle_domain(dict(cfg, heat_sources=[(q, 4.0, 2.0, 1.0, 2.5, 0.0)]), T=np.zeros((nz, ny, nx)), u=u)
+        d.set_wall_temperature(0, tw)
+        d.initialize()
+        d.warm_temperature(30, 0.0, 100)
+        return d.get_field("T")
+
+    e = np.zeros((nz, nx))
+    e[2, 3] = 1.0
+    both, src, wall = run(0.7, 0.4 * e), run(0.7, 0 * e), run(0.0, 0.4 * e)
+    assert np.max(np.abs(both - src - wall)) < 1e-14 * np.max(np.abs(both))
+    assert np.max(np.abs(run(1.4, 0 * e) - 2 * src)) < 1e-14 * np.max(np.abs(src))
