@@ -199,9 +199,11 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
  * anti-bounce-back walls and the source of Eq. HeatSource) form an affine map
  * from the heat-source amplitudes Q_k and the wall temperatures to T.  For
  * the loss L = sum_x dL_dT[x] T(x) of the T reached after nsteps updates of
- * tcp_warm_temperature, this returns dL/dQ_k (dL_dQ, one value per heat
- * source in the order of tcp_set_heat_sources) and dL/dT_w of every column of
- * the bottom and top walls (dL_dTw_bot, dL_dTw_top: nx*nz values, x fastest).
+ * tcp_warm_temperature, this returns for every heat source, in the order of
+ * tcp_set_heat_sources, four values dL/dQ_k, dL/dx_k, dL/dy_k, dL/dz_k
+ * (dL_dsource, 4*n values; the cut-off sphere moves with the source), and
+ * dL/dT_w of every column of the bottom and top walls (dL_dTw_bot,
+ * dL_dTw_top: nx*nz values, x fastest).
  * The gradients do not depend on the current T or PDFs, which are left
  * untouched.  dL_dT: host array of nx*ny*nz values (cell order x fastest);
  * the three outputs are host arrays or NULL to skip.  One adjoint kernel per
@@ -209,8 +211,8 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
  * accumulation of the gradients; the workspace (two link-adjoint arrays of
  * the thermal PDF size, three FP64 fields) is allocated on the first call and
  * kept.  Synchronises.  TCP_ERR_UNSUPPORTED for the RK schemes. */
-int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dQ, double *dL_dTw_bot,
-                        double *dL_dTw_top);
+int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dsource,
+                        double *dL_dTw_bot, double *dL_dTw_top);
 
 /* Read back one field as FP64 into host (synchronises) or dev (FP64 device
  * array of nx*ny*nz values, asynchronous); exactly one is non-NULL. */

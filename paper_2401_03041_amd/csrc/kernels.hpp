@@ -186,11 +186,12 @@ void launch_adjoint_seed(const Geometry &g, const double *m, void *mu, hipStream
 template <int Q, typename S, typename R>
 void launch_adjoint_step(const ThermalAdjointArgs &a, hipStream_t s);
 
-// dL/dQ_k = sum_x g_k(x) grad_q(x) for every heat source (g_k: the source's
-// profile at unit amplitude); partial sums per work-group in `partial`
-// (kMaxSources x kSourceGradBlocks values), then one work-group
-constexpr int kSourceGradBlocks = 256;
-static_assert(kMaxSources * kSourceGradBlocks <= 4 * kReduceBlocks, "shares the reduction's partial buffer");
+// For every heat source, dL/dQ_k = sum_x g_k(x) grad_q(x) (g_k: the source's
+// profile at unit amplitude) and dL/d(x_k, y_k, z_k), written as four values
+// per source; partial sums per work-group in `partial` (4 kMaxSources
+// kSourceGradBlocks values), then one work-group
+constexpr int kSourceGradBlocks = 64;
+static_assert(4 * kMaxSources * kSourceGradBlocks <= 4 * kReduceBlocks, "shares the reduction's partial buffer");
 void launch_source_grad(const Geometry &g, const HeatSources &hs, const double *grad_q, double *partial,
                         double *out, hipStream_t s);
 

@@ -122,47 +122,61 @@ __global__ void __launch_bounds__(kTX *kTY) k_adj_step(const ThermalAdjointArgs 
         adjoint_cell<Q, S, R, false>(a, nb);
 }
 
-// dL/dQ_k = sum_x g_k(x) G(x), g_k the unit-amplitude profile of source k and
-// G the accumulated source adjoint: partial sums per work-group, then one group
+// Source gradients from the accumulated source adjoint G: with the profile
+// g_k(x) = exp(-2 |x - x_k|^2 / w_k^2) (inside the cut-off), q = sum_k Q_k g_k
+// and dg_k/dx_k = 4 (x - x_k) g_k / w_k^2, so
+//   dL/dQ_k = sum_x G g_k,   dL/dx_k = Q_k sum_x G g_k 4 (x - x_k) / w_k^2
+// (the cut-off sphere moves with the source; its rim is a set of measure zero
+// and contributes nothing).  Four sums per source: partial sums per
+// work-group, then one work-group.
 __global__ void __launch_bounds__(kThreads) k_source_grad_partial(const Geometry g, const HeatSources hs,
                                                                   const double *G, double *partial)
 {
-    __shared__ double sh[kThreads];
+    __shared__ double sh[4][kThreads];
     for (int k = 0; k < hs.n; ++k) {
-        double acc = 0.0;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < g.N; c += (int64_t)gridDim.x * kThreads) {
             const int x = (int)(c % g.nx), y = (int)((c / g.nx) % g.ny), z = (int)(c / g.plane);
             const double dx = x - hs.x[k], dy = y - hs.y[k], dz = z - hs.z[k];
             const double d2 = dx * dx + dy * dy + dz * dz;
             if (hs.dcut2[k] > 0.0 && d2 > hs.dcut2[k]) continue;
-            acc += G[c] * exp(-2.0 * d2 * hs.inv_w2[k]);
+            const double v = G[c] * exp(-2.0 * d2 * hs.inv_w2[k]);
+            const double s = 4.0 * hs.inv_w2[k] * v;
+            acc[0] += v;
+            acc[1] += s * dx;
+            acc[2] += s * dy;
+            acc[3] += s * dz;
         }
-        sh[threadIdx.x] = acc;
+        for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] = acc[j];
         __syncthreads();
         for (int s = kThreads / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+            if ((int)threadIdx.x < s)
+                for (int j = 0; j < 4; ++j) sh[j][threadIdx.x] += sh[j][threadIdx.x + s];
             __syncthreads();
         }
-        if (threadIdx.x == 0) partial[kMaxSources * blockIdx.x + k] = sh[0];
+        if (threadIdx.x == 0)
+            for (int j = 0; j < 4; ++j) partial[4 * (kMaxSources * blockIdx.x + k) + j] = sh[j][0];
         __syncthreads();
     }
 }
 
-__global__ void __launch_bounds__(kThreads) k_source_grad_final(const double *partial, int nblocks, int n,
-                                                                double *out)
+__global__ void __launch_bounds__(kThreads) k_source_grad_final(const double *partial, int nblocks,
+                                                                const HeatSources hs, double *out)
 {
     __shared__ double sh[kThreads];
-    for (int k = 0; k < n; ++k) {
-        double acc = 0.0;
-        for (int b = threadIdx.x; b < nblocks; b += kThreads) acc += partial[kMaxSources * b + k];
-        sh[threadIdx.x] = acc;
-        __syncthreads();
-        for (int s = kThreads / 2; s > 0; s >>= 1) {
-            if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    for (int k = 0; k < hs.n; ++k) {
+        for (int j = 0; j < 4; ++j) {
+            double acc = 0.0;
+            for (int b = threadIdx.x; b < nblocks; b += kThreads) acc += partial[4 * (kMaxSources * b + k) + j];
+            sh[threadIdx.x] = acc;
+            __syncthreads();
+            for (int s = kThreads / 2; s > 0; s >>= 1) {
+                if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) out[4 * k + j] = j == 0 ? sh[0] : hs.Q[k] * sh[0];
             __syncthreads();
         }
-        if (threadIdx.x == 0) out[k] = sh[0];
-        __syncthreads();
     }
 }
 
@@ -186,7 +200,7 @@ void launch_source_grad(const Geometry &g, const HeatSources &hs, const double *
                         hipStream_t s)
 {
     hipLaunchKernelGGL(k_source_grad_partial, dim3(kSourceGradBlocks), dim3(kThreads), 0, s, g, hs, G, partial);
-    hipLaunchKernelGGL(k_source_grad_final, dim3(1), dim3(kThreads), 0, s, partial, kSourceGradBlocks, hs.n, out);
+    hipLaunchKernelGGL(k_source_grad_final, dim3(1), dim3(kThreads), 0, s, partial, kSourceGradBlocks, hs, out);
 }
 
 #define TCP_ADJ_INST(Q)                                                                                      \

@@ -875,8 +875,8 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
     });
 }
 
-int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dQ, double *dL_dTw_bot,
-                        double *dL_dTw_top)
+int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dsource,
+                        double *dL_dTw_bot, double *dL_dTw_top)
 {
     if (!d) return TCP_ERR_ARG;
     if (nsteps < 0) return fail(d, TCP_ERR_ARG, "nsteps must be >= 0");
@@ -888,7 +888,7 @@ int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, doub
         if (!d->adj_mu[0]) {
             const size_t mb = (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->sb;
             void *p[6] = {own(d, mb), own(d, mb), own(d, N * sizeof(double)), own(d, N * sizeof(double)),
-                          own(d, 2 * ncol * sizeof(double)), own(d, kMaxSources * sizeof(double))};
+                          own(d, 2 * ncol * sizeof(double)), own(d, 4 * kMaxSources * sizeof(double))};
             for (void *q : p)
                 if (!q) return fail(d, TCP_ERR_OOM, "device allocation failed (adjoint workspace)");
             d->adj_mu[0] = p[0];
@@ -912,8 +912,9 @@ int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, doub
         if (ns > 0) launch_source_grad(d->geo, d->src, d->adj_g, d->partial, d->adj_q, d->stream);
         int rc = check_launch(d);
         if (rc != TCP_OK) return rc;
-        if (dL_dQ && ns > 0)
-            TCP_HIP(d, hipMemcpyAsync(dL_dQ, d->adj_q, ns * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+        if (dL_dsource && ns > 0)
+            TCP_HIP(d, hipMemcpyAsync(dL_dsource, d->adj_q, 4 * ns * sizeof(double), hipMemcpyDeviceToHost,
+                                      d->stream));
         if (dL_dTw_bot)
             TCP_HIP(d, hipMemcpyAsync(dL_dTw_bot, d->adj_tw, ncol * sizeof(double), hipMemcpyDeviceToHost, d->stream));
         if (dL_dTw_top)

@@ -271,15 +271,15 @@ class Domain:
 
     def thermal_adjoint(self, nsteps: int, dL_dT):
         """Gradients of L = sum(dL_dT * T), T after nsteps warm-up updates (phi, u
-        held), with respect to the heat-source amplitudes and the wall
-        temperatures: (dQ[n_sources], dTw_bot[nz, nx], dTw_top[nz, nx])."""
+        held), with respect to the heat sources and the wall temperatures:
+        (dsrc[n_sources, 4] = dL/d(Q, x, y, z) per source, dTw_bot[nz, nx], dTw_top[nz, nx])."""
         m = np.ascontiguousarray(np.broadcast_to(np.asarray(dL_dT, dtype=np.float64), self.shape3))
-        dq = np.zeros(16)
+        dq = np.zeros(64)
         bot = np.zeros((self.nz, self.nx))
         top = np.zeros((self.nz, self.nx))
         self._check(self._lib.tcp_thermal_adjoint(self._h, int(nsteps), _dptr(m), _dptr(dq), _dptr(bot), _dptr(top)),
                     "thermal_adjoint")
-        return dq[:self.n_sources], bot, top
+        return dq[:4 * self.n_sources].reshape(self.n_sources, 4), bot, top
 
     # -- read-back ---------------------------------------------------------------------
     def get_field(self, name: str, out=None):
@@ -375,3 +375,38 @@ def domain_from_workload(cfg: dict, device: int = 0, temperature=None, velocity=
         d.set_heat_sources(cfg["heat_sources"])
     d.initialize()
     return d
+
+
+def thermal_warmup(domain: Domain, nsteps: int):
+    """The temperature warm-up as a differentiable function for torch.
+
+    Returns f(sources, tw_bot, tw_top) -> T: `sources` an (n, 6) float64 tensor
+    of heat sources (Q, x, y, z, w, d_cut), `tw_bot` / `tw_top` (nz, nx) wall
+    temperatures.  Each call restores the domain's state as it was when this
+    function was made, loads the inputs and runs nsteps warm-up updates (phi
+    and u held); T comes back as an (nz, ny, nx) float64 tensor.  The backward
+    pass is tcp_thermal_adjoint: gradients for Q, x, y, z of every source and
+    for both walls (w and d_cut get none)."""
+    import torch
+    snapshot = domain.save_state()
+
+    class _Warmup(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sources, tw_bot, tw_top):
+            domain.load_state(snapshot)
+            domain.set_heat_sources(sources.detach().cpu().numpy().tolist())
+            domain.set_wall_temperature(0, tw_bot.detach().cpu().numpy())
+            domain.set_wall_temperature(1, tw_top.detach().cpu().numpy())
+            domain.warm_temperature(nsteps, 0.0, max(int(nsteps), 1))
+            return torch.from_numpy(domain.get_field("T")).to(sources.device)
+
+        @staticmethod
+        def backward(ctx, grad_T):
+            dsrc, dbot, dtop = domain.thermal_adjoint(nsteps, grad_T.detach().cpu().numpy())
+            n = dsrc.shape[0]
+            g = torch.zeros((n, 6), dtype=torch.float64)
+            g[:, :4] = torch.from_numpy(dsrc)
+            dev = grad_T.device
+            return g.to(dev), torch.from_numpy(dbot).to(dev), torch.from_numpy(dtop).to(dev)
+
+    return _Warmup.apply

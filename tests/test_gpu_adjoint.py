@@ -20,7 +20,7 @@ def _case(q, precision, nx=12, ny=10, nz=6):
     cfg = W.make(shape=(nx, ny, nz), periodic_y=False, precision=precision, q_thermal=q, rho_l=0.5, xi=3.0,
                  kappa_h=0.25, kappa_l=0.1, t_wall_bot=0.3, t_wall_top=0.8,
                  droplets=[(5.3, 3.2, 2.7, 3.0)],
-                 heat_sources=[(0.02, 4.0, 2.0, 3.0, 3.0, 0.0), (0.01, 9.5, 7.0, 1.0, 2.0, 3.5)])
+                 heat_sources=[(0.02, 4.0, 2.0, 3.0, 3.0, 0.0), (0.01, 9.5, 7.0, 1.0, 2.0, 3.7)])
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
     u = [0.02 * np.sin(2 * np.pi * (x / nx + 0.3 * k)) * np.cos(np.pi * (y + 0.5) / ny) for k in range(3)]
     m = rng.uniform(-1.0, 1.0, (nz, ny, nx))
@@ -43,14 +43,25 @@ def _oracle_loss(cfg, phi, u, m, steps, sources, tw_bot, tw_top):
     return L
 
 
-def _oracle_gradient(cfg, phi, u, m, steps):
+def _oracle_gradient(cfg, phi, u, m, steps, h=1e-4):
+    """dL/dQ_k and dL/dT_w exactly (the loss at unit inputs), dL/d(x, y, z)_k by
+    central differences of Q_k L(unit amplitude k) in the source position (no
+    lattice cell lies within h of a cut-off sphere here)."""
     nx, ny, nz = cfg["shape"]
     zero = np.zeros((nz, nx))
     src = [list(s) for s in cfg["heat_sources"]]
     dq = []
     for k in range(len(src)):
         unit = [[1.0 if j == k else 0.0] + s[1:] for j, s in enumerate(src)]
-        dq.append(_oracle_loss(cfg, phi, u, m, steps, unit, zero, zero))
+        row = [_oracle_loss(cfg, phi, u, m, steps, unit, zero, zero)]
+        for ax in range(3):
+            lp, lm = [list(s) for s in unit], [list(s) for s in unit]
+            lp[k][1 + ax] += h
+            lm[k][1 + ax] -= h
+            dl = _oracle_loss(cfg, phi, u, m, steps, lp, zero, zero) - \
+                _oracle_loss(cfg, phi, u, m, steps, lm, zero, zero)
+            row.append(src[k][0] * dl / (2 * h))
+        dq.append(row)
     off = [[0.0] + s[1:] for s in src]
     tw = [np.zeros((nz, nx)), np.zeros((nz, nx))]
     for wall in (0, 1):
@@ -71,7 +82,9 @@ def _rel(a, b):
 def test_thermal_adjoint_matches_oracle_gradient(precision, q):
     """Walls, two heaters (one cut off), conductivity ratio 2.5 across a droplet,
     a held velocity field, random loss weights, 25 updates: dL/dQ and dL/dT_w
-    of both walls within 1e-11 (FP64) or 1e-5 (FP32) of the oracle's."""
+    of both walls within 1e-11 (FP64) or 1e-5 (FP32) of the oracle's, and the
+    source-position gradients within 1e-7 (FP64; the oracle's are central
+    differences) or 1e-5 (FP32)."""
     steps = 25
     cfg, u, m = _case(q, precision)
     g = gpu_domain(cfg, u=u, T=np.full(m.shape, 0.4))
@@ -79,9 +92,11 @@ def test_thermal_adjoint_matches_oracle_gradient(precision, q):
     dq, tb, tt = g.thermal_adjoint(steps, m)
     oq, ob, ot = _oracle_gradient(cfg, phi, u, m, steps)
     tol = 1e-11 if precision == "fp64" else 1e-5
-    errs = {"Q": _rel(dq, oq), "Tw_bot": _rel(tb, ob), "Tw_top": _rel(tt, ot)}
-    print(precision, q, errs, dq, oq)
+    errs = {"Q": _rel(dq[:, 0], oq[:, 0]), "Tw_bot": _rel(tb, ob), "Tw_top": _rel(tt, ot)}
+    pos = _rel(dq[:, 1:], oq[:, 1:])
+    print(precision, q, errs, "position", pos, dq, oq)
     assert all(v < tol for v in errs.values()), errs
+    assert pos < (1e-7 if precision == "fp64" else 1e-5), pos
     # the state is untouched and a second call gives the same gradients
     dq2, tb2, tt2 = g.thermal_adjoint(steps, m)
     assert np.array_equal(dq, dq2) and np.array_equal(tb, tb2) and np.array_equal(tt, tt2)
@@ -114,8 +129,39 @@ def test_thermal_adjoint_against_gpu_forward():
     for k in range(2):
         unit = [[1.0 if j == k else 0.0] + s[1:] for j, s in enumerate(src)]
         ref = loss(unit, 0.0, 0.0)
-        assert abs(dq[k] - ref) <= 1e-11 * abs(ref), (k, dq[k], ref)
+        assert abs(dq[k, 0] - ref) <= 1e-11 * abs(ref), (k, dq[k, 0], ref)
     off = [[0.0] + s[1:] for s in src]
     for wall, grad in ((0, tb), (1, tt)):
         ref = loss(off, 1.0 if wall == 0 else 0.0, 1.0 if wall == 1 else 0.0)
         assert abs(grad.sum() - ref) <= 1e-11 * abs(ref), (wall, grad.sum(), ref)
+
+
+def test_thermal_warmup_autograd():
+    """The torch wrapper: backward through a scalar loss gives the adjoint's
+    gradients, and a central difference of the wrapped forward in the first
+    source's x agrees with its x gradient (FP64)."""
+    import torch
+
+    from paper_2401_03041_amd import tcplb
+    nx, ny, nz = 16, 12, 8
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_thermal=7, kappa_h=0.2, kappa_l=0.1, rho_l=0.5,
+                 xi=3.0, droplets=[(7.3, 4.2, 3.7, 3.0)], t_wall_top=0.5,
+                 heat_sources=[(0.03, 6.0, 3.0, 4.0, 3.0, 0.0)])
+    g = gpu_domain(cfg)
+    f = tcplb.thermal_warmup(g, 40)
+    m = torch.from_numpy(np.random.default_rng(5).uniform(0.0, 1.0, (nz, ny, nx)))
+    src = torch.tensor([[0.03, 6.0, 3.0, 4.0, 3.0, 0.0]], dtype=torch.float64, requires_grad=True)
+    twb = torch.zeros((nz, nx), dtype=torch.float64, requires_grad=True)
+    twt = torch.full((nz, nx), 0.5, dtype=torch.float64, requires_grad=True)
+    loss = (f(src, twb, twt) * m).sum()
+    loss.backward()
+    dsrc, dbot, dtop = g.thermal_adjoint(40, m.numpy())
+    assert np.array_equal(src.grad[:, :4].numpy(), dsrc)
+    assert np.array_equal(twb.grad.numpy(), dbot) and np.array_equal(twt.grad.numpy(), dtop)
+    h = 1e-4
+    with torch.no_grad():
+        sp, sm = src.clone(), src.clone()
+        sp[0, 1] += h
+        sm[0, 1] -= h
+        fd = float(((f(sp, twb, twt) - f(sm, twb, twt)) * m).sum()) / (2 * h)
+    assert abs(fd - float(src.grad[0, 1])) <= 1e-6 * abs(fd), (fd, float(src.grad[0, 1]))
