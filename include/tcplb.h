@@ -194,10 +194,11 @@ int tcp_step(tcp_domain *d, int64_t nsteps);
 int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t check_every,
                          int64_t *steps_done, double *change);
 
-/* Adjoint of the temperature warm-up (thermal LB only).  With phi and u held
- * at their current values, nsteps thermal LB updates (Eq. lb_thermal with the
- * anti-bounce-back walls and the source of Eq. HeatSource) form an affine map
- * from the heat-source amplitudes Q_k and the wall temperatures to T.  For
+/* Adjoint of the temperature warm-up.  With phi and u held at their current
+ * values, nsteps thermal updates (the LB of Eq. lb_thermal with the
+ * anti-bounce-back walls, or the RK2 / RK4 stages of Eq. rk2 / rk4 with the
+ * wall ghosts; the source of Eq. HeatSource) form an affine map from the
+ * heat-source amplitudes Q_k and the wall temperatures to T.  For
  * the loss L = sum_x dL_dT[x] T(x) of the T reached after nsteps updates of
  * tcp_warm_temperature, this returns for every heat source, in the order of
  * tcp_set_heat_sources, four values dL/dQ_k, dL/dx_k, dL/dy_k, dL/dz_k
@@ -207,10 +208,10 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
  * The gradients do not depend on the current T or PDFs, which are left
  * untouched.  dL_dT: host array of nx*ny*nz values (cell order x fastest);
  * the three outputs are host arrays or NULL to skip.  One adjoint kernel per
- * update, last to first, in the storage precision of the domain with FP64
- * accumulation of the gradients; the workspace (two link-adjoint arrays of
- * the thermal PDF size, three FP64 fields) is allocated on the first call and
- * kept.  Synchronises.  TCP_ERR_UNSUPPORTED for the RK schemes. */
+ * LB update or RK stage, last to first, in the storage precision of the
+ * domain with FP64 accumulation of the gradients; the workspace (LB: two
+ * link-adjoint arrays of the thermal PDF size; RK: eight fields; and two FP64
+ * fields) is allocated on the first call and kept.  Synchronises. */
 int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dsource,
                         double *dL_dTw_bot, double *dL_dTw_top);
 

@@ -180,6 +180,31 @@ struct ThermalAdjointArgs {
     int last; // the first forward update: no earlier output to propagate to
 };
 
+// Adjoint of the RK2 / RK4 update with phi and u held: coeff holds a (three
+// fields) and kappa (one field) of the right-hand side; one stage launch per
+// reverse stage, reading lambda' (lam) and A^T kappa of the stage after it
+// (theta_in, null for the last stage), writing theta_out and acc.
+struct RkAdjointArgs {
+    Geometry geo;
+    const void *phi;
+    const void *u[3];
+    void *coeff;
+    const void *lam;
+    const void *theta_in;
+    void *theta_out;
+    void *acc;
+    double kappa_l, dkappa;
+    double wet[2];
+    double w_s, a_s; // kappa = w_s lambda' + a_s theta_in
+    int first;       // acc starts from lambda'
+    double *grad_q;
+    double *grad_twb, *grad_twt;
+};
+template <typename S, typename R>
+void launch_rk_adjoint_coeff(const RkAdjointArgs &a, hipStream_t s);
+template <typename S, typename R>
+void launch_rk_adjoint_stage(const RkAdjointArgs &a, hipStream_t s);
+
 // mu of the last update: dL/dfp_j(x) = m(x) for the loss sum_x m(x) T(x)
 template <int Q, typename S>
 void launch_adjoint_seed(const Geometry &g, const double *m, void *mu, hipStream_t s);

@@ -17,6 +17,20 @@
 //                 s0 = sum_i lambda_i w_i (1 + zeta_i),  s_a = sum_i lambda_i D_ia;
 // the source gets sum_i w_i lambda_i(x) per update, a wall column
 // 2 w_opp mu_opp(x) per reflected link.  The last update's T seeds mu = m.
+//
+// RK2 / RK4 with the flow held: R(theta) = A theta + b is affine, with
+//   (A theta)(c) = sum_k C_k(c) theta(c + e_k) - 6 kappa(c) (1 - w_0) theta(c),
+//   C_k(c) = w_k (3 a(c) . e_k + 6 kappa(c)),  a = -u + (kappa_H - kappa_L) grad phi,
+// the D3Q27 weights w_k, a neighbour across a wall replaced by its ghost
+// 2 T_w - theta(mirror cell), and b = q plus the ghosts' 2 C_k T_w.  For
+// T' = T + sum_s w_s K_s, K_s = R(theta_s), theta_1 = T, theta_{s+1} = T + a_s K_s
+// the reverse sweep over the stages is
+//   kappa_s = w_s lambda' + a_s A^T kappa_{s+1}   (s = S .. 1),
+//   lambda  = lambda' + sum_s A^T kappa_s,
+// with dL/dq(x) += kappa_s(x) and dL/dT_w += 2 C_k kappa_s over the ghost links.
+// A^T is applied as a gather: cell x collects C_k(x - e_k) kappa(x - e_k) over
+// the links that reach it, minus C_k(c) kappa(c) over the ghost links whose
+// mirror cell it is (c in its own row, shifted by -e_k in x and z).
 #include "kernels.hpp"
 
 namespace tcp {
@@ -180,7 +194,118 @@ __global__ void __launch_bounds__(kThreads) k_source_grad_final(const double *pa
     }
 }
 
+// a = -u + (kappa_H - kappa_L) grad phi and kappa(phi) per cell (phi and u
+// held), the coefficients of the RK right-hand side; grad phi with the
+// contact-angle ghosts as in the forward stages
+template <typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_rk_adj_coeff(const RkAdjointArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    const S *pp = static_cast<const S *>(a.phi);
+    R gp[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int i = 1; i < 27; ++i) {
+        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+        const R w = R(weight<27>(i));
+        R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+        if (nb.ghost(ey)) pv = nb.phi_ghost(pv, ey, a.wet);
+        gp[0] += R(ex) * w * pv;
+        gp[1] += R(ey) * w * pv;
+        gp[2] += R(ez) * w * pv;
+    }
+    S *co = static_cast<S *>(a.coeff);
+    const int64_t N = a.geo.N;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const R u = ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
+        st(elem(co + k * N, nb.c), -u + R(a.dkappa) * R(3) * gp[k]);
+    }
+    const R phic = fmin(fmax(ld<R>(elem(pp, nb.c)), R(0)), R(1));
+    st(elem(co + 3 * N, nb.c), R(a.kappa_l) + phic * R(a.dkappa));
+}
+
+// one reverse RK stage: kappa = w_s lambda' + a_s theta_in at every cell of the
+// stencil, theta_out = A^T kappa, acc = (first ? lambda' : acc) + theta_out
+template <typename S, typename R>
+__device__ __forceinline__ R rk_adj_kappa(const RkAdjointArgs &a, const S *lam, const S *thi, uint32_t c)
+{
+    R k = R(a.w_s) * ld<R>(elem(lam, c));
+    if (thi) k += R(a.a_s) * ld<R>(elem(thi, c));
+    return k;
+}
+
+template <typename S, typename R>
+__device__ __forceinline__ R rk_adj_coef(const RkAdjointArgs &a, const S *co, uint32_t c, int i)
+{
+    const int64_t N = a.geo.N;
+    const R ax = ld<R>(elem(co, c)), ay = ld<R>(elem(co + N, c)), az = ld<R>(elem(co + 2 * N, c));
+    const R kap = ld<R>(elem(co + 3 * N, c));
+    const R ae = R(vel27(i, 0)) * ax + R(vel27(i, 1)) * ay + R(vel27(i, 2)) * az;
+    return R(weight<27>(i)) * (R(3) * ae + R(6) * kap);
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_rk_adj_stage(const RkAdjointArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    const S *lam = static_cast<const S *>(a.lam);
+    const S *thi = static_cast<const S *>(a.theta_in);
+    const S *co = static_cast<const S *>(a.coeff);
+    const R k_own = rk_adj_kappa<S, R>(a, lam, thi, nb.c);
+    const R kap_own = ld<R>(elem(co + 3 * a.geo.N, nb.c));
+    R out = -R(6) * kap_own * R(1.0 - 8.0 / 27.0) * k_own;
+    R refl[2] = {R(0), R(0)}; // ghost links mirrored onto this cell: bottom, top
+#pragma unroll
+    for (int i = 1; i < 27; ++i) {
+        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+        if (!nb.ghost(-ey)) {
+            // the link from c = x - e_i reaches this cell
+            const uint32_t c = nb.at(-ex, -ey, -ez);
+            out += rk_adj_coef<S, R>(a, co, c, i) * rk_adj_kappa<S, R>(a, lam, thi, c);
+        }
+        if (nb.ghost(ey)) {
+            // the link from c = x - (e_x, 0, e_z) in this row leaves through the wall;
+            // its ghost mirrors onto this cell
+            const uint32_t c = nb.at(-ex, 0, -ez);
+            refl[ey > 0] += rk_adj_coef<S, R>(a, co, c, i) * rk_adj_kappa<S, R>(a, lam, thi, c);
+        }
+    }
+    out -= refl[0] + refl[1];
+    st(elem(static_cast<S *>(a.theta_out), nb.c), out);
+    S *acc = static_cast<S *>(a.acc);
+    st(elem(acc, nb.c), (a.first ? ld<R>(elem(lam, nb.c)) : ld<R>(elem(acc, nb.c))) + out);
+    a.grad_q[nb.c] += static_cast<double>(k_own);
+    if (nb.below || nb.above) {
+        const uint32_t col = nb.col(0, 0, a.geo);
+        if (nb.below) a.grad_twb[col] += 2.0 * static_cast<double>(refl[0]);
+        if (nb.above) a.grad_twt[col] += 2.0 * static_cast<double>(refl[1]);
+    }
+}
+
 } // namespace
+
+template <typename S, typename R>
+void launch_rk_adjoint_coeff(const RkAdjointArgs &a, hipStream_t s)
+{
+    const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_rk_adj_coeff<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+}
+
+template <typename S, typename R>
+void launch_rk_adjoint_stage(const RkAdjointArgs &a, hipStream_t s)
+{
+    const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_rk_adj_stage<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+}
+
+template void launch_rk_adjoint_coeff<double, double>(const RkAdjointArgs &, hipStream_t);
+template void launch_rk_adjoint_coeff<float, float>(const RkAdjointArgs &, hipStream_t);
+template void launch_rk_adjoint_stage<double, double>(const RkAdjointArgs &, hipStream_t);
+template void launch_rk_adjoint_stage<float, float>(const RkAdjointArgs &, hipStream_t);
 
 template <int Q, typename S>
 void launch_adjoint_seed(const Geometry &g, const double *m, void *mu, hipStream_t s)

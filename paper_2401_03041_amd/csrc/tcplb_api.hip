@@ -52,6 +52,9 @@ struct tcp_domain {
     // adjoints (bottom then top) and the per-source gradients
     void *adj_mu[2]{};
     double *adj_m = nullptr, *adj_g = nullptr, *adj_tw = nullptr, *adj_q = nullptr;
+    // RK schemes instead of adj_mu: lambda', acc, two stage fields, and the
+    // right-hand side's coefficients (a_x, a_y, a_z, kappa), N values each
+    void *adj_rk = nullptr;
 
     bool prof = false;
     std::vector<TimingRecord> records;
@@ -566,6 +569,50 @@ void run_thermal_adjoint(tcp_domain *d, int64_t nsteps)
     }
 }
 
+template <typename S>
+void run_rk_adjoint(tcp_domain *d, int64_t nsteps)
+{
+    const size_t N = (size_t)d->geo.N;
+    S *base = static_cast<S *>(d->adj_rk);
+    S *lam = base, *acc = base + N, *th[2] = {base + 2 * N, base + 3 * N};
+    RkAdjointArgs a{};
+    a.geo = d->geo;
+    a.phi = d->phi[d->cur];
+    for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+    a.coeff = base + 4 * N;
+    a.kappa_l = d->P.kappa_l;
+    a.dkappa = d->P.kappa_h - d->P.kappa_l;
+    a.wet[0] = wetting(d->P.contact_angle_bot, d->P.xi);
+    a.wet[1] = wetting(d->P.contact_angle_top, d->P.xi);
+    a.grad_q = d->adj_g;
+    a.grad_twb = d->adj_tw;
+    a.grad_twt = d->adj_tw + (size_t)d->P.nx * d->P.nz;
+    launch_rk_adjoint_coeff<S, S>(a, d->stream);
+    launch_from_f64<S>(d->adj_m, lam, (int64_t)N, d->stream);
+    // forward: T' = T + sum_s w_s K_s, K_s = R(theta_s), theta_{s+1} = T + a_s K_s
+    const bool rk4 = d->P.thermal == TCP_THERMAL_RK4;
+    const int ns = rk4 ? 4 : 2;
+    const double w4[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0}, a4[3] = {0.5, 0.5, 1.0};
+    const double w2[2] = {0.0, 1.0}, a2[1] = {0.5};
+    const double *w = rk4 ? w4 : w2, *an = rk4 ? a4 : a2;
+    for (int64_t n = 0; n < nsteps; ++n) {
+        a.lam = lam;
+        a.acc = acc;
+        int b = 0;
+        for (int st = ns - 1; st >= 0; --st) {
+            a.w_s = w[st];
+            a.a_s = st + 1 < ns ? an[st] : 0.0;
+            a.theta_in = st + 1 < ns ? th[1 - b] : nullptr;
+            a.theta_out = th[b];
+            a.first = st == ns - 1;
+            KernelTimer t(d, TCP_K_ADJOINT);
+            launch_rk_adjoint_stage<S, S>(a, d->stream);
+            b = 1 - b;
+        }
+        std::swap(lam, acc); // lambda of the update before
+    }
+}
+
 } // namespace
 
 extern "C" {
@@ -881,18 +928,24 @@ int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, doub
     if (!d) return TCP_ERR_ARG;
     if (nsteps < 0) return fail(d, TCP_ERR_ARG, "nsteps must be >= 0");
     if (!dL_dT) return fail(d, TCP_ERR_ARG, "dL_dT (one value per cell) is required");
-    if (d->P.thermal != TCP_THERMAL_LB) return fail(d, TCP_ERR_UNSUPPORTED, "the adjoint covers the thermal LB only");
     if (!d->initialized) return fail(d, TCP_ERR_STATE, "tcp_initialize must precede tcp_thermal_adjoint");
     return guarded(d, [&]() -> int {
         const size_t N = (size_t)d->geo.N, ncol = (size_t)d->P.nx * d->P.nz;
-        if (!d->adj_mu[0]) {
-            const size_t mb = (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->sb;
-            void *p[6] = {own(d, mb), own(d, mb), own(d, N * sizeof(double)), own(d, N * sizeof(double)),
-                          own(d, 2 * ncol * sizeof(double)), own(d, 4 * kMaxSources * sizeof(double))};
-            for (void *q : p)
-                if (!q) return fail(d, TCP_ERR_OOM, "device allocation failed (adjoint workspace)");
-            d->adj_mu[0] = p[0];
-            d->adj_mu[1] = p[1];
+        const bool lb = d->P.thermal == TCP_THERMAL_LB;
+        if (!d->adj_m) {
+            // link adjoints (LB) or eight fields (RK), then the FP64 buffers
+            const size_t mb = lb ? (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->sb : 8 * N * d->sb;
+            void *p[6] = {own(d, mb), lb ? own(d, mb) : nullptr, own(d, N * sizeof(double)),
+                          own(d, N * sizeof(double)), own(d, 2 * ncol * sizeof(double)),
+                          own(d, 4 * kMaxSources * sizeof(double))};
+            for (int k = 0; k < 6; ++k)
+                if (!p[k] && (k != 1 || lb)) return fail(d, TCP_ERR_OOM, "device allocation failed (adjoint workspace)");
+            if (lb) {
+                d->adj_mu[0] = p[0];
+                d->adj_mu[1] = p[1];
+            } else {
+                d->adj_rk = p[0];
+            }
             d->adj_m = static_cast<double *>(p[2]);
             d->adj_g = static_cast<double *>(p[3]);
             d->adj_tw = static_cast<double *>(p[4]);
@@ -902,7 +955,10 @@ int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, doub
         TCP_HIP(d, hipMemsetAsync(d->adj_g, 0, N * sizeof(double), d->stream));
         TCP_HIP(d, hipMemsetAsync(d->adj_tw, 0, 2 * ncol * sizeof(double), d->stream));
         const bool f64 = d->sb == 8;
-        switch (d->P.q_thermal) {
+        if (!lb) {
+            if (f64) run_rk_adjoint<double>(d, nsteps);
+            else run_rk_adjoint<float>(d, nsteps);
+        } else switch (d->P.q_thermal) {
         case 7: f64 ? run_thermal_adjoint<7, double>(d, nsteps) : run_thermal_adjoint<7, float>(d, nsteps); break;
         case 15: f64 ? run_thermal_adjoint<15, double>(d, nsteps) : run_thermal_adjoint<15, float>(d, nsteps); break;
         case 19: f64 ? run_thermal_adjoint<19, double>(d, nsteps) : run_thermal_adjoint<19, float>(d, nsteps); break;
@@ -1113,8 +1169,11 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     b[TCP_K_STEP] = d->P.thermal == TCP_THERMAL_LB
                         ? 2.0 * (d->P.q_pf + d->P.q_thermal) * pb + 54.0 * sb + 10.0 * sb
                         : 0.0;
-    // link adjoints in/out, u and phi in, the FP64 source adjoint read and written
-    b[TCP_K_ADJOINT] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * sb + 4.0 * sb + 16.0 : 0.0;
+    // per launch.  LB update: link adjoints in/out, u and phi in, the FP64
+    // source adjoint read and written.  RK stage: lambda', the next stage's
+    // field, four coefficient fields and acc in, acc and the stage field out,
+    // the FP64 source adjoint read and written.
+    b[TCP_K_ADJOINT] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * sb + 4.0 * sb + 16.0 : 9.0 * sb + 16.0;
     return TCP_OK;
 }
 

@@ -1,4 +1,4 @@
-"""Adjoint of the temperature warm-up (thermal LB with phi and u held) through the
+"""Adjoint of the temperature warm-up (thermal LB or RK, phi and u held) through the
 C interface, against gradients the oracle gives by definition: the warm-up is
 linear in the source amplitudes and the wall temperatures once the initial T is
 zero, so dL/dQ_k is L with Q = e_k (all else zero) and dL/dT_w at one column is
@@ -15,9 +15,10 @@ from tests.helpers import gpu_domain
 pytestmark = pytest.mark.gpu
 
 
-def _case(q, precision, nx=12, ny=10, nz=6):
+def _case(q, precision, thermal="lb", nx=12, ny=10, nz=6):
     rng = np.random.default_rng(7)
-    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, precision=precision, q_thermal=q, rho_l=0.5, xi=3.0,
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, precision=precision, q_thermal=q, thermal=thermal,
+                 rho_l=0.5, xi=3.0, contact_angle_bot=70.0,
                  kappa_h=0.25, kappa_l=0.1, t_wall_bot=0.3, t_wall_top=0.8,
                  droplets=[(5.3, 3.2, 2.7, 3.0)],
                  heat_sources=[(0.02, 4.0, 2.0, 3.0, 3.0, 0.0), (0.01, 9.5, 7.0, 1.0, 2.0, 3.7)])
@@ -78,15 +79,18 @@ def _rel(a, b):
     return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
 
 
-@pytest.mark.parametrize("precision,q", [("fp64", 7), ("fp64", 19), ("fp32", 7), ("fp32", 27)])
-def test_thermal_adjoint_matches_oracle_gradient(precision, q):
-    """Walls, two heaters (one cut off), conductivity ratio 2.5 across a droplet,
-    a held velocity field, random loss weights, 25 updates: dL/dQ and dL/dT_w
+@pytest.mark.parametrize("precision,q,thermal", [("fp64", 7, "lb"), ("fp64", 19, "lb"), ("fp32", 7, "lb"),
+                                                 ("fp32", 27, "lb"), ("fp64", 7, "rk2"), ("fp64", 7, "rk4"),
+                                                 ("fp32", 7, "rk4")])
+def test_thermal_adjoint_matches_oracle_gradient(precision, q, thermal):
+    """Walls (70-degree bottom wall), two heaters (one cut off), conductivity
+    ratio 2.5 across a droplet, a held velocity field, random loss weights, 25
+    updates of the LB or RK scheme: dL/dQ and dL/dT_w
     of both walls within 1e-11 (FP64) or 1e-5 (FP32) of the oracle's, and the
     source-position gradients within 1e-7 (FP64; the oracle's are central
     differences) or 1e-5 (FP32)."""
     steps = 25
-    cfg, u, m = _case(q, precision)
+    cfg, u, m = _case(q, precision, thermal)
     g = gpu_domain(cfg, u=u, T=np.full(m.shape, 0.4))
     phi = g.get_field("phi")
     dq, tb, tt = g.thermal_adjoint(steps, m)
@@ -94,7 +98,7 @@ def test_thermal_adjoint_matches_oracle_gradient(precision, q):
     tol = 1e-11 if precision == "fp64" else 1e-5
     errs = {"Q": _rel(dq[:, 0], oq[:, 0]), "Tw_bot": _rel(tb, ob), "Tw_top": _rel(tt, ot)}
     pos = _rel(dq[:, 1:], oq[:, 1:])
-    print(precision, q, errs, "position", pos, dq, oq)
+    print(precision, q, thermal, errs, "position", pos, dq, oq)
     assert all(v < tol for v in errs.values()), errs
     assert pos < (1e-7 if precision == "fp64" else 1e-5), pos
     # the state is untouched and a second call gives the same gradients
