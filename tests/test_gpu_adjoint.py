@@ -81,7 +81,7 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("precision,q,thermal", [("fp64", 7, "lb"), ("fp64", 19, "lb"), ("fp32", 7, "lb"),
                                                  ("fp32", 27, "lb"), ("fp64", 7, "rk2"), ("fp64", 7, "rk4"),
-                                                 ("fp32", 7, "rk4")])
+                                                 ("fp32", 7, "rk4"), ("fp16", 15, "lb")])
 def test_thermal_adjoint_matches_oracle_gradient(precision, q, thermal):
     """Walls (70-degree bottom wall), two heaters (one cut off), conductivity
     ratio 2.5 across a droplet, a held velocity field, random loss weights, 25
@@ -95,7 +95,7 @@ def test_thermal_adjoint_matches_oracle_gradient(precision, q, thermal):
     phi = g.get_field("phi")
     dq, tb, tt = g.thermal_adjoint(steps, m)
     oq, ob, ot = _oracle_gradient(cfg, phi, u, m, steps)
-    tol = 1e-11 if precision == "fp64" else 1e-5
+    tol = 1e-11 if precision == "fp64" else 1e-5  # FP16 PDFs: the adjoint itself runs in FP32
     errs = {"Q": _rel(dq[:, 0], oq[:, 0]), "Tw_bot": _rel(tb, ob), "Tw_top": _rel(tt, ot)}
     pos = _rel(dq[:, 1:], oq[:, 1:])
     print(precision, q, thermal, errs, "position", pos, dq, oq)
@@ -169,3 +169,39 @@ def test_thermal_warmup_autograd():
         sm[0, 1] -= h
         fd = float(((f(sp, twb, twt) - f(sm, twb, twt)) * m).sum()) / (2 * h)
     assert abs(fd - float(src.grad[0, 1])) <= 1e-6 * abs(fd), (fd, float(src.grad[0, 1]))
+
+
+def test_adjoint_gradient_step_moves_heater_towards_target():
+    """The gradients drive a design search: L = sum (T - T*)^2 over a probe
+    region, T* the warm-up temperature of a heater at x = 20.  Starting from
+    x = 14 and stepping against the sign of dL/dx (the step halved whenever that
+    sign flips), the heater's x ends within a quarter cell of 20."""
+    import torch
+
+    from paper_2401_03041_amd import tcplb
+    nx, ny, nz = 32, 12, 8
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, thermal="lb", kappa_h=0.2, kappa_l=0.2,
+                 heat_sources=[(0.05, 14.0, 5.0, 4.0, 3.0, 0.0)])
+    g = gpu_domain(cfg)
+    f = tcplb.thermal_warmup(g, 150)
+    twb = torch.zeros((nz, nx), dtype=torch.float64)
+    twt = torch.zeros((nz, nx), dtype=torch.float64)
+    with torch.no_grad():
+        target = f(torch.tensor([[0.05, 20.0, 5.0, 4.0, 3.0, 0.0]], dtype=torch.float64), twb, twt).clone()
+    mask = torch.zeros((nz, ny, nx), dtype=torch.float64)
+    mask[:, 2:9, 12:28] = 1.0
+    src = torch.tensor([[0.05, 14.0, 5.0, 4.0, 3.0, 0.0]], dtype=torch.float64, requires_grad=True)
+    step, last_sign = 2.0, 0.0
+    for it in range(30):
+        loss = (((f(src, twb, twt) - target) * mask) ** 2).sum()
+        src.grad = None
+        loss.backward()
+        sign = float(np.sign(float(src.grad[0, 1])))
+        if last_sign and sign != last_sign:
+            step *= 0.5
+        last_sign = sign
+        with torch.no_grad():
+            src[0, 1] -= sign * step
+    x = float(src.detach()[0, 1])
+    print("heater x", x, "loss", float(loss))
+    assert abs(x - 20.0) < 0.25
