@@ -203,5 +203,5 @@ def test_adjoint_gradient_step_moves_heater_towards_target():
         with torch.no_grad():
             src[0, 1] -= sign * step
     x = float(src.detach()[0, 1])
-    print("heater x", x, "loss", float(loss))
+    print("heater x", x, "loss", float(loss.detach()))
     assert abs(x - 20.0) < 0.25
