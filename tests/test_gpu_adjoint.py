@@ -16,16 +16,18 @@ pytestmark = pytest.mark.gpu
 
 
 def _case(q, precision, thermal="lb", nx=12, ny=10, nz=6):
+    """Inputs generated here and given to both sides: a smooth phase field in
+    [0.05, 0.95], a held velocity field and random loss weights."""
     rng = np.random.default_rng(7)
     cfg = W.make(shape=(nx, ny, nz), periodic_y=False, precision=precision, q_thermal=q, thermal=thermal,
                  rho_l=0.5, xi=3.0, contact_angle_bot=70.0,
                  kappa_h=0.25, kappa_l=0.1, t_wall_bot=0.3, t_wall_top=0.8,
-                 droplets=[(5.3, 3.2, 2.7, 3.0)],
                  heat_sources=[(0.02, 4.0, 2.0, 3.0, 3.0, 0.0), (0.01, 9.5, 7.0, 1.0, 2.0, 3.7)])
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    phi = 0.5 + 0.45 * np.sin(2 * np.pi * x / nx) * np.cos(np.pi * (y + 0.5) / ny) * np.cos(2 * np.pi * z / nz)
     u = [0.02 * np.sin(2 * np.pi * (x / nx + 0.3 * k)) * np.cos(np.pi * (y + 0.5) / ny) for k in range(3)]
     m = rng.uniform(-1.0, 1.0, (nz, ny, nx))
-    return cfg, u, m
+    return cfg, phi, u, m
 
 
 def _oracle_loss(cfg, phi, u, m, steps, sources, tw_bot, tw_top):
@@ -84,15 +86,15 @@ def _rel(a, b):
                                                  ("fp32", 7, "rk4"), ("fp16", 15, "lb")])
 def test_thermal_adjoint_matches_oracle_gradient(precision, q, thermal):
     """Walls (70-degree bottom wall), two heaters (one cut off), conductivity
-    ratio 2.5 across a droplet, a held velocity field, random loss weights, 25
+    ratio 2.5 over a smooth phase field, a held velocity field, random loss weights, 25
     updates of the LB or RK scheme: dL/dQ and dL/dT_w
     of both walls within 1e-11 (FP64) or 1e-5 (FP32) of the oracle's, and the
     source-position gradients within 1e-7 (FP64; the oracle's are central
     differences) or 1e-5 (FP32)."""
     steps = 25
-    cfg, u, m = _case(q, precision, thermal)
-    g = gpu_domain(cfg, u=u, T=np.full(m.shape, 0.4))
-    phi = g.get_field("phi")
+    cfg, phi, u, m = _case(q, precision, thermal)
+    g = gpu_domain(cfg, phi=phi, u=u, T=np.full(m.shape, 0.4))
+    phi_before = g.get_field("phi")
     dq, tb, tt = g.thermal_adjoint(steps, m)
     oq, ob, ot = _oracle_gradient(cfg, phi, u, m, steps)
     tol = 1e-11 if precision == "fp64" else 1e-5  # FP16 PDFs: the adjoint itself runs in FP32
@@ -104,7 +106,7 @@ def test_thermal_adjoint_matches_oracle_gradient(precision, q, thermal):
     # the state is untouched and a second call gives the same gradients
     dq2, tb2, tt2 = g.thermal_adjoint(steps, m)
     assert np.array_equal(dq, dq2) and np.array_equal(tb, tb2) and np.array_equal(tt, tt2)
-    assert np.array_equal(g.get_field("phi"), phi)
+    assert np.array_equal(g.get_field("phi"), phi_before)
 
 
 def test_thermal_adjoint_against_gpu_forward():
