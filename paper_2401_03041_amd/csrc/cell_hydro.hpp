@@ -31,6 +31,7 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
 
     // pull; halfway bounce-back, plus 2 w_i (e_i . u_w)/c_s^2 from a moving wall
     R g[27];
+    __builtin_amdgcn_s_setprio(kPullPriority);
 #pragma unroll
     for (int i = 0; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
@@ -43,6 +44,7 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
             g[i] = ld<R>(elem(pdf_row<27>(gs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     // zeroth, first and second raw moments from sums and differences of opposite pairs
     R ps = g[0], u0[3] = {R(0), R(0), R(0)};
     R mxx = R(0), myy = R(0), mzz = R(0), mxy = R(0), mxz = R(0), myz = R(0);

@@ -37,8 +37,10 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
         if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);
     }
 
-    // pull; a link that crosses a wall returns the cell's own opposite PDF
+    // pull; a link that crosses a wall returns the cell's own opposite PDF.
+    // The wave issues its PDF loads at raised priority (kPullPriority).
     R h[Q];
+    __builtin_amdgcn_s_setprio(kPullPriority);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
@@ -51,6 +53,7 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
             if (!wall) h[i] += R(weight<Q>(i)) * (pn[opposite<27>(index27<Q>(i))] - pn[0]);
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     // zeroth and first moments from sums and differences of opposite pairs
     // (with deviation storage h[] holds h - w phi^n(own): sum_i w_i = 1 adds
     // phi^n(own) to the zeroth moment, sum_i w_i e_i = 0 leaves the first)

@@ -27,6 +27,7 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
     // f[] holds f - w ts (constant shift) or f - w T^n(own) (deviation storage:
     // stored + w (T^n(source) - T^n(own)), exactly zero in a uniform region at rest)
     R f[Q];
+    __builtin_amdgcn_s_setprio(kPullPriority);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
@@ -43,6 +44,7 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
             }
         }
     }
+    __builtin_amdgcn_s_setprio(0);
     // zeroth and first moments from sums and differences of opposite pairs
     R Tp = f[0], j[3] = {R(0), R(0), R(0)};
 #pragma unroll

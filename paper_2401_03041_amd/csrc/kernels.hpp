@@ -77,6 +77,12 @@ struct RkArgs {
     HeatSources src;
 };
 
+// Wave priority (s_setprio) while a cell update issues its PDF pull: a wave
+// that is loading goes ahead of waves that are computing, which keeps more
+// loads in flight (measured +1 % on the fused FP32 step at 512^3, FP64
+// unchanged).
+constexpr int kPullPriority = 2;
+
 // Template parameters: P storage type of the phase-field / thermal PDFs, S
 // storage type of the hydrodynamic PDFs and of every field, R arithmetic type.
 //
