@@ -72,6 +72,7 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
     const R phi = ld<R>(elem(pp, nb.c));
     const R T = ld<R>(elem(tp, nb.c));
     R gp[3] = {R(0), R(0), R(0)}, gT[3] = {R(0), R(0), R(0)}, lap = R(0);
+    __builtin_amdgcn_s_setprio(kPullPriority);
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
@@ -91,6 +92,7 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
         if (ey) gT[1] += R(ey) * w * tv;
         if (ez) gT[2] += R(ez) * w * tv;
     }
+    __builtin_amdgcn_s_setprio(0);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         gp[k] *= R(3);

@@ -28,8 +28,11 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
     const P *hs = static_cast<const P *>(a.h_src);
     const PdfLanes<Q> pl(nb);
 
-    // phi^n on the 3x3x3 neighbourhood (contact-angle ghosts across walls)
+    // phi^n on the 3x3x3 neighbourhood (contact-angle ghosts across walls);
+    // the wave issues these loads and the PDF pull at raised priority
+    // (kPullPriority)
     const S *po = static_cast<const S *>(a.phi_old);
+    __builtin_amdgcn_s_setprio(kPullPriority);
     R pn[27];
 #pragma unroll
     for (int k = dev ? 0 : 1; k < 27; ++k) {
@@ -37,10 +40,8 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
         if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);
     }
 
-    // pull; a link that crosses a wall returns the cell's own opposite PDF.
-    // The wave issues its PDF loads at raised priority (kPullPriority).
+    // pull; a link that crosses a wall returns the cell's own opposite PDF
     R h[Q];
-    __builtin_amdgcn_s_setprio(kPullPriority);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);

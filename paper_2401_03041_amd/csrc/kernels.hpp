@@ -77,10 +77,10 @@ struct RkArgs {
     HeatSources src;
 };
 
-// Wave priority (s_setprio) while a cell update issues its PDF pull: a wave
-// that is loading goes ahead of waves that are computing, which keeps more
-// loads in flight (measured +1 % on the fused FP32 step at 512^3, FP64
-// unchanged).
+// Wave priority (s_setprio) while a cell update issues its PDF pull and its
+// stencil loads of phi and T: a wave that is loading goes ahead of waves that
+// are computing, which keeps more loads in flight (measured +2 to +2.5 % on
+// the fused FP32 step at 512^3).
 constexpr int kPullPriority = 2;
 
 // Template parameters: P storage type of the phase-field / thermal PDFs, S
