@@ -113,9 +113,9 @@ def run_gpu(cfg: dict, steps: int, warmup: int, precision: str, fuse: bool = Tru
 
 
 def adjoint_cost(cfg: dict, updates: int, precision: str) -> dict:
-    """Thermal LB update with phi and u held (the temperature warm-up) against one
-    update of its adjoint (tcp_thermal_adjoint), per-kernel HIP-event times, on
-    the same domain."""
+    """Thermal update with phi and u held (the temperature warm-up: the LB kernel,
+    or the RK stages) against its adjoint (tcp_thermal_adjoint), per update, from
+    per-kernel HIP-event times on the same domain."""
     import numpy as np
     import torch
 
@@ -127,7 +127,8 @@ def adjoint_cost(cfg: dict, updates: int, precision: str) -> dict:
     d.set_profiling(True)
     d.kernel_times()
     d.warm_temperature(updates, 0.0, updates + 1)
-    fwd = d.kernel_times()["thermal"]
+    fkey = "thermal" if cfg.get("thermal", "lb") == "lb" else "rk"
+    fwd = d.kernel_times()[fkey]
     d.thermal_adjoint(updates, m)
     adj = d.kernel_times()["adjoint"]
     d.set_profiling(False)
@@ -136,14 +137,18 @@ def adjoint_cost(cfg: dict, updates: int, precision: str) -> dict:
     d.close()
     del d
     torch.cuda.empty_cache()
-    f_ms, a_ms = fwd[0] / fwd[1], adj[0] / adj[1]
-    _log(f"{precision}: thermal update {f_ms:.3f} ms, adjoint update {a_ms:.3f} ms")
-    return {"kind": "thermal LB D3Q7 with phi and u held (temperature warm-up) and its adjoint",
+    # per update: the byte model counts a whole update, except an RK adjoint
+    # stage, which it counts per launch
+    f_ms, a_ms = fwd[0] / updates, adj[0] / updates
+    a_bytes = bpc["adjoint"] * (adj[1] / updates if fkey == "rk" else 1.0)
+    scheme = "thermal LB D3Q%d" % cfg.get("q_thermal", 7) if fkey == "thermal" else cfg["thermal"].upper()
+    _log(f"{precision} {scheme}: update {f_ms:.3f} ms, adjoint update {a_ms:.3f} ms")
+    return {"kind": f"{scheme} with phi and u held (temperature warm-up) and its adjoint",
             "updates": updates, "forward_ms_per_update": round(f_ms, 4), "adjoint_ms_per_update": round(a_ms, 4),
             "adjoint_over_forward": round(a_ms / f_ms, 3),
-            "forward_GBs": round(bpc["thermal"] * ncell / (f_ms * 1e-3) / 1e9, 1),
-            "adjoint_GBs": round(bpc["adjoint"] * ncell / (a_ms * 1e-3) / 1e9, 1),
-            "adjoint_bytes_per_cell": bpc["adjoint"]}
+            "forward_GBs": round(bpc[fkey] * ncell / (f_ms * 1e-3) / 1e9, 1),
+            "adjoint_GBs": round(a_bytes * ncell / (a_ms * 1e-3) / 1e9, 1),
+            "adjoint_bytes_per_cell_update": a_bytes}
 
 
 def roofline(res: dict, precision: str) -> dict:
@@ -321,6 +326,7 @@ def main() -> int:
     fp16 = run_gpu(cfg, fp16_steps, max(2, args.warmup // 4), "fp16") if fp16_steps > 0 else None
     adjoint = adjoint_cost(cfg, 20, "fp32")
     adjoint["adjoint_update_over_coupled_step"] = round(adjoint["adjoint_ms_per_update"] / fp32["ms_per_step"], 3)
+    adjoint["rk4"] = adjoint_cost(dict(cfg, thermal="rk4"), 10, "fp32")
     pblock = None if args.no_paper_block else paper_block(10, 2)
     base = None if args.no_cpu_baseline else cpu_baseline(cfg, args.oracle_box, args.oracle_steps)
 
