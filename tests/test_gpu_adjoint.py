@@ -15,11 +15,11 @@ from tests.helpers import gpu_domain
 pytestmark = pytest.mark.gpu
 
 
-def _case(q, precision, thermal="lb", nx=12, ny=10, nz=6):
+def _case(q, precision, thermal="lb", nx=12, ny=10, nz=6, periodic_y=False):
     """Inputs generated here and given to both sides: a smooth phase field in
     [0.05, 0.95], a held velocity field and random loss weights."""
     rng = np.random.default_rng(7)
-    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, precision=precision, q_thermal=q, thermal=thermal,
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=periodic_y, precision=precision, q_thermal=q, thermal=thermal,
                  rho_l=0.5, xi=3.0, contact_angle_bot=70.0,
                  kappa_h=0.25, kappa_l=0.1, t_wall_bot=0.3, t_wall_top=0.8,
                  heat_sources=[(0.02, 4.0, 2.0, 3.0, 3.0, 0.0), (0.01, 9.5, 7.0, 1.0, 2.0, 3.7)])
@@ -107,6 +107,27 @@ def test_thermal_adjoint_matches_oracle_gradient(precision, q, thermal):
     dq2, tb2, tt2 = g.thermal_adjoint(steps, m)
     assert np.array_equal(dq, dq2) and np.array_equal(tb, tb2) and np.array_equal(tt, tt2)
     assert np.array_equal(g.get_field("phi"), phi_before)
+
+
+@pytest.mark.parametrize("thermal,shape,periodic", [("lb", (12, 10, 6), True), ("rk4", (12, 10, 6), True),
+                                                    ("lb", (8, 2, 4), False), ("rk2", (8, 2, 4), False)])
+def test_thermal_adjoint_periodic_and_two_rows(thermal, shape, periodic):
+    """Periodic y (no wall gradients: exactly zero) and a two-row channel, the
+    smallest with walls (every cell next to a wall), FP64, against the oracle's
+    unit-input gradients."""
+    steps = 20
+    cfg, phi, u, m = _case(7, "fp64", thermal, *shape, periodic_y=periodic)
+    g = gpu_domain(cfg, phi=phi, u=u)
+    dq, tb, tt = g.thermal_adjoint(steps, m)
+    oq, ob, ot = _oracle_gradient(cfg, phi, u, m, steps)
+    def close(a, b):
+        return np.max(np.abs(a - b)) <= 1e-11 * np.max(np.abs(b))
+
+    assert close(dq[:, 0], oq[:, 0]), (dq, oq)
+    if periodic:
+        assert not tb.any() and not tt.any()
+    else:
+        assert close(tb, ob) and close(tt, ot), (tb, ob, tt, ot)
 
 
 def test_thermal_adjoint_against_gpu_forward():
