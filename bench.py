@@ -307,7 +307,7 @@ def main() -> int:
     ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernel")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: the single-GPU block is the unit this build "
+        print("bench.py runs on one GPU only: the single-GPU block is the unit it "
               "measures (--gpus 1)", file=sys.stderr)
         return 2
     if args.copy_calibration:

@@ -40,7 +40,7 @@ extern "C" {
 enum {
     TCP_OK = 0,
     TCP_ERR_ARG = -1,         /* invalid argument or parameter value */
-    TCP_ERR_UNSUPPORTED = -2, /* valid request this build does not implement */
+    TCP_ERR_UNSUPPORTED = -2, /* valid request the library does not implement */
     TCP_ERR_HIP = -3,         /* a HIP runtime call or kernel launch failed */
     TCP_ERR_OOM = -4,         /* device allocation failed */
     TCP_ERR_NONFINITE = -5,   /* a reduction met NaN or Inf in the phase field */
