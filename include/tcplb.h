@@ -210,7 +210,7 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
  * the three outputs are host arrays or NULL to skip.  One adjoint kernel per
  * LB update or RK stage, last to first, in the storage precision of the
  * domain with FP64 accumulation of the gradients; the workspace (LB: two
- * link-adjoint arrays of the thermal PDF size; RK: eight fields; and two FP64
+ * link-adjoint arrays of the thermal PDF size; RK: thirteen fields; and two FP64
  * fields) is allocated on the first call and kept.  Synchronises. */
 int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dsource,
                         double *dL_dTw_bot, double *dL_dTw_top);

@@ -30,7 +30,9 @@
 // with dL/dq(x) += kappa_s(x) and dL/dT_w += 2 C_k kappa_s over the ghost links.
 // A^T is applied as a gather: cell x collects C_k(x - e_k) kappa(x - e_k) over
 // the links that reach it, minus C_k(c) kappa(c) over the ghost links whose
-// mirror cell it is (c in its own row, shifted by -e_k in x and z).
+// mirror cell it is (c in its own row, shifted by -e_k in x and z).  A first
+// per-cell pass packs C_k(c) kappa(c) = w_k (e_k . B(c) + D(c)) into four
+// fields, so the gather reads four values per link.
 #include "kernels.hpp"
 
 namespace tcp {
@@ -226,59 +228,66 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_coeff(const RkAdjointArgs a
     st(elem(co + 3 * N, nb.c), R(a.kappa_l) + phic * R(a.dkappa));
 }
 
-// one reverse RK stage: kappa = w_s lambda' + a_s theta_in at every cell of the
-// stencil, theta_out = A^T kappa, acc = (first ? lambda' : acc) + theta_out
+// one reverse RK stage, first pass (per cell): kappa = w_s lambda' + a_s theta_in
+// and the packed link sources B = 3 kappa a, D = 6 kappa_diff kappa, so that
+// C_k(c) kappa(c) = w_k (e_k . B(c) + D(c)); packed = (B_x, B_y, B_z, D, kappa)
 template <typename S, typename R>
-__device__ __forceinline__ R rk_adj_kappa(const RkAdjointArgs &a, const S *lam, const S *thi, uint32_t c)
+__global__ void __launch_bounds__(kTX *kTY) k_rk_adj_pack(const RkAdjointArgs a, const Tiling t)
 {
-    R k = R(a.w_s) * ld<R>(elem(lam, c));
-    if (thi) k += R(a.a_s) * ld<R>(elem(thi, c));
-    return k;
-}
-
-template <typename S, typename R>
-__device__ __forceinline__ R rk_adj_coef(const RkAdjointArgs &a, const S *co, uint32_t c, int i)
-{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const uint32_t c = (uint32_t)x + (uint32_t)y * (uint32_t)a.geo.nx + (uint32_t)z * (uint32_t)a.geo.plane;
     const int64_t N = a.geo.N;
-    const R ax = ld<R>(elem(co, c)), ay = ld<R>(elem(co + N, c)), az = ld<R>(elem(co + 2 * N, c));
-    const R kap = ld<R>(elem(co + 3 * N, c));
-    const R ae = R(vel27(i, 0)) * ax + R(vel27(i, 1)) * ay + R(vel27(i, 2)) * az;
-    return R(weight<27>(i)) * (R(3) * ae + R(6) * kap);
+    R k = R(a.w_s) * ld<R>(elem(static_cast<const S *>(a.lam), c));
+    if (a.theta_in) k += R(a.a_s) * ld<R>(elem(static_cast<const S *>(a.theta_in), c));
+    const S *co = static_cast<const S *>(a.coeff);
+    S *pk = static_cast<S *>(a.packed);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) st(elem(pk + j * N, c), R(3) * k * ld<R>(elem(co + j * N, c)));
+    st(elem(pk + 3 * N, c), R(6) * k * ld<R>(elem(co + 3 * N, c)));
+    st(elem(pk + 4 * N, c), k);
 }
 
+// second pass (gather): theta_out = A^T kappa, acc = (first ? lambda' : acc) + theta_out
 template <typename S, typename R>
 __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_stage(const RkAdjointArgs a, const Tiling t)
 {
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
     const Nbr nb(a.geo, x, y, z);
-    const S *lam = static_cast<const S *>(a.lam);
-    const S *thi = static_cast<const S *>(a.theta_in);
-    const S *co = static_cast<const S *>(a.coeff);
-    const R k_own = rk_adj_kappa<S, R>(a, lam, thi, nb.c);
-    const R kap_own = ld<R>(elem(co + 3 * a.geo.N, nb.c));
-    R out = -R(6) * kap_own * R(1.0 - 8.0 / 27.0) * k_own;
+    const int64_t N = a.geo.N;
+    const S *pk = static_cast<const S *>(a.packed);
+    const S *bx = pk, *by = pk + N, *bz = pk + 2 * N, *dd = pk + 3 * N;
+    R out = -R(1.0 - 8.0 / 27.0) * ld<R>(elem(dd, nb.c));
     R refl[2] = {R(0), R(0)}; // ghost links mirrored onto this cell: bottom, top
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+        const R w = R(weight<27>(i));
         if (!nb.ghost(-ey)) {
             // the link from c = x - e_i reaches this cell
-            const uint32_t c = nb.at(-ex, -ey, -ez);
-            out += rk_adj_coef<S, R>(a, co, c, i) * rk_adj_kappa<S, R>(a, lam, thi, c);
+            R v = ld<R>(nb.ptr(dd, -ex, -ey, -ez));
+            if (ex) v += R(ex) * ld<R>(nb.ptr(bx, -ex, -ey, -ez));
+            if (ey) v += R(ey) * ld<R>(nb.ptr(by, -ex, -ey, -ez));
+            if (ez) v += R(ez) * ld<R>(nb.ptr(bz, -ex, -ey, -ez));
+            out += w * v;
         }
         if (nb.ghost(ey)) {
             // the link from c = x - (e_x, 0, e_z) in this row leaves through the wall;
             // its ghost mirrors onto this cell
-            const uint32_t c = nb.at(-ex, 0, -ez);
-            refl[ey > 0] += rk_adj_coef<S, R>(a, co, c, i) * rk_adj_kappa<S, R>(a, lam, thi, c);
+            R v = ld<R>(nb.ptr(dd, -ex, 0, -ez));
+            if (ex) v += R(ex) * ld<R>(nb.ptr(bx, -ex, 0, -ez));
+            v += R(ey) * ld<R>(nb.ptr(by, -ex, 0, -ez));
+            if (ez) v += R(ez) * ld<R>(nb.ptr(bz, -ex, 0, -ez));
+            refl[ey > 0] += w * v;
         }
     }
     out -= refl[0] + refl[1];
     st(elem(static_cast<S *>(a.theta_out), nb.c), out);
     S *acc = static_cast<S *>(a.acc);
+    const S *lam = static_cast<const S *>(a.lam);
     st(elem(acc, nb.c), (a.first ? ld<R>(elem(lam, nb.c)) : ld<R>(elem(acc, nb.c))) + out);
-    a.grad_q[nb.c] += static_cast<double>(k_own);
+    a.grad_q[nb.c] += static_cast<double>(ld<R>(elem(pk + 4 * N, nb.c)));
     if (nb.below || nb.above) {
         const uint32_t col = nb.col(0, 0, a.geo);
         if (nb.below) a.grad_twb[col] += 2.0 * static_cast<double>(refl[0]);
@@ -299,6 +308,7 @@ template <typename S, typename R>
 void launch_rk_adjoint_stage(const RkAdjointArgs &a, hipStream_t s)
 {
     const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_rk_adj_pack<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
     hipLaunchKernelGGL((k_rk_adj_stage<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
