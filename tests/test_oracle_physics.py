@@ -417,15 +417,16 @@ def test_temperature_warmup_with_uniform_source(thermal):
     assert np.array_equal(g0, o.get_pdfs("g"))
 
 
-def test_temperature_warmup_is_linear_in_sources_and_walls():
+@pytest.mark.parametrize("thermal", ["lb", "rk4"])
+def test_temperature_warmup_is_linear_in_sources_and_walls(thermal):
     """From T = 0 the warm-up map is linear in the source amplitudes and the wall
     temperatures (phi and u held): the T of a combined input is the sum of the
     T of its parts.  This is what lets the adjoint test take gradients as the
     loss at unit inputs."""
     nx, ny, nz = 10, 8, 4
     z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
-    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_thermal=15, kappa_h=0.25, kappa_l=0.1, rho_l=0.5,
-                 xi=3.0, droplets=[(4.3, 3.2, 1.7, 2.5)])
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_thermal=15, thermal=thermal, kappa_h=0.25,
+                 kappa_l=0.1, rho_l=0.5, xi=3.0, droplets=[(4.3, 3.2, 1.7, 2.5)])
     u = [0.02 * np.sin(2 * np.pi * x / nx), 0.01 * np.cos(np.pi * (y + 0.5) / ny), 0.0 * x]
 
     def run(q, tw):
