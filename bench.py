@@ -241,8 +241,8 @@ def _cpu_model() -> str:
 
 # The paper's own per-GPU figures for its coupled FP64 step on a 512 x 256 x 256
 # block (D3Q27 phase field and hydrodynamics; one node of four GPUs in the weak
-# scaling figures of Sec. 5, MLUPS per GPU, an MI250 "GPU" being the module) and
-# for the thermal sub-step alone (Sec. 5 comparison of the thermal schemes, GLUPS).
+# scaling figures of Sec. 4.3, MLUPS per GPU, an MI250 "GPU" being the module) and
+# for the thermal sub-step alone (Sec. 4.2 comparison of the thermal schemes, GLUPS).
 PAPER_COUPLED_MLUPS = {"A100": {"lb_d3q7": 1189.6, "rk2": 1190.9, "rk4": 1030.8},
                        "MI250": {"lb_d3q7": 1626.7, "rk2": 1472.5, "rk4": 1244.7}}
 PAPER_THERMAL_GLUPS = {"A100": {"lb_d3q7": 9.058, "lb_d3q15": 4.785, "lb_d3q19": 3.949, "lb_d3q27": 2.859,

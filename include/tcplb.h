@@ -139,46 +139,64 @@ typedef struct {
     double contact_angle_top; /*   measured through the heavy phase, in (0, 180); 90 = neutral */
 } tcp_params;
 
-/* Fill *p with defaults: 32^3 periodic, D3Q15 phase field, D3Q7 thermal LB,
+/* Passage: Sec. 2.1-2.3 (model parameters), Sec. 3.1 (channel parameters).
+ * Fill *p with defaults: 32^3 periodic, D3Q15 phase field, D3Q7 thermal LB,
  * FP64, unit densities, nu = 1/6, M = 0.05, xi = 5, no surface tension,
  * kappa = 0.2, omega_bulk = 1, normal_eps = 1e-6, t_shift = 0, contact angles
  * 90 degrees. */
 int tcp_params_default(tcp_params *p);
 
-/* Validate *p and allocate a domain.  Rejects (TCP_ERR_ARG) any relaxation
+/* Passage: Sec. 2.2 (relaxation rates of Eq. pflbm-tau and the viscosity
+ * law), Sec. 2.3 (Eq. thlbm-tau; the RK schemes of Eq. rk2 / rk4), Sec. 4.1
+ * (the PDF and field arrays that a step updates).
+ * Validate *p and allocate a domain.  Rejects (TCP_ERR_ARG) any relaxation
  * rate outside (0, 2), and for RK thermal updates kappa_max above the
  * real-axis stability bound of the isotropic Laplacian (2/5.78 for RK2,
  * 2.785/5.78 for RK4).  alloc: NULL uses hipMalloc/hipFree.  stream: a
  * hipStream_t (NULL: the default stream).  On success *out owns all device
  * state; release it with tcp_destroy. */
 int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tcp_domain **out);
+/* Passage: none (releases what tcp_create allocated).  Synchronises the
+ * domain's stream, frees every device buffer and the domain itself. */
 int tcp_destroy(tcp_domain *d);
 
-/* Copy one macroscopic field into the domain.  Exactly one of host (FP64
+/* Passage: Sec. 4.1 (phase field, velocity and temperature are the fields
+ * initialised before the first step).
+ * Copy one macroscopic field into the domain.  Exactly one of host (FP64
  * host array) or dev (FP64 device array) is non-NULL; both hold nx*ny*nz
  * values.  The library keeps no reference to the caller's array. */
 int tcp_set_field(tcp_domain *d, int which, const double *host, const void *dev);
 
-/* phi := max over droplets of 1/2 + 1/2 tanh(2 (r_k - dist_k) / xi)
+/* Passage: Sec. 3.1 (tanh interface profile), Sec. 3.2-3.3 (droplet set-ups).
+ * phi := max over droplets of 1/2 + 1/2 tanh(2 (r_k - dist_k) / xi)
  * (the tanh interface of Sec. 3.1), with minimum-image distances along the
  * periodic axes.  n = 0 sets phi = 0. */
 int tcp_set_droplets(tcp_domain *d, const tcp_droplet *drops, int n);
 
-/* Heat sources of Eq. HeatSource (at most 16); replaces any previous set. */
+/* Passage: Eq. HeatSource (Sec. 3.2).
+ * Heat sources of Eq. HeatSource (at most 16); replaces any previous set. */
 int tcp_set_heat_sources(tcp_domain *d, const tcp_heat_source *src, int n);
 
-/* Per-column wall temperature (walls_y = 1): wall 0 = bottom, 1 = top;
+/* Passage: Sec. 3.1 and Sec. 3.2 (Dirichlet temperature walls).
+ * Per-column wall temperature (walls_y = 1): wall 0 = bottom, 1 = top;
  * Tw holds nx*nz FP64 host values, index x + nx*z. */
 int tcp_set_wall_temperature(tcp_domain *d, int wall, const double *Tw);
 
-/* Set all PDFs to the equilibria of the current phi, u, T with p* = 0
+/* Passage: Sec. 4.1 (initialisation of the three PDF fields); the equilibria
+ * of Sec. 2.2 (h, g) and Eq. lb_thermal (f).
+ * Set all PDFs to the equilibria of the current phi, u, T with p* = 0
  * (Sec. 4.1 initialisation).  Must precede tcp_step. */
 int tcp_initialize(tcp_domain *d);
 
-/* Advance nsteps coupled time steps (asynchronous). */
+/* Passage: Algorithm 1 (thermal LB) and Algorithm 2 (RK): per step the
+ * phase-field update (Eq. lb_interface), the hydrodynamic update (Sec. 2.2)
+ * and the thermal update (Eq. lb_thermal, or Eq. rk2 / rk4), each with its
+ * boundary conditions (Sec. 4.1).
+ * Advance nsteps coupled time steps (asynchronous). */
 int tcp_step(tcp_domain *d, int64_t nsteps);
 
-/* Temperature initialisation by running the thermal solver on its own
+/* Passage: Sec. 4.1 (temperature initialised by running the thermal solver).
+ * Temperature initialisation by running the thermal solver on its own
  * (Sec. 4.1: phi and u are set statically, T by iterating the thermal
  * update until it settles).  Runs thermal updates (the LB of Eq. lb_thermal
  * or the RK stages of Eq. rk2 / rk4, heat sources and wall temperatures
@@ -194,7 +212,9 @@ int tcp_step(tcp_domain *d, int64_t nsteps);
 int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t check_every,
                          int64_t *steps_done, double *change);
 
-/* Adjoint of the temperature warm-up.  With phi and u held at their current
+/* Passage: Eq. lb_thermal, Eq. rk2 / rk4 and Eq. HeatSource (the map that is
+ * reversed); Sec. 3.3 (heater placement is the design question it serves).
+ * Adjoint of the temperature warm-up.  With phi and u held at their current
  * values, nsteps thermal updates (the LB of Eq. lb_thermal with the
  * anti-bounce-back walls, or the RK2 / RK4 stages of Eq. rk2 / rk4 with the
  * wall ghosts; the source of Eq. HeatSource) form an affine map from the
@@ -215,37 +235,46 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
 int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dsource,
                         double *dL_dTw_bot, double *dL_dTw_top);
 
-/* Read back one field as FP64 into host (synchronises) or dev (FP64 device
+/* Passage: Sec. 2.2 (phi, u, the normalised pressure p* and p = p* rho c_s^2,
+ * rho(phi)), Eq. lb_thermal (T = sum_i f_i).
+ * Read back one field as FP64 into host (synchronises) or dev (FP64 device
  * array of nx*ny*nz values, asynchronous); exactly one is non-NULL. */
 int tcp_get_field(tcp_domain *d, int which, double *host, void *dev);
 
-/* Post-collision PDFs of the current step, unshifted FP64, component-major:
+/* Passage: App. B (stencil order), Eq. lb_interface, Sec. 2.2, Eq. lb_thermal.
+ * Post-collision PDFs of the current step, unshifted FP64, component-major:
  * out[i*N + cell], i in the stencil order of App. B.  Synchronises. */
 int tcp_get_pdfs(tcp_domain *d, int which, double *host_out);
 
-/* FP64 diagnostics: mass = sum phi and centroid = sum phi x / sum phi with
+/* Passage: Sec. 3.2 and Sec. 3.3 (droplet centroid trajectories); Sec. 2.2
+ * (the conservative phase field: sum phi is the conserved mass).
+ * FP64 diagnostics: mass = sum phi and centroid = sum phi x / sum phi with
  * integer cell coordinates.  Synchronises.  TCP_ERR_NONFINITE if phi holds
  * NaN or Inf. */
 int tcp_reduce(tcp_domain *d, double *mass, double centroid[3]);
 
-/* Raw state (all PDF buffers and fields, storage precision) for checkpoint
+/* Passage: Sec. 4.1 (the state a step carries: three PDF fields, phi, u, T).
+ * Raw state (all PDF buffers and fields, storage precision) for checkpoint
  * and restart: tcp_state_bytes gives the size; save/load copy to/from a host
  * buffer of that size.  Loading restores a bitwise identical state. */
 int tcp_state_bytes(const tcp_domain *d, size_t *bytes);
 int tcp_save_state(tcp_domain *d, void *host);
 int tcp_load_state(tcp_domain *d, const void *host);
 
-/* Wait for all work enqueued on the domain's stream. */
+/* Passage: none (stream synchronisation).
+ * Wait for all work enqueued on the domain's stream. */
 int tcp_synchronize(tcp_domain *d);
 
-/* Per-kernel timing with HIP events on the domain's stream.  While enabled,
+/* Passage: Sec. 4.2 (per-kernel performance of the updates).
+ * Per-kernel timing with HIP events on the domain's stream.  While enabled,
  * every launch is bracketed by two events.  tcp_kernel_times synchronises,
  * writes the summed milliseconds and launch counts per TCP_K_* kind (arrays
  * of TCP_K_COUNT entries) and resets the counters. */
 int tcp_set_profiling(tcp_domain *d, int enabled);
 int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches);
 
-/* Fusion.  With the thermal LB (TCP_THERMAL_LB) a step runs as one kernel in
+/* Passage: Algorithm 1 (the order the fused kernel keeps per cell).
+ * Fusion.  With the thermal LB (TCP_THERMAL_LB) a step runs as one kernel in
  * which each thread updates its cell's phase field, hydrodynamics and
  * temperature in turn (no thread reads what another writes within a step, so
  * this is the same update as the three kernels of Algorithm 1, with fewer
@@ -253,7 +282,8 @@ int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches);
  * The RK schemes always run the separate kernels. */
 int tcp_set_fusion(tcp_domain *d, int enabled);
 
-/* Step graphs.  On small grids a step's few-microsecond kernels are bound by
+/* Passage: none (launch scheduling of Algorithm 1 / 2 steps).
+ * Step graphs.  On small grids a step's few-microsecond kernels are bound by
  * host launch cost; tcp_step then captures 16 steps into one HIP graph (on
  * first use, once per buffer parity) and replays it.  mode 0: never;
  * 1 (default): grids of at most 2^21 cells; 2: always.  Results are bitwise
@@ -261,17 +291,23 @@ int tcp_set_fusion(tcp_domain *d, int enabled);
  * enabled, and are rebuilt after tcp_set_heat_sources. */
 int tcp_set_graphs(tcp_domain *d, int mode);
 
-/* Bytes each kernel kind moves per cell by the algorithmic model (each PDF
+/* Passage: Sec. 4.2 (bytes per cell of the roofline model, 2Q+4 values for
+ * the D3Q7 thermal LB).
+ * Bytes each kernel kind moves per cell by the algorithmic model (each PDF
  * read and written once, each scalar field read or written once). */
 int tcp_algorithmic_bytes(const tcp_domain *d, double *bytes_per_cell);
 
-/* Practical HBM ceiling: allocate two device buffers of `bytes` each, copy
+/* Passage: Sec. 4.2 (memory bandwidth as the bound of the LB updates).
+ * Practical HBM ceiling: allocate two device buffers of `bytes` each, copy
  * one into the other `reps` times with a 16-byte-per-lane streaming kernel on
  * the default stream, and return the best copy rate (read + write bytes per
  * second, in GB/s).  Synchronises; frees its buffers before returning. */
 int tcp_bandwidth_probe(size_t bytes, int reps, double *gbs);
 
+/* Passage: none (error reporting).  Text of a TCP_* code. */
 const char *tcp_error_string(int code);
+/* Passage: none (error reporting).  Message of the last failed call on d, or
+ * of the last failed tcp_create / tcp_bandwidth_probe when d is NULL. */
 const char *tcp_last_error(const tcp_domain *d);
 
 #ifdef __cplusplus

@@ -936,7 +936,8 @@ int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, doub
         const size_t N = (size_t)d->geo.N, ncol = (size_t)d->P.nx * d->P.nz;
         const bool lb = d->P.thermal == TCP_THERMAL_LB;
         if (!d->adj_m) {
-            // link adjoints (LB) or eight fields (RK), then the FP64 buffers
+            // link adjoints (LB) or thirteen fields (RK: lambda', acc, two stage fields,
+            // four coefficients, five packed link sources), then the FP64 buffers
             const size_t mb = lb ? (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->sb : 13 * N * d->sb;
             void *p[6] = {own(d, mb), lb ? own(d, mb) : nullptr, own(d, N * sizeof(double)),
                           own(d, N * sizeof(double)), own(d, 2 * ncol * sizeof(double)),

@@ -385,23 +385,32 @@ def thermal_warmup(domain: Domain, nsteps: int):
     temperatures.  Each call restores the domain's state as it was when this
     function was made, loads the inputs and runs nsteps warm-up updates (phi
     and u held); T comes back as an (nz, ny, nx) float64 tensor.  The backward
-    pass is tcp_thermal_adjoint: gradients for Q, x, y, z of every source and
+    pass reloads that call's own inputs (another call may have run in between)
+    and runs tcp_thermal_adjoint: gradients for Q, x, y, z of every source and
     for both walls (w and d_cut get none)."""
     import torch
     snapshot = domain.save_state()
 
+    def load_inputs(src, bot, top):
+        domain.load_state(snapshot)
+        domain.set_heat_sources(src.tolist())
+        domain.set_wall_temperature(0, bot)
+        domain.set_wall_temperature(1, top)
+
     class _Warmup(torch.autograd.Function):
         @staticmethod
         def forward(ctx, sources, tw_bot, tw_top):
-            domain.load_state(snapshot)
-            domain.set_heat_sources(sources.detach().cpu().numpy().tolist())
-            domain.set_wall_temperature(0, tw_bot.detach().cpu().numpy())
-            domain.set_wall_temperature(1, tw_top.detach().cpu().numpy())
+            # the backward pass reloads these: the domain may have been given other
+            # inputs by another forward call in between
+            ctx.inputs = (sources.detach().cpu().numpy().copy(), tw_bot.detach().cpu().numpy().copy(),
+                          tw_top.detach().cpu().numpy().copy())
+            load_inputs(*ctx.inputs)
             domain.warm_temperature(nsteps, 0.0, max(int(nsteps), 1))
             return torch.from_numpy(domain.get_field("T")).to(sources.device)
 
         @staticmethod
         def backward(ctx, grad_T):
+            load_inputs(*ctx.inputs)
             dsrc, dbot, dtop = domain.thermal_adjoint(nsteps, grad_T.detach().cpu().numpy())
             n = dsrc.shape[0]
             g = torch.zeros((n, 6), dtype=torch.float64)

@@ -116,3 +116,40 @@ def test_warm_temperature_rejects_bad_arguments_without_a_domain():
     lib = tcplb.load()
     n, ch = C.c_int64(), C.c_double()
     assert lib.tcp_warm_temperature(None, 10, 0.0, 1, C.byref(n), C.byref(ch)) == -1  # TCP_ERR_ARG
+
+
+def _declaration_comments():
+    """(name, comment block directly above the declaration) for every entry point."""
+    text = open(HEADER).read()
+    out = []
+    for m in re.finditer(r"^\s*(?:const\s+)?\w+\s*\*?\s*(tcp_\w+)\s*\(", text, flags=re.M):
+        head = text[:m.start()].rstrip()
+        # declarations directly after another one share the comment above the first
+        while head.endswith(";") and "\n" in head:
+            head = head[:head.rindex("\n")].rstrip()
+        block = head[head.rindex("/*"):] if head.endswith("*/") else ""
+        out.append((m.group(1), block))
+    return out
+
+
+# calls that carry the paper's problem statement: each must cite a section,
+# equation, algorithm or appendix of the paper
+PAPER_CALLS = ("tcp_params_default", "tcp_create", "tcp_set_field", "tcp_set_droplets", "tcp_set_heat_sources",
+               "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_warm_temperature",
+               "tcp_thermal_adjoint", "tcp_get_field", "tcp_get_pdfs", "tcp_reduce")
+
+
+def test_every_declaration_names_its_passage():
+    """Each entry point's comment opens with 'Passage:' and either cites the
+    paper (Sec./Eq./Algorithm/App.) or says 'none' for a pure library utility;
+    the calls of the problem statement always cite."""
+    cite = re.compile(r"Sec\. \d|Eq\. \w|Algorithm \d|App\. [A-C]")
+    seen = set()
+    for name, block in _declaration_comments():
+        assert "Passage:" in block, f"{name}: no 'Passage:' line"
+        passage = block[block.index("Passage:"):].split(".  ", 1)[0]
+        assert cite.search(block) or "none" in passage, f"{name}: neither a citation nor 'none'"
+        if name in PAPER_CALLS:
+            assert cite.search(block), f"{name}: must cite the paper"
+        seen.add(name)
+    assert set(PAPER_CALLS) <= seen

@@ -194,6 +194,38 @@ def test_thermal_warmup_autograd():
     assert abs(fd - float(src.grad[0, 1])) <= 1e-6 * abs(fd), (fd, float(src.grad[0, 1]))
 
 
+def test_thermal_warmup_backward_uses_its_own_inputs():
+    """Two forward calls with different heaters (one source, then two) before
+    the backward pass of the first: its gradients are those of its own inputs,
+    not of the heaters the domain holds when backward runs."""
+    import torch
+
+    from paper_2401_03041_amd import tcplb
+    nx, ny, nz = 16, 12, 8
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_thermal=7, kappa_h=0.2, kappa_l=0.1, rho_l=0.5,
+                 xi=3.0, droplets=[(7.3, 4.2, 3.7, 3.0)], heat_sources=[])
+    g = gpu_domain(cfg)
+    f = tcplb.thermal_warmup(g, 30)
+    m = torch.from_numpy(np.random.default_rng(11).uniform(0.0, 1.0, (nz, ny, nx)))
+    twb = torch.zeros((nz, nx), dtype=torch.float64, requires_grad=True)
+    twt = torch.full((nz, nx), 0.5, dtype=torch.float64, requires_grad=True)
+    s1 = torch.tensor([[0.03, 6.0, 3.0, 4.0, 3.0, 0.0]], dtype=torch.float64, requires_grad=True)
+    s2 = torch.tensor([[0.05, 11.0, 6.0, 2.0, 2.5, 0.0], [0.02, 3.0, 8.0, 5.0, 3.5, 0.0]], dtype=torch.float64,
+                      requires_grad=True)
+    l1 = (f(s1, twb, twt) * m).sum()
+    l2 = (f(s2, twb * 0.5, twt) * m).sum()
+    l1.backward()
+    g1 = s1.grad.clone()
+    l2.backward()
+    g2 = s2.grad.clone()
+    # references: the adjoint called directly on each call's own heaters (phi and
+    # u are the held fields of the snapshot both calls start from)
+    for src, grad in ((s1, g1), (s2, g2)):
+        g.set_heat_sources(src.detach().numpy().tolist())
+        dsrc, _, _ = g.thermal_adjoint(30, m.numpy())
+        assert np.array_equal(grad[:, :4].numpy(), dsrc), (grad, dsrc)
+
+
 def test_adjoint_gradient_step_moves_heater_towards_target():
     """The gradients drive a design search: L = sum (T - T*)^2 over a probe
     region, T* the warm-up temperature of a heater at x = 20.  Starting from

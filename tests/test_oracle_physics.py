@@ -463,3 +463,78 @@ def test_temperature_warmup_split_runs_equal_one_run(thermal):
     b.step(1)
     for k in ("phi", "ux", "uy", "p", "T"):
         assert np.array_equal(a.get_field(k), b.get_field(k)), k
+
+
+# ---------------------------------------------------------------------------------------
+# Marangoni term of F_s (Sec. 2.1; readings R4, R5): size of the tangential stress
+# ---------------------------------------------------------------------------------------
+def _marangoni_column_momentum(xi, grad_t=0.01, sigma_t=-2e-3, rho_l=0.1):
+    """Flat layer at rest (interfaces normal to y), T = G x.  Returns the column sums
+    of rho u_x after one step over the interior columns, in units of sigma_T G."""
+    nx, ny = 16, 96
+    cfg = W.make(shape=(nx, ny, 1), xi=xi, sigma_ref=1e-3, sigma_t=sigma_t, t_ref=0.0, rho_h=1.0, rho_l=rho_l,
+                 nu_h=0.1, nu_l=0.1, kappa_h=0.01, kappa_l=0.01)
+    y = np.arange(ny, dtype=np.float64)
+    phi = np.broadcast_to(_tanh_layer(y, 24.3, 72.3, xi)[None, :, None], (1, ny, nx)).copy()
+    T = np.broadcast_to(grad_t * np.arange(nx, dtype=np.float64)[None, None, :], (1, ny, nx)).copy()
+    d = oracle_domain(cfg, phi=phi, T=T)
+    d.step(1)
+    col = (d.get_field("rho") * d.get_field("ux")).sum(axis=(0, 1))
+    return col[2:nx - 2] / (sigma_t * grad_t)  # away from the periodic seam of T
+
+
+def test_marangoni_stress_one_step_momentum():
+    """Each interface of a flat tanh layer in a temperature gradient G along it carries
+    the tangential force sigma_T G per unit area: 3/2 xi |grad phi|^2 integrates to one
+    across the interface (R4), mu_phi grad phi, F_p and F_mu have no tangential part
+    at rest, and the first step's velocity is u0 + F/(2 rho) with u0 = 0.  So the
+    column sum of rho u_x over the two interfaces is sigma_T G after one step, up to
+    the lattice sum of |grad phi|^2, whose error falls as 1/xi^2."""
+    r12 = _marangoni_column_momentum(12.0)
+    r8 = _marangoni_column_momentum(8.0)
+    assert np.ptp(r12) < 1e-12 and np.ptp(r8) < 1e-12  # every interior column alike
+    assert abs(r12[0] - 1.0) < 1e-2
+    assert 1.8 < (1.0 - r8[0]) / (1.0 - r12[0]) < 2.8  # (12/8)^2 = 2.25
+
+
+# ---------------------------------------------------------------------------------------
+# Initial interface profile (Sec. 3.1, reading R21)
+# ---------------------------------------------------------------------------------------
+def test_droplet_profile_along_a_ray():
+    """ora_set_droplets writes 1/2 + 1/2 tanh(2 (R - r)/xi) (Sec. 3.1's profile),
+    r the minimum-image distance on the periodic box."""
+    from oracle import oracle as O
+    n, xi, R = 40, 5.0, 11.0
+    cfg = W.make(shape=(n, n, n), xi=xi)
+    c = (13.25, 19.5, 21.75)
+    d = O.OracleDomain(cfg)
+    d.set_droplets([c + (R,)])
+    phi = d.get_field("phi")
+    x = np.arange(n, dtype=np.float64)
+    dx = (x - c[0] + n / 2) % n - n / 2  # minimum image across the periodic seam
+    r = np.sqrt(dx ** 2 + (19 - c[1]) ** 2 + (21 - c[2]) ** 2)
+    ref = 0.5 + 0.5 * np.tanh(2.0 * (R - r) / xi)
+    assert np.max(np.abs(phi[21, 19, :] - ref)) < 1e-14
+    d.close()
+
+
+def test_droplet_profile_is_the_stationary_interface():
+    """The interface written by ora_set_droplets is the equilibrium profile of the
+    conservative Allen-Cahn equation with the counter-term 4 phi (1 - phi)/xi
+    (Eq. phasefieldforce): a disk at rest stays put (drift 5e-3 in 200 steps from
+    the lattice), while the same disk with a width 10 % off relaxes visibly
+    (2e-2 and 3e-2 for +-10 %)."""
+    from oracle import oracle as O
+    n, xi, R = 48, 5.0, 12.0
+    cfg = W.make(shape=(n, n, 1), xi=xi, mobility=0.05)
+    c = (n - 1) / 2 + 0.21
+    d = O.OracleDomain(cfg)
+    d.set_droplets([(c, c + 0.13, 0.0, R)])
+    d.set_field("T", np.zeros((1, n, n)))
+    for k in ("ux", "uy", "uz"):
+        d.set_field(k, np.zeros((1, n, n)))
+    d.initialize()
+    p0 = d.get_field("phi")
+    d.step(200)
+    assert np.max(np.abs(d.get_field("phi") - p0)) < 1e-2
+    d.close()
