@@ -77,8 +77,9 @@ enum { TCP_FP64 = 0, TCP_FP32 = 1, TCP_FP16 = 2 };
 /* Kernel kinds reported by tcp_kernel_times and tcp_algorithmic_bytes:
  * the phase-field, hydrodynamic and thermal LB kernels, an RK stage, the
  * fused step (all three LB updates of a step in one kernel, see
- * tcp_set_fusion) and one update of the thermal adjoint
- * (tcp_thermal_adjoint). */
+ * tcp_set_fusion), one update of the thermal adjoint (tcp_thermal_adjoint)
+ * and one reverse step of the coupled adjoint (tcp_tape_adjoint: its three
+ * kernels together). */
 enum {
     TCP_K_PHASE = 0,
     TCP_K_HYDRO = 1,
@@ -86,7 +87,8 @@ enum {
     TCP_K_RK = 3,
     TCP_K_STEP = 4,
     TCP_K_ADJOINT = 5,
-    TCP_K_COUNT = 6
+    TCP_K_COUPLED_ADJOINT = 6,
+    TCP_K_COUNT = 7
 };
 
 typedef struct tcp_domain tcp_domain;
@@ -234,6 +236,40 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
  * fields) is allocated on the first call and kept.  Synchronises. */
 int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dsource,
                         double *dL_dTw_bot, double *dL_dTw_top);
+
+/* Passage: Algorithm 1 (the steps that are taped); Sec. 3.3 (heater design
+ * by the droplet's capture, which the gradients of tcp_tape_adjoint serve).
+ * Advance nsteps coupled steps exactly as tcp_step does, and keep what their
+ * adjoint needs: the state (all PDFs, phi, T, u) at the start of every
+ * segment of `segment` steps (segment <= 0: ceil(sqrt(nsteps))), and the heat
+ * sources and wall temperatures in force.  Replaces any earlier tape; the
+ * device memory (nseg + segment + 1 states plus the reverse sweep's
+ * workspace, about 2.2 states) is allocated through the domain's allocator on
+ * the first call and again when the sizes change.  Thermal LB only
+ * (TCP_ERR_UNSUPPORTED for RK).  Asynchronous.  TCP_ERR_ARG for nsteps < 1,
+ * TCP_ERR_STATE before tcp_initialize. */
+int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment);
+
+/* Passage: Algorithm 1 and the updates it runs (Eq. lb_interface, Sec. 2.2,
+ * Eq. lb_thermal, Eq. HeatSource), reversed; Sec. 3.3 (the droplet centroid
+ * as the outcome of a capture set-up).
+ * Adjoint of the taped run.  The loss depends on the final phase field phi^N
+ * through its centroid c = sum phi x / sum phi (integer cell coordinates, as
+ * tcp_reduce) and, optionally, directly: dL/dphi^N(x) =
+ * dL_dcentroid . (x - c) / sum phi + dL_dphi[x] (dL_dphi: host FP64 array of
+ * nx*ny*nz values, or NULL).  Returns, as tcp_thermal_adjoint does, dL/dQ_k,
+ * dL/dx_k, dL/dy_k, dL/dz_k for every taped heat source (dL_dsource, 4 per
+ * source) and dL/dT_w of every column of the bottom and top walls (nx*nz
+ * values each, x fastest); each output may be NULL.  Each segment is
+ * recomputed from its checkpoint, then undone step by step, last to first,
+ * with three reverse kernels per step (thermal, hydrodynamic, phase field:
+ * recompute of the cell's update and its vector-Jacobian product, with link
+ * and stencil adjoints gathered from the neighbours); arithmetic in the
+ * domain's precision (FP32 for FP16 PDFs), gradient sums in FP64.  The
+ * domain's current state is not touched.  Synchronises.  TCP_ERR_STATE
+ * without a tape; TCP_ERR_ARG for a missing or non-finite dL_dcentroid. */
+int tcp_tape_adjoint(tcp_domain *d, const double dL_dcentroid[3], const double *dL_dphi, double *dL_dsource,
+                     double *dL_dTw_bot, double *dL_dTw_top);
 
 /* Passage: Sec. 2.2 (phi, u, the normalised pressure p* and p = p* rho c_s^2,
  * rho(phi)), Eq. lb_thermal (T = sum_i f_i).

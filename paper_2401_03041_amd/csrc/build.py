@@ -12,7 +12,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libtcplb.so")
 SOURCES = ["kernels_pf.hip", "kernels_hydro.hip", "kernels_thermal.hip", "kernels_step.hip", "kernels_aux.hip",
-           "kernels_adjoint.hip", "tcplb_api.hip"]
+           "kernels_adjoint.hip", "kernels_coupled_adjoint.hip", "tcplb_api.hip"]
 ARCH = os.environ.get("TCP_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-Wall",
          # keep the compiler from emitting packed FP32 instructions

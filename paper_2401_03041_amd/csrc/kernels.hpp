@@ -2,6 +2,7 @@
 // kernels (internal to the library; the public interface is tcplb.h).
 #pragma once
 
+#include "adjoint_math.hpp"
 #include "lattice.hpp"
 
 namespace tcp {
@@ -226,6 +227,52 @@ constexpr int kSourceGradBlocks = 64;
 static_assert(4 * kMaxSources * kSourceGradBlocks <= 4 * kReduceBlocks, "shares the reduction's partial buffer");
 void launch_source_grad(const Geometry &g, const HeatSources &hs, const double *grad_q, double *partial,
                         double *out, hipStream_t s);
+
+// ---- adjoint of the coupled step (kernels_coupled_adjoint.hip) -------------
+// One stored state of the coupled step (time level n): the three PDF fields
+// (storage layout of the domain), phi^n, T^n and u^n.
+struct StateSlot {
+    void *h, *g, *f, *phi, *T;
+    void *u[3];
+};
+
+// Reverse of step n -> n+1.  s0 holds state n, s1 state n+1.  The carried
+// adjoint (type S): link adjoints mu of h, g, f (blocked like the PDFs; src
+// from step n+1, dst for step n), sphi (five fields: dL/d grad phi (3),
+// dL/d lap phi, dL/d phi at the cell) and sT (four fields: dL/d grad T (3),
+// dL/d T at the cell) of the stencil reads of K1/K2, lu1 = dL/du from K1 (in
+// place); lu3 / lphi3 pass K3's local adjoints of u^{n+1} and phi^{n+1} to
+// R2 / R1.  grad_q (per cell) and the wall-column adjoints accumulate in FP64.
+struct CoupledAdjointArgs {
+    Geometry geo;
+    StateSlot s0, s1;
+    const void *mu_src[3];
+    void *mu_dst[3];
+    const void *sphi_src;
+    void *sphi_dst;
+    const void *sT_src;
+    void *sT_dst;
+    void *lu1, *lu3, *lphi3;
+    const double *twb, *twt;
+    double uw_bot[3], uw_top[3];
+    double wet[2];
+    double t_shift;
+    PfCoef pf;
+    HyCoef hy;
+    ThCoef th;
+    double *grad_q, *grad_twb, *grad_twt;
+};
+template <int QH, int QF, typename P, typename S, typename R>
+void launch_coupled_adjoint_step(const CoupledAdjointArgs &a, hipStream_t s);
+// sphi of the last step from the centroid gradient dL/dc (gc) and an optional
+// per-cell dL/dphi (dphi, FP64 device array or null); out4 holds the FP64
+// sums of launch_reduce for the final phi
+template <typename S>
+void launch_coupled_adjoint_seed(const Geometry &g, const double *out4, const double gc[3], const double *dphi,
+                                 void *sphi, hipStream_t s);
+// wall-temperature adjoint of the T ghosts read in the first step (sT of step 0)
+template <typename S>
+void launch_coupled_adjoint_tw(const Geometry &g, const void *sT, double *grad_twb, double *grad_twt, hipStream_t s);
 
 // streaming copy of n16 16-byte words (bandwidth probe)
 void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);

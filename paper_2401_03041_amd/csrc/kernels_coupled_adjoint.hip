@@ -1,0 +1,469 @@
+// kernels_coupled_adjoint.hip -- reverse (adjoint) kernels of one coupled
+// time step with the thermal LB: phase field (K1), hydrodynamics (K2) and
+// thermal LB (K3) of Algorithm 1, run backwards K3 -> K2 -> K1.
+//
+// Notation for step n -> n+1 (time levels of the forward kernels): K1 reads
+// the pulled h, the stencil of phi^n and u^n(x) and writes h*, phi^{n+1};
+// K2 reads the pulled g and the stencils of phi^n and T^n and writes g*,
+// u^{n+1}; K3 reads the pulled f, u^{n+1}(x), phi^{n+1}(x) and writes f*,
+// T^{n+1}.  The adjoint carried from step n+1 back to step n is, per cell:
+//   mu_h, mu_g, mu_f  dL/d(pulled PDFs) of step n+1 (blocked like the PDFs);
+//   sphi = (Gamma_x, Gamma_y, Gamma_z, Lambda, Pi): dL/d of the isotropic
+//          gradient and Laplacian of phi^{n+1} at the cell and dL/d of the
+//          cell's own phi^{n+1} as K2 of step n+1 reads it;
+//   sT   = (GammaT_x, GammaT_y, GammaT_z, PiT): the same for T^{n+1};
+//   lu1  = dL/du^{n+1} from K1 of step n+1.
+// Reverse step n, each kernel one thread per cell:
+//   R3 gathers dL/df*^{n+1}(x, i) = mu_f(x + e_i, i) (or -mu_f(x, opp i)
+//      across a wall: anti-bounce-back) and dL/dT^{n+1}(x) from sT (the
+//      transpose of the gradient stencil, with the wall ghosts 2 T_w - T),
+//      recomputes K3 of step n at x and runs it backwards: mu_f, the local
+//      adjoints of u^{n+1}, phi^{n+1} (lu3, lphi3), the heat-source adjoint
+//      sum_i w_i dL/df*_i and the wall-temperature adjoints of the reflected
+//      links and of the ghosts;
+//   R2 gathers dL/dg*^{n+1} (bounce-back across walls), adds lu1 + lu3 for
+//      u^{n+1}, recomputes K2 and writes mu_g, sphi and sT of step n;
+//   R1 gathers dL/dh*^{n+1} and dL/dphi^{n+1} (transposed gradient and
+//      Laplacian of sphi, with the derivative of the contact-angle ghost,
+//      plus lphi3), recomputes K1, writes mu_h and lu1 and adds its gradient
+//      adjoint to sphi's Gamma.
+// Every gather reads values a cell's neighbours wrote in an earlier launch,
+// so there are no atomics and the result does not depend on scheduling.
+#include "adjoint_math.hpp"
+#include "kernels.hpp"
+
+namespace tcp {
+
+namespace {
+
+template <int Q, typename A>
+__device__ __forceinline__ A *mu_at(A *base, const Geometry &g, const Nbr &nb, const PdfLanes<Q> &pl, int i, int dx,
+                                    int dy, int dz)
+{
+    return elem(pdf_row<Q>(base, g, nb.yr[1 + dy], nb.zi[1 + dz], i), pl.xq[1 + dx]);
+}
+
+// dL/d(post-collision PDF i at this cell) from the link adjoints of the next
+// step: the link leads to x + e_i, or back into the cell's own opposite
+// direction where x + e_i lies across a wall (sign -1 for anti-bounce-back)
+template <int Q, typename A, typename R, bool WALL>
+__device__ __forceinline__ void gather_links(const A *mu, const Geometry &g, const Nbr &nb, R sign_wall, R a[Q])
+{
+    const PdfLanes<Q> pl(nb);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        if (WALL && nb.ghost(ey))
+            a[i] = sign_wall * ld<R>(mu_at<Q>(mu, g, nb, pl, opposite<Q>(i), 0, 0, 0));
+        else
+            a[i] = ld<R>(mu_at<Q>(mu, g, nb, pl, i, ex, ey, ez));
+    }
+}
+
+template <int Q, typename A, typename R>
+__device__ __forceinline__ void store_links(A *mu, const Geometry &g, const Nbr &nb, const R m[Q])
+{
+    const PdfLanes<Q> pl(nb);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) st(mu_at<Q>(mu, g, nb, pl, i, 0, 0, 0), m[i]);
+}
+
+// ---------------------------------------------------------------------------
+// R3: thermal LB
+// ---------------------------------------------------------------------------
+template <int Q, typename P, typename S, typename R, bool WALL>
+__device__ __forceinline__ void adj_thermal_cell(const CoupledAdjointArgs &a, const Nbr &nb, int x, int y, int z)
+{
+    constexpr bool dev = deviation_storage<P>();
+    const Geometry &g = a.geo;
+    const int64_t N = g.N;
+    const uint32_t col = nb.col(0, 0, g);
+
+    // dL/df*^{n+1}
+    R lam[Q];
+    gather_links<Q, S, R, WALL>(static_cast<const S *>(a.mu_src[2]), g, nb, R(-1), lam);
+
+    // dL/dT^{n+1}: own PiT plus the transposed gradient stencil of K2 of step n+1
+    const S *sT = static_cast<const S *>(a.sT_src);
+    R aT = ld<R>(elem(sT + 3 * N, nb.c));
+    R ghost_sum[2] = {R(0), R(0)};
+#pragma unroll
+    for (int k = 1; k < 27; ++k) {
+        const int ex = vel27(k, 0), ey = vel27(k, 1), ez = vel27(k, 2);
+        const R w3 = R(3.0 * weight<27>(k));
+        if (!(WALL && nb.ghost(-ey))) {
+            R v = R(0);
+            if (ex) v += R(ex) * ld<R>(nb.ptr(sT, -ex, -ey, -ez));
+            if (ey) v += R(ey) * ld<R>(nb.ptr(sT + N, -ex, -ey, -ez));
+            if (ez) v += R(ez) * ld<R>(nb.ptr(sT + 2 * N, -ex, -ey, -ez));
+            aT += w3 * v;
+        }
+        if (WALL && nb.ghost(ey)) {
+            // the link of the cell x - (e_x, 0, e_z) that leaves through the wall
+            // reads the ghost 2 T_w - T of this cell
+            R v = R(0);
+            if (ex) v += R(ex) * ld<R>(nb.ptr(sT, -ex, 0, -ez));
+            v += R(ey) * ld<R>(nb.ptr(sT + N, -ex, 0, -ez));
+            if (ez) v += R(ez) * ld<R>(nb.ptr(sT + 2 * N, -ex, 0, -ez));
+            ghost_sum[ey > 0] += w3 * v;
+        }
+    }
+    double gtw[2] = {0.0, 0.0};
+    if (WALL) {
+        aT -= ghost_sum[0] + ghost_sum[1];
+        gtw[0] = 2.0 * (double)ghost_sum[0];
+        gtw[1] = 2.0 * (double)ghost_sum[1];
+    }
+
+    // recompute K3 of step n: pulled f (actual values, anti-bounce-back)
+    const P *fs = static_cast<const P *>(a.s0.f);
+    const S *to = static_cast<const S *>(a.s0.T);
+    const PdfLanes<Q> pl(nb);
+    const R t_own = dev ? ld<R>(elem(to, nb.c)) : R(0);
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        const R w = R(weight<Q>(i));
+        if (WALL && nb.ghost(-ey)) {
+            const double *tw = ey > 0 ? a.twb : a.twt;
+            const R fo = ld<R>(elem(pdf_row<Q>(fs, g, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1])) +
+                         w * (dev ? t_own : R(a.t_shift));
+            f[i] = R(2) * w * R(tw[col]) - fo;
+        } else {
+            f[i] = ld<R>(elem(pdf_row<Q>(fs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+            f[i] += w * (dev ? ld<R>(nb.ptr(to, -ex, -ey, -ez)) : R(a.t_shift));
+        }
+    }
+    R u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.s1.u[k]), nb.c));
+    const R phi = ld<R>(elem(static_cast<const S *>(a.s1.phi), nb.c));
+
+    R mu[Q], au[3], aphi, aq;
+    thermal_vjp<Q, R>(a.th, f, u, phi, lam, aT, mu, au, aphi, aq);
+    store_links<Q, S, R>(static_cast<S *>(a.mu_dst[2]), g, nb, mu);
+    S *lu3 = static_cast<S *>(a.lu3);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) st(elem(lu3 + k * N, nb.c), au[k]);
+    st(elem(static_cast<S *>(a.lphi3), nb.c), aphi);
+    a.grad_q[nb.c] += (double)aq;
+    if (WALL) {
+        // anti-bounce-back links of step n: f_i = 2 w_i T_w - f*_opp
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ey = vel<Q>(i, 1);
+            if (nb.ghost(-ey)) gtw[ey < 0] += 2.0 * weight<Q>(i) * (double)mu[i];
+        }
+        if (nb.below) a.grad_twb[col] += gtw[0];
+        if (nb.above) a.grad_twt[col] += gtw[1];
+    }
+}
+
+template <int Q, typename P, typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_adj_thermal(const CoupledAdjointArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    if (nb.below || nb.above)
+        adj_thermal_cell<Q, P, S, R, true>(a, nb, x, y, z);
+    else
+        adj_thermal_cell<Q, P, S, R, false>(a, nb, x, y, z);
+}
+
+// ---------------------------------------------------------------------------
+// R2: hydrodynamics
+// ---------------------------------------------------------------------------
+template <typename S, typename R, bool WALL>
+__device__ __forceinline__ void adj_hydro_cell(const CoupledAdjointArgs &a, const Nbr &nb)
+{
+    const Geometry &g = a.geo;
+    const int64_t N = g.N;
+    R lam[27];
+    gather_links<27, S, R, WALL>(static_cast<const S *>(a.mu_src[1]), g, nb, R(1), lam);
+    R au[3];
+    const S *lu1 = static_cast<const S *>(a.lu1), *lu3 = static_cast<const S *>(a.lu3);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) au[k] = ld<R>(elem(lu1 + k * N, nb.c)) + ld<R>(elem(lu3 + k * N, nb.c));
+
+    // recompute K2 of step n: pulled g (bounce-back, moving wall)
+    const S *gs = static_cast<const S *>(a.s0.g);
+    const PdfLanes<27> pl(nb);
+    R gp[27];
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+        if (WALL && nb.ghost(-ey)) {
+            const double *uw = ey > 0 ? a.uw_bot : a.uw_top;
+            const double eu = ex * uw[0] + ey * uw[1] + ez * uw[2];
+            gp[i] = ld<R>(elem(pdf_row<27>(gs, g, nb.yr[1], nb.zi[1], opposite<27>(i)), pl.xq[1])) +
+                    R(6.0 * weight<27>(i) * eu);
+        } else {
+            gp[i] = ld<R>(elem(pdf_row<27>(gs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+        }
+    }
+    // stencils of phi^n and T^n (wall ghosts as in the forward kernel)
+    const S *pp = static_cast<const S *>(a.s0.phi);
+    const S *tp = static_cast<const S *>(a.s0.T);
+    HyIn<R> in;
+    in.phi = ld<R>(elem(pp, nb.c));
+    in.T = ld<R>(elem(tp, nb.c));
+    R lap = R(0);
+    for (int k = 0; k < 3; ++k) in.gp[k] = in.gT[k] = R(0);
+#pragma unroll
+    for (int i = 1; i < 27; ++i) {
+        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+        const R w = R(weight<27>(i));
+        R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+        R tv = ld<R>(nb.ptr(tp, ex, ey, ez));
+        if (WALL && nb.ghost(ey)) {
+            pv = nb.phi_ghost(pv, ey, a.wet);
+            const double *tw = ey < 0 ? a.twb : a.twt;
+            tv = R(2) * R(tw[nb.col(ex, ez, g)]) - tv;
+        }
+        if (ex) { in.gp[0] += R(ex) * w * pv; in.gT[0] += R(ex) * w * tv; }
+        if (ey) { in.gp[1] += R(ey) * w * pv; in.gT[1] += R(ey) * w * tv; }
+        if (ez) { in.gp[2] += R(ez) * w * pv; in.gT[2] += R(ez) * w * tv; }
+        lap += w * pv;
+    }
+    for (int k = 0; k < 3; ++k) {
+        in.gp[k] *= R(3);
+        in.gT[k] *= R(3);
+    }
+    in.lap = R(6) * (lap - R(1.0 - weight<27>(0)) * in.phi);
+
+    R mu[27];
+    HyAdj<R> ad;
+    hydro_vjp<R>(a.hy, gp, in, lam, au, mu, ad);
+    store_links<27, S, R>(static_cast<S *>(a.mu_dst[1]), g, nb, mu);
+    S *sp = static_cast<S *>(a.sphi_dst);
+    S *sT = static_cast<S *>(a.sT_dst);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        st(elem(sp + k * N, nb.c), ad.gp[k]);
+        st(elem(sT + k * N, nb.c), ad.gT[k]);
+    }
+    st(elem(sp + 3 * N, nb.c), ad.lap);
+    st(elem(sp + 4 * N, nb.c), ad.phi);
+    st(elem(sT + 3 * N, nb.c), ad.T);
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_adj_hydro(const CoupledAdjointArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    if (nb.below || nb.above)
+        adj_hydro_cell<S, R, true>(a, nb);
+    else
+        adj_hydro_cell<S, R, false>(a, nb);
+}
+
+// ---------------------------------------------------------------------------
+// R1: phase field
+// ---------------------------------------------------------------------------
+template <int Q, typename P, typename S, typename R, bool WALL>
+__device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const Nbr &nb)
+{
+    constexpr bool dev = deviation_storage<P>();
+    const Geometry &g = a.geo;
+    const int64_t N = g.N;
+    R lam[Q];
+    gather_links<Q, S, R, WALL>(static_cast<const S *>(a.mu_src[0]), g, nb, R(1), lam);
+
+    // dL/dphi^{n+1}: the transposed gradient and Laplacian of step n+1 (K1 and
+    // K2 read the same stencil), the cell's own Pi, and K3's local adjoint
+    const S *sp = static_cast<const S *>(a.sphi_src);
+    R aphi = ld<R>(elem(sp + 4 * N, nb.c)) - R(6.0 * (1.0 - weight<27>(0))) * ld<R>(elem(sp + 3 * N, nb.c)) +
+             ld<R>(elem(static_cast<const S *>(a.lphi3), nb.c));
+    R ghost_sum[2] = {R(0), R(0)};
+#pragma unroll
+    for (int k = 1; k < 27; ++k) {
+        const int ex = vel27(k, 0), ey = vel27(k, 1), ez = vel27(k, 2);
+        const R w = R(weight<27>(k));
+        if (!(WALL && nb.ghost(-ey))) {
+            R v = R(6) * ld<R>(nb.ptr(sp + 3 * N, -ex, -ey, -ez));
+            if (ex) v += R(3 * ex) * ld<R>(nb.ptr(sp, -ex, -ey, -ez));
+            if (ey) v += R(3 * ey) * ld<R>(nb.ptr(sp + N, -ex, -ey, -ez));
+            if (ez) v += R(3 * ez) * ld<R>(nb.ptr(sp + 2 * N, -ex, -ey, -ez));
+            aphi += w * v;
+        }
+        if (WALL && nb.ghost(ey)) {
+            R v = R(6) * ld<R>(nb.ptr(sp + 3 * N, -ex, 0, -ez));
+            if (ex) v += R(3 * ex) * ld<R>(nb.ptr(sp, -ex, 0, -ez));
+            v += R(3 * ey) * ld<R>(nb.ptr(sp + N, -ex, 0, -ez));
+            if (ez) v += R(3 * ez) * ld<R>(nb.ptr(sp + 2 * N, -ex, 0, -ez));
+            ghost_sum[ey > 0] += w * v;
+        }
+    }
+    if (WALL) {
+        // d ghost / d phi = 1 + wet (1 - 2 phi) for the contact-angle ghost of this cell
+        const R p1 = ld<R>(elem(static_cast<const S *>(a.s1.phi), nb.c));
+        aphi += ghost_sum[0] * (R(1) + R(a.wet[0]) * (R(1) - R(2) * p1)) +
+                ghost_sum[1] * (R(1) + R(a.wet[1]) * (R(1) - R(2) * p1));
+    }
+
+    // recompute K1 of step n: phi^n stencil, pulled h (actual values)
+    const S *po = static_cast<const S *>(a.s0.phi);
+    R pn[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) {
+        pn[k] = ld<R>(nb.ptr(po, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
+        if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);
+    }
+    const P *hs = static_cast<const P *>(a.s0.h);
+    const PdfLanes<Q> pl(nb);
+    R h[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+        const R w = R(weight<Q>(i));
+        if (WALL && nb.ghost(-ey)) {
+            h[i] = ld<R>(elem(pdf_row<Q>(hs, g, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1]));
+            if (dev) h[i] += w * pn[0];
+        } else {
+            h[i] = ld<R>(elem(pdf_row<Q>(hs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+            if (dev) h[i] += w * pn[opposite<27>(index27<Q>(i))];
+        }
+    }
+    R G[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int k = 1; k < 27; ++k) {
+        const R v = R(weight<27>(k)) * pn[k];
+        G[0] += R(vel27(k, 0)) * v;
+        G[1] += R(vel27(k, 1)) * v;
+        G[2] += R(vel27(k, 2)) * v;
+    }
+    for (int k = 0; k < 3; ++k) G[k] *= R(3);
+    R u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.s0.u[k]), nb.c));
+
+    R mu[Q], aG[3], au[3];
+    pf_vjp<Q, R>(a.pf, h, G, u, lam, aphi, mu, aG, au);
+    store_links<Q, S, R>(static_cast<S *>(a.mu_dst[0]), g, nb, mu);
+    S *sd = static_cast<S *>(a.sphi_dst);
+    S *lu1 = static_cast<S *>(a.lu1);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        st(elem(sd + k * N, nb.c), ld<R>(elem(sd + k * N, nb.c)) + aG[k]);
+        st(elem(lu1 + k * N, nb.c), au[k]);
+    }
+}
+
+template <int Q, typename P, typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_adj_pf(const CoupledAdjointArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    if (nb.below || nb.above)
+        adj_pf_cell<Q, P, S, R, true>(a, nb);
+    else
+        adj_pf_cell<Q, P, S, R, false>(a, nb);
+}
+
+// ---------------------------------------------------------------------------
+// seed and the last wall-temperature pass
+// ---------------------------------------------------------------------------
+// sphi of the final step: Pi = dL/dphi^N for the loss through the centroid
+// c = sum phi x / sum phi (sums in out4: M, sum phi x, sum phi y, sum phi z)
+// plus an optional per-cell term; Gamma = Lambda = 0
+template <typename S>
+__global__ void __launch_bounds__(kTX *kTY) k_adj_seed_phi(const Geometry g, const Tiling t, const double *out4,
+                                                           double gcx, double gcy, double gcz, const double *dphi,
+                                                           S *sphi)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, g, x, y, z)) return;
+    const uint32_t c = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * (uint32_t)g.plane;
+    const double M = out4[0];
+    const double cx = out4[1] / M, cy = out4[2] / M, cz = out4[3] / M;
+    double s = (gcx * (x - cx) + gcy * (y - cy) + gcz * (z - cz)) / M;
+    if (dphi) s += dphi[c];
+    const int64_t N = g.N;
+    for (int k = 0; k < 4; ++k) st(elem(sphi + k * N, c), 0.0);
+    st(elem(sphi + 4 * N, c), s);
+}
+
+// wall-temperature adjoint of the ghosts read by K2 of the first step (sT of step 0)
+template <typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_adj_tw_ghosts(const Geometry g, const Tiling t, const S *sT,
+                                                            double *grad_twb, double *grad_twt)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, g, x, y, z)) return;
+    const Nbr nb(g, x, y, z);
+    if (!nb.below && !nb.above) return;
+    const int64_t N = g.N;
+    R ghost_sum[2] = {R(0), R(0)};
+#pragma unroll
+    for (int k = 1; k < 27; ++k) {
+        const int ex = vel27(k, 0), ey = vel27(k, 1), ez = vel27(k, 2);
+        if (!nb.ghost(ey)) continue;
+        R v = R(0);
+        if (ex) v += R(ex) * ld<R>(nb.ptr(sT, -ex, 0, -ez));
+        v += R(ey) * ld<R>(nb.ptr(sT + N, -ex, 0, -ez));
+        if (ez) v += R(ez) * ld<R>(nb.ptr(sT + 2 * N, -ex, 0, -ez));
+        ghost_sum[ey > 0] += R(3.0 * weight<27>(k)) * v;
+    }
+    const uint32_t col = nb.col(0, 0, g);
+    if (nb.below) grad_twb[col] += 2.0 * (double)ghost_sum[0];
+    if (nb.above) grad_twt[col] += 2.0 * (double)ghost_sum[1];
+}
+
+} // namespace
+
+template <int QH, int QF, typename P, typename S, typename R>
+void launch_coupled_adjoint_step(const CoupledAdjointArgs &a, hipStream_t s)
+{
+    const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_adj_thermal<QF, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    hipLaunchKernelGGL((k_adj_hydro<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    hipLaunchKernelGGL((k_adj_pf<QH, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+}
+
+template <typename S>
+void launch_coupled_adjoint_seed(const Geometry &g, const double *out4, const double gc[3], const double *dphi,
+                                 void *sphi, hipStream_t s)
+{
+    const Tiling t = make_tiling(g);
+    hipLaunchKernelGGL((k_adj_seed_phi<S>), tiling_grid(t), tiling_block(), 0, s, g, t, out4, gc[0], gc[1], gc[2],
+                       dphi, static_cast<S *>(sphi));
+}
+
+template <typename S>
+void launch_coupled_adjoint_tw(const Geometry &g, const void *sT, double *grad_twb, double *grad_twt, hipStream_t s)
+{
+    const Tiling t = make_tiling(g);
+    hipLaunchKernelGGL((k_adj_tw_ghosts<S, S>), tiling_grid(t), tiling_block(), 0, s, g, t,
+                       static_cast<const S *>(sT), grad_twb, grad_twt);
+}
+
+#define TCP_CADJ_INST(QH, QF)                                                                                \
+    template void launch_coupled_adjoint_step<QH, QF, double, double, double>(const CoupledAdjointArgs &,    \
+                                                                             hipStream_t);                   \
+    template void launch_coupled_adjoint_step<QH, QF, float, float, float>(const CoupledAdjointArgs &,       \
+                                                                          hipStream_t);                      \
+    template void launch_coupled_adjoint_step<QH, QF, _Float16, float, float>(const CoupledAdjointArgs &,    \
+                                                                             hipStream_t);
+TCP_CADJ_INST(15, 7)
+TCP_CADJ_INST(15, 15)
+TCP_CADJ_INST(15, 19)
+TCP_CADJ_INST(15, 27)
+TCP_CADJ_INST(27, 7)
+TCP_CADJ_INST(27, 15)
+TCP_CADJ_INST(27, 19)
+TCP_CADJ_INST(27, 27)
+#undef TCP_CADJ_INST
+
+template void launch_coupled_adjoint_seed<double>(const Geometry &, const double *, const double[3], const double *,
+                                                  void *, hipStream_t);
+template void launch_coupled_adjoint_seed<float>(const Geometry &, const double *, const double[3], const double *,
+                                                 void *, hipStream_t);
+template void launch_coupled_adjoint_tw<double>(const Geometry &, const void *, double *, double *, hipStream_t);
+template void launch_coupled_adjoint_tw<float>(const Geometry &, const void *, double *, double *, hipStream_t);
+
+} // namespace tcp

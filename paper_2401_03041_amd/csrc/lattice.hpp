@@ -309,7 +309,7 @@ struct FirstOrder;
 
 template <typename R>
 struct FirstOrder<7, R> {
-    __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[7])
+    __host__ __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[7])
     {
         d[0] = R(-2) * (u[0] * v[0] + u[1] * v[1] + u[2] * v[2]);
         d[1] = v[1] * (u[1] + R(0.5));
@@ -323,7 +323,7 @@ struct FirstOrder<7, R> {
 
 template <typename R>
 struct FirstOrder<15, R> {
-    __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[15])
+    __host__ __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[15])
     {
         const R ux = u[0], uy = u[1], uz = u[2], vx = v[0], vy = v[1], vz = v[2];
         // raw moments of d
@@ -357,7 +357,7 @@ struct FirstOrder<15, R> {
 
 template <typename R>
 struct FirstOrder<19, R> {
-    __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[19])
+    __host__ __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[19])
     {
         const R ux = u[0], uy = u[1], uz = u[2], vx = v[0], vy = v[1], vz = v[2];
         // the D3Q19 basis is closed under taking factors, so every raw moment
@@ -401,7 +401,7 @@ struct FirstOrder<19, R> {
 template <typename R>
 struct Axis1D {
     R m0[3], m1[3], m2[3]; // index c + 1
-    __device__ __forceinline__ explicit Axis1D(R u)
+    __host__ __device__ __forceinline__ explicit Axis1D(R u)
     {
         const R u2 = u * u;
         m0[1] = R(1) - u2;
@@ -418,7 +418,7 @@ struct Axis1D {
 
 template <typename R>
 struct FirstOrder<27, R> {
-    __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[27])
+    __host__ __device__ __forceinline__ static void apply(const R u[3], const R v[3], R d[27])
     {
         const Axis1D<R> X(u[0]), Y(u[1]), Z(u[2]);
 #pragma unroll

@@ -57,6 +57,22 @@ struct tcp_domain {
     // link sources (five fields), N values each
     void *adj_rk = nullptr;
 
+    // tape of a coupled run for its adjoint (tcp_step_taped / tcp_tape_adjoint):
+    // checkpoints of the state every `seg` steps, a ring of seg + 1 states for
+    // recomputing one segment, the heat sources and wall temperatures in force,
+    // and the reverse sweep's workspace
+    struct Tape {
+        bool valid = false;
+        int64_t nsteps = 0, seg = 0, nseg = 0;
+        void *mem = nullptr;
+        size_t mem_bytes = 0;
+        std::vector<StateSlot> ckpt, ring;
+        HeatSources src{};
+        double *twb = nullptr, *twt = nullptr;
+        void *mu[3][2]{}, *sphi[2]{}, *sT[2]{}, *lu1 = nullptr, *lu3 = nullptr, *lphi3 = nullptr;
+        double *grad_q = nullptr, *grad_tw = nullptr, *gsrc = nullptr, *dphi = nullptr;
+    } tape;
+
     bool prof = false;
     std::vector<TimingRecord> records;
     std::vector<hipEvent_t> pool;
@@ -618,6 +634,244 @@ void run_rk_adjoint(tcp_domain *d, int64_t nsteps)
 
 } // namespace
 
+namespace {
+
+// advance nsteps coupled steps from the current state (step graphs on small grids)
+int advance(tcp_domain *d, int64_t nsteps)
+{
+    int64_t left = nsteps;
+    if (use_graphs(d, nsteps)) {
+        for (; left >= kGraphSteps; left -= kGraphSteps) {
+            if (!d->gexec[d->cur]) {
+                const int rc = build_graph(d);
+                if (rc != TCP_OK) return rc;
+            }
+            TCP_HIP(d, hipGraphLaunch(d->gexec[d->cur], d->stream));
+        }
+    }
+    run_steps(d, left);
+    return check_launch(d);
+}
+
+// ---- tape of a coupled run ---------------------------------------------------
+StateSlot domain_slot(const tcp_domain *d)
+{
+    StateSlot s{};
+    s.h = d->h[d->cur];
+    s.g = d->g[d->cur];
+    s.f = d->f[d->cur];
+    s.phi = d->phi[d->cur];
+    s.T = d->T[d->cur];
+    for (int k = 0; k < 3; ++k) s.u[k] = d->u[k];
+    return s;
+}
+
+constexpr int kSlotPieces = 8; // h, g, f, phi, T, u_x, u_y, u_z
+
+void *&slot_piece(StateSlot &s, int k)
+{
+    switch (k) {
+    case 0: return s.h;
+    case 1: return s.g;
+    case 2: return s.f;
+    case 3: return s.phi;
+    case 4: return s.T;
+    default: return s.u[k - 5];
+    }
+}
+
+void slot_sizes(const tcp_domain *d, size_t sz[kSlotPieces])
+{
+    const size_t N = (size_t)d->geo.N;
+    sz[0] = (size_t)pdf_elems(d->geo, d->P.q_pf) * d->pb;
+    sz[1] = (size_t)pdf_elems(d->geo, 27) * d->sb;
+    sz[2] = (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->pb;
+    for (int k = 3; k < kSlotPieces; ++k) sz[k] = N * d->sb;
+}
+
+size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+int copy_slot(tcp_domain *d, StateSlot dst, StateSlot src)
+{
+    size_t sz[kSlotPieces];
+    slot_sizes(d, sz);
+    for (int k = 0; k < kSlotPieces; ++k)
+        TCP_HIP(d, hipMemcpyAsync(slot_piece(dst, k), slot_piece(src, k), sz[k], hipMemcpyDeviceToDevice, d->stream));
+    return TCP_OK;
+}
+
+// One allocation holds nseg checkpoints, seg + 1 ring states, the taped wall
+// temperatures and the reverse sweep's workspace.
+int ensure_tape(tcp_domain *d, int64_t nseg, int64_t seg)
+{
+    auto &tp = d->tape;
+    const size_t N = (size_t)d->geo.N, ncol = (size_t)d->P.nx * d->P.nz, sb = d->sb;
+    size_t sz[kSlotPieces];
+    slot_sizes(d, sz);
+    size_t slot = 0;
+    for (int k = 0; k < kSlotPieces; ++k) slot += round256(sz[k]);
+    const size_t qb[3] = {(size_t)pdf_elems(d->geo, d->P.q_pf) * sb, (size_t)pdf_elems(d->geo, 27) * sb,
+                          (size_t)pdf_elems(d->geo, d->P.q_thermal) * sb};
+    std::vector<size_t> work;
+    for (int k = 0; k < 3; ++k) work.insert(work.end(), {qb[k], qb[k]});          // mu[k][0..1]
+    work.insert(work.end(), {5 * N * sb, 5 * N * sb, 4 * N * sb, 4 * N * sb}); // sphi, sT
+    work.insert(work.end(), {3 * N * sb, 3 * N * sb, N * sb});                // lu1, lu3, lphi3
+    work.insert(work.end(), {N * sizeof(double), 2 * ncol * sizeof(double), 4 * kMaxSources * sizeof(double),
+                             N * sizeof(double), ncol * sizeof(double), ncol * sizeof(double)});
+    const size_t nslots = (size_t)(nseg + seg + 1);
+    size_t total = nslots * slot;
+    for (size_t w : work) total += round256(w);
+    if (tp.mem && tp.mem_bytes != total) {
+        (void)hipStreamSynchronize(d->stream);
+        dev_free(d, tp.mem);
+        tp.mem = nullptr;
+    }
+    if (!tp.mem) {
+        tp.mem = dev_alloc(d, total);
+        if (!tp.mem) return fail(d, TCP_ERR_OOM, "device allocation failed (tape of the coupled run)");
+        tp.mem_bytes = total;
+    }
+    char *p = static_cast<char *>(tp.mem);
+    tp.ckpt.assign((size_t)nseg, StateSlot{});
+    tp.ring.assign((size_t)seg + 1, StateSlot{});
+    for (size_t j = 0; j < nslots; ++j) {
+        StateSlot &s = j < (size_t)nseg ? tp.ckpt[j] : tp.ring[j - (size_t)nseg];
+        for (int k = 0; k < kSlotPieces; ++k) {
+            slot_piece(s, k) = p;
+            p += round256(sz[k]);
+        }
+    }
+    void **dst[] = {&tp.mu[0][0], &tp.mu[0][1], &tp.mu[1][0], &tp.mu[1][1], &tp.mu[2][0], &tp.mu[2][1],
+                    &tp.sphi[0], &tp.sphi[1], &tp.sT[0], &tp.sT[1], &tp.lu1, &tp.lu3, &tp.lphi3};
+    size_t k = 0;
+    for (; k < 13; ++k) {
+        *dst[k] = p;
+        p += round256(work[k]);
+    }
+    double **dd[] = {&tp.grad_q, &tp.grad_tw, &tp.gsrc, &tp.dphi, &tp.twb, &tp.twt};
+    for (int m = 0; m < 6; ++m, ++k) {
+        *dd[m] = reinterpret_cast<double *>(p);
+        p += round256(work[k]);
+    }
+    return TCP_OK;
+}
+
+// one coupled step (fused kernel) from ring state `from` to `to`, with the
+// taped heat sources and wall temperatures
+template <typename S, typename Pdf>
+void slot_step(tcp_domain *d, const StateSlot &from, const StateSlot &to)
+{
+    StepArgs a{pf_args(d), hydro_args(d), thermal_args(d)};
+    a.pf.h_src = from.h;
+    a.pf.h_dst = to.h;
+    a.pf.phi_old = from.phi;
+    a.pf.phi_new = to.phi;
+    a.hy.g_src = from.g;
+    a.hy.g_dst = to.g;
+    a.hy.phi = from.phi;
+    a.hy.T = from.T;
+    a.hy.twb = a.th.twb = d->tape.twb;
+    a.hy.twt = a.th.twt = d->tape.twt;
+    a.th.f_src = from.f;
+    a.th.f_dst = to.f;
+    a.th.phi = to.phi;
+    a.th.T_old = from.T;
+    a.th.T = to.T;
+    a.th.src = d->tape.src;
+    for (int k = 0; k < 3; ++k) {
+        a.pf.u[k] = from.u[k];
+        a.hy.u[k] = to.u[k];
+        a.th.u[k] = to.u[k];
+    }
+    KernelTimer t(d, TCP_K_STEP);
+    if (d->P.q_pf == 15) fused_step_q<15, S, Pdf>(d, a);
+    else fused_step_q<27, S, Pdf>(d, a);
+}
+
+template <int QH, typename S, typename Pdf>
+void reverse_step_q(tcp_domain *d, const CoupledAdjointArgs &a)
+{
+    switch (d->P.q_thermal) {
+    case 7: launch_coupled_adjoint_step<QH, 7, Pdf, S, S>(a, d->stream); break;
+    case 15: launch_coupled_adjoint_step<QH, 15, Pdf, S, S>(a, d->stream); break;
+    case 19: launch_coupled_adjoint_step<QH, 19, Pdf, S, S>(a, d->stream); break;
+    default: launch_coupled_adjoint_step<QH, 27, Pdf, S, S>(a, d->stream); break;
+    }
+}
+
+// reverse of the step from ring state s0 to s1; the carried adjoint is read
+// from parity b and written to 1 - b
+template <typename S, typename Pdf>
+void reverse_step(tcp_domain *d, const StateSlot &s0, const StateSlot &s1, int b)
+{
+    auto &tp = d->tape;
+    const tcp_params &P = d->P;
+    CoupledAdjointArgs a{};
+    a.geo = d->geo;
+    a.s0 = s0;
+    a.s1 = s1;
+    for (int k = 0; k < 3; ++k) {
+        a.mu_src[k] = tp.mu[k][b];
+        a.mu_dst[k] = tp.mu[k][1 - b];
+        a.uw_bot[k] = P.u_wall_bot[k];
+        a.uw_top[k] = P.u_wall_top[k];
+    }
+    a.sphi_src = tp.sphi[b];
+    a.sphi_dst = tp.sphi[1 - b];
+    a.sT_src = tp.sT[b];
+    a.sT_dst = tp.sT[1 - b];
+    a.lu1 = tp.lu1;
+    a.lu3 = tp.lu3;
+    a.lphi3 = tp.lphi3;
+    a.twb = tp.twb;
+    a.twt = tp.twt;
+    a.wet[0] = wetting(P.contact_angle_bot, P.xi);
+    a.wet[1] = wetting(P.contact_angle_top, P.xi);
+    a.t_shift = P.t_shift;
+    a.pf = PfCoef{d->omega_phi, 1.0 / P.xi, P.normal_eps * P.normal_eps};
+    a.hy = HyCoef{P.rho_l, P.rho_h - P.rho_l, d->tau_l, d->tau_h - d->tau_l, P.sigma_ref, P.sigma_t, P.t_ref, P.xi,
+                  {P.g[0], P.g[1], P.g[2]}, P.omega_bulk};
+    a.th = ThCoef{P.kappa_l, P.kappa_h - P.kappa_l};
+    a.grad_q = tp.grad_q;
+    a.grad_twb = tp.grad_tw;
+    a.grad_twt = tp.grad_tw + (size_t)P.nx * P.nz;
+    KernelTimer t(d, TCP_K_COUPLED_ADJOINT);
+    if (P.q_pf == 15) reverse_step_q<15, S, Pdf>(d, a);
+    else reverse_step_q<27, S, Pdf>(d, a);
+}
+
+// Reverse sweep over the taped steps, last segment first: restore the
+// segment's checkpoint into ring state 0, recompute the segment's states,
+// then undo its steps last to first.  The loss enters through the final phase
+// field (seeded before the first reverse step).
+template <typename S, typename Pdf>
+int run_tape_adjoint(tcp_domain *d, const double gc[3], const double *dphi)
+{
+    auto &tp = d->tape;
+    const size_t ncol = (size_t)d->P.nx * d->P.nz;
+    int b = 0;
+    for (int64_t j = tp.nseg - 1; j >= 0; --j) {
+        const int64_t kj = std::min(tp.seg, tp.nsteps - j * tp.seg);
+        int rc = copy_slot(d, tp.ring[0], tp.ckpt[(size_t)j]);
+        if (rc != TCP_OK) return rc;
+        for (int64_t s = 0; s < kj; ++s) slot_step<S, Pdf>(d, tp.ring[(size_t)s], tp.ring[(size_t)s + 1]);
+        if (j == tp.nseg - 1) {
+            launch_reduce<S>(d->geo, tp.ring[(size_t)kj].phi, d->partial, d->out4, d->stream);
+            launch_coupled_adjoint_seed<S>(d->geo, d->out4, gc, dphi, tp.sphi[0], d->stream);
+        }
+        for (int64_t s = kj - 1; s >= 0; --s) {
+            reverse_step<S, Pdf>(d, tp.ring[(size_t)s], tp.ring[(size_t)s + 1], b);
+            b = 1 - b;
+        }
+        rc = check_launch(d);
+        if (rc != TCP_OK) return rc;
+    }
+    launch_coupled_adjoint_tw<S>(d->geo, tp.sT[b], tp.grad_tw, tp.grad_tw + ncol, d->stream);
+    return check_launch(d);
+}
+
+} // namespace
+
 extern "C" {
 
 int tcp_params_default(tcp_params *p)
@@ -739,6 +993,7 @@ int tcp_destroy(tcp_domain *d)
         (void)hipEventDestroy(r.stop);
     }
     for (auto e : d->pool) (void)hipEventDestroy(e);
+    if (d->tape.mem) dev_free(d, d->tape.mem);
     for (void *p : d->owned) dev_free(d, p);
     delete d;
     return TCP_OK;
@@ -862,19 +1117,81 @@ int tcp_step(tcp_domain *d, int64_t nsteps)
     if (!d) return TCP_ERR_ARG;
     if (nsteps < 0) return fail(d, TCP_ERR_ARG, "nsteps must be >= 0");
     if (!d->initialized) return fail(d, TCP_ERR_STATE, "tcp_initialize must precede tcp_step");
+    return guarded(d, [&]() -> int { return advance(d, nsteps); });
+}
+
+int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment)
+{
+    if (!d) return TCP_ERR_ARG;
+    if (nsteps < 1) return fail(d, TCP_ERR_ARG, "nsteps must be >= 1");
+    if (!d->initialized) return fail(d, TCP_ERR_STATE, "tcp_initialize must precede tcp_step_taped");
+    if (d->P.thermal != TCP_THERMAL_LB)
+        return fail(d, TCP_ERR_UNSUPPORTED, "the adjoint of the coupled step is built for the thermal LB only");
     return guarded(d, [&]() -> int {
-        int64_t left = nsteps;
-        if (use_graphs(d, nsteps)) {
-            for (; left >= kGraphSteps; left -= kGraphSteps) {
-                if (!d->gexec[d->cur]) {
-                    const int rc = build_graph(d);
-                    if (rc != TCP_OK) return rc;
-                }
-                TCP_HIP(d, hipGraphLaunch(d->gexec[d->cur], d->stream));
-            }
+        auto &tp = d->tape;
+        tp.valid = false;
+        const int64_t seg = segment > 0 ? std::min(segment, nsteps)
+                                        : std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)nsteps)));
+        const int64_t nseg = (nsteps + seg - 1) / seg;
+        int rc = ensure_tape(d, nseg, seg);
+        if (rc != TCP_OK) return rc;
+        tp.src = d->src;
+        const size_t ncol = (size_t)d->P.nx * d->P.nz;
+        TCP_HIP(d, hipMemcpyAsync(tp.twb, d->twb, ncol * sizeof(double), hipMemcpyDeviceToDevice, d->stream));
+        TCP_HIP(d, hipMemcpyAsync(tp.twt, d->twt, ncol * sizeof(double), hipMemcpyDeviceToDevice, d->stream));
+        for (int64_t j = 0; j < nseg; ++j) {
+            rc = copy_slot(d, tp.ckpt[(size_t)j], domain_slot(d));
+            if (rc == TCP_OK) rc = advance(d, std::min(seg, nsteps - j * seg));
+            if (rc != TCP_OK) return rc;
         }
-        run_steps(d, left);
+        tp.nsteps = nsteps;
+        tp.seg = seg;
+        tp.nseg = nseg;
+        tp.valid = true;
         return check_launch(d);
+    });
+}
+
+int tcp_tape_adjoint(tcp_domain *d, const double dL_dcentroid[3], const double *dL_dphi, double *dL_dsource,
+                     double *dL_dTw_bot, double *dL_dTw_top)
+{
+    if (!d || !dL_dcentroid) return fail(d, TCP_ERR_ARG, "dL_dcentroid is required");
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(dL_dcentroid[k])) return fail(d, TCP_ERR_ARG, "dL_dcentroid must be finite");
+    if (!d->tape.valid) return fail(d, TCP_ERR_STATE, "no taped run: tcp_step_taped must precede tcp_tape_adjoint");
+    return guarded(d, [&]() -> int {
+        auto &tp = d->tape;
+        const size_t N = (size_t)d->geo.N, ncol = (size_t)d->P.nx * d->P.nz, sb = d->sb;
+        const size_t qb[3] = {(size_t)pdf_elems(d->geo, d->P.q_pf) * sb, (size_t)pdf_elems(d->geo, 27) * sb,
+                              (size_t)pdf_elems(d->geo, d->P.q_thermal) * sb};
+        for (int k = 0; k < 3; ++k) TCP_HIP(d, hipMemsetAsync(tp.mu[k][0], 0, qb[k], d->stream));
+        TCP_HIP(d, hipMemsetAsync(tp.sT[0], 0, 4 * N * sb, d->stream));
+        TCP_HIP(d, hipMemsetAsync(tp.lu1, 0, 3 * N * sb, d->stream));
+        TCP_HIP(d, hipMemsetAsync(tp.grad_q, 0, N * sizeof(double), d->stream));
+        TCP_HIP(d, hipMemsetAsync(tp.grad_tw, 0, 2 * ncol * sizeof(double), d->stream));
+        if (dL_dphi)
+            TCP_HIP(d, hipMemcpyAsync(tp.dphi, dL_dphi, N * sizeof(double), hipMemcpyHostToDevice, d->stream));
+        const double *dphi = dL_dphi ? tp.dphi : nullptr;
+        int rc;
+        switch (d->P.precision) {
+        case TCP_FP64: rc = run_tape_adjoint<double, double>(d, dL_dcentroid, dphi); break;
+        case TCP_FP32: rc = run_tape_adjoint<float, float>(d, dL_dcentroid, dphi); break;
+        default: rc = run_tape_adjoint<float, _Float16>(d, dL_dcentroid, dphi); break;
+        }
+        if (rc != TCP_OK) return rc;
+        const int ns = tp.src.n;
+        if (ns > 0) launch_source_grad(d->geo, tp.src, tp.grad_q, d->partial, tp.gsrc, d->stream);
+        rc = check_launch(d);
+        if (rc != TCP_OK) return rc;
+        if (dL_dsource && ns > 0)
+            TCP_HIP(d, hipMemcpyAsync(dL_dsource, tp.gsrc, 4 * ns * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+        if (dL_dTw_bot)
+            TCP_HIP(d, hipMemcpyAsync(dL_dTw_bot, tp.grad_tw, ncol * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+        if (dL_dTw_top)
+            TCP_HIP(d, hipMemcpyAsync(dL_dTw_top, tp.grad_tw + ncol, ncol * sizeof(double), hipMemcpyDeviceToHost,
+                                      d->stream));
+        TCP_HIP(d, hipStreamSynchronize(d->stream));
+        return TCP_OK;
     });
 }
 
@@ -1180,6 +1497,22 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     // and writes acc and the stage field; the FP64 source adjoint is read and
     // written.
     b[TCP_K_ADJOINT] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * sb + 4.0 * sb + 16.0 : 20.0 * sb + 16.0;
+    // reverse step of the coupled adjoint (link and field adjoints in the
+    // arithmetic type, sb bytes), per kernel: thermal reads the f link
+    // adjoints, sT, the PDFs f (and T^n with deviation storage), u^{n+1},
+    // phi^{n+1}, and writes the link adjoints, lu3, lphi3, plus the FP64
+    // source adjoint read and written; hydrodynamic reads the g link
+    // adjoints, lu1, lu3, the PDFs g, phi^n, T^n and writes the link
+    // adjoints, sphi, sT; phase field reads the h link adjoints, sphi,
+    // lphi3, the PDFs h, phi^n, u^n, the gradient part of the new sphi, and
+    // writes the link adjoints, that part of sphi and lu1
+    if (d->P.thermal == TCP_THERMAL_LB) {
+        const double qf = d->P.q_thermal, qh = d->P.q_pf;
+        b[TCP_K_COUPLED_ADJOINT] = (2.0 * qf * sb + qf * pb + (12.0 + (d->pb <= 4 ? 1.0 : 0.0)) * sb + 16.0) +
+                                   98.0 * sb + (2.0 * qh * sb + qh * pb + 19.0 * sb);
+    } else {
+        b[TCP_K_COUPLED_ADJOINT] = 0.0;
+    }
     return TCP_OK;
 }
 

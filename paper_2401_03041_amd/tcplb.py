@@ -20,12 +20,13 @@ FIELDS = {"phi": PHI, "ux": UX, "uy": UY, "uz": UZ, "T": T, "p": P, "pstar": PST
 PDFS = {"h": 0, "g": 1, "f": 2}
 THERMAL = {"lb": 0, "rk2": 1, "rk4": 2}
 PRECISION = {"fp64": 0, "fp32": 1, "fp16": 2}
-KERNELS = ("phase", "hydro", "thermal", "rk", "step", "adjoint")
+KERNELS = ("phase", "hydro", "thermal", "rk", "step", "adjoint", "coupled_adjoint")
 
 # names of every entry point the header declares
 EXPORTS = (
     "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_droplets",
-    "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_warm_temperature", "tcp_thermal_adjoint", "tcp_get_field",
+    "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_step_taped", "tcp_tape_adjoint",
+    "tcp_warm_temperature", "tcp_thermal_adjoint", "tcp_get_field",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
     "tcp_set_profiling", "tcp_set_fusion", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
     "tcp_last_error",
@@ -94,6 +95,8 @@ def load() -> C.CDLL:
         "tcp_set_wall_temperature": [vp, C.c_int, dp],
         "tcp_initialize": [vp],
         "tcp_step": [vp, i64],
+        "tcp_step_taped": [vp, i64, i64],
+        "tcp_tape_adjoint": [vp, dp, dp, dp, dp, dp],
         "tcp_warm_temperature": [vp, i64, C.c_double, i64, C.POINTER(i64), dp],
         "tcp_thermal_adjoint": [vp, i64, dp, dp, dp, dp],
         "tcp_get_field": [vp, C.c_int, dp, vp],
@@ -260,6 +263,27 @@ class Domain:
     def step(self, n: int = 1) -> None:
         self._check(self._lib.tcp_step(self._h, int(n)), "step")
 
+    def step_taped(self, n: int, segment: int = 0) -> None:
+        """Advance n coupled steps and keep the tape tape_adjoint needs
+        (checkpoints every `segment` steps; 0: ceil(sqrt(n)))."""
+        self._check(self._lib.tcp_step_taped(self._h, int(n), int(segment)), "step_taped")
+
+    def tape_adjoint(self, dL_dcentroid, dL_dphi=None):
+        """Gradients of a loss of the final phase field (through its centroid,
+        dL_dcentroid (3,), plus an optional per-cell dL_dphi) after the taped run,
+        with respect to the taped heat sources and the wall temperatures:
+        (dsrc[n_sources, 4] = dL/d(Q, x, y, z) per source, dTw_bot[nz, nx], dTw_top[nz, nx])."""
+        gc = np.ascontiguousarray(np.asarray(dL_dcentroid, dtype=np.float64).reshape(3))
+        m = None
+        if dL_dphi is not None:
+            m = np.ascontiguousarray(np.broadcast_to(np.asarray(dL_dphi, dtype=np.float64), self.shape3))
+        dq = np.zeros(64)
+        bot = np.zeros((self.nz, self.nx))
+        top = np.zeros((self.nz, self.nx))
+        self._check(self._lib.tcp_tape_adjoint(self._h, _dptr(gc), _dptr(m) if m is not None else None, _dptr(dq),
+                                               _dptr(bot), _dptr(top)), "tape_adjoint")
+        return dq[:4 * self.n_sources].reshape(self.n_sources, 4), bot, top
+
     def warm_temperature(self, max_steps: int, tol: float = 0.0, check_every: int = 100):
         """Thermal updates alone (phi, u held) until the per-update change of T is at
         most tol or max_steps have run; returns (steps run, last change)."""
@@ -419,3 +443,53 @@ def thermal_warmup(domain: Domain, nsteps: int):
             return g.to(dev), torch.from_numpy(dbot).to(dev), torch.from_numpy(dtop).to(dev)
 
     return _Warmup.apply
+
+
+def centroid_run(domain: Domain, nsteps: int, segment: int = 0):
+    """A coupled run as a differentiable function for torch.
+
+    Returns f(sources, tw_bot, tw_top) -> centroid: `sources` an (n, 6) float64
+    tensor of heat sources (Q, x, y, z, w, d_cut), `tw_bot` / `tw_top` (nz, nx)
+    wall temperatures.  Each call restores the domain's state as it was when
+    this function was made, loads the inputs, runs nsteps taped coupled steps
+    and returns the FP64 centroid of the final phase field, a (3,) tensor.  The
+    backward pass runs tcp_tape_adjoint with dL/dcentroid; if another call has
+    replaced the tape in between, it first reloads this call's inputs and
+    tapes the run again.  Gradients for Q, x, y, z of every source and for both
+    walls (w and d_cut get none)."""
+    import torch
+    snapshot = domain.save_state()
+    counter = [0]
+
+    def run(src, bot, top):
+        domain.load_state(snapshot)
+        domain.set_heat_sources(src.tolist())
+        domain.set_wall_temperature(0, bot)
+        domain.set_wall_temperature(1, top)
+        domain.step_taped(nsteps, segment)
+        counter[0] += 1
+        domain._tape_owner = counter[0]
+        return domain.reduce()[1]
+
+    class _Centroid(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, sources, tw_bot, tw_top):
+            ctx.inputs = (sources.detach().cpu().numpy().copy(), tw_bot.detach().cpu().numpy().copy(),
+                          tw_top.detach().cpu().numpy().copy())
+            c = run(*ctx.inputs)
+            ctx.tape = domain._tape_owner
+            return torch.from_numpy(c.copy()).to(sources.device)
+
+        @staticmethod
+        def backward(ctx, grad_c):
+            if getattr(domain, "_tape_owner", None) != ctx.tape:
+                run(*ctx.inputs)
+                ctx.tape = domain._tape_owner
+            dsrc, dbot, dtop = domain.tape_adjoint(grad_c.detach().cpu().numpy())
+            n = dsrc.shape[0]
+            g = torch.zeros((n, 6), dtype=torch.float64)
+            g[:, :4] = torch.from_numpy(dsrc)
+            dev = grad_c.device
+            return g.to(dev), torch.from_numpy(dbot).to(dev), torch.from_numpy(dtop).to(dev)
+
+    return _Centroid.apply

@@ -139,6 +139,34 @@ def capture(shape=(256, 128, 96), precision: str = "fp32", steps: int = 5000,
                 t_init={"kind": "uniform", "value": 0.0}, contact_angle_bot=contact_angle, **kw)
 
 
+def capture_design(shape=(96, 64, 64), R: float = 8.0, drop_x: float = 24.0, heater_x: float = 56.0,
+                   heater_w: float = 8.0, Q: float = 0.8, target=(44.0, None, None), precision: str = "fp32",
+                   steps: int = 2000, **kw) -> dict:
+    """Heater design by the adjoint: the capture channel (walls in y at T = 0,
+    top wall moving at 0.02, hemisphere of radius R on the bottom wall at
+    x = drop_x, mid-z; Gaussian heater of amplitude Q and width heater_w on the
+    bottom wall at x = heater_x, mid-z, no cut-off) with the capture study's
+    scaling (Re = 0.08, Ca = 0.16, Ma = 0.01, sigma_T = 0.04 sigma_ref, xi = 4,
+    U = gamma R, gamma = 0.02 / ny).  The loss is the squared distance of the
+    final droplet centroid to `target` (None components: the initial
+    centroid's value, filled in by the caller); the design variables are the
+    heater amplitude, its x/z position and the bottom-wall temperature."""
+    nx, ny, nz = shape
+    gamma = 0.02 / ny
+    U = gamma * R
+    Re, Ca, Ma = 0.08, 0.16, 0.01
+    nu = U * R / Re
+    sigma_ref = U * nu / Ca
+    kappa = U * R / Ma
+    return make(name=f"capture_design_{nx}x{ny}x{nz}", shape=shape, periodic_y=False, precision=precision,
+                steps=steps, rho_h=1.0, rho_l=1.0, nu_h=nu, nu_l=nu, mobility=0.05, xi=4.0,
+                sigma_ref=sigma_ref, sigma_t=0.04 * sigma_ref, t_ref=0.0, kappa_h=kappa, kappa_l=kappa,
+                u_wall_top=(0.02, 0.0, 0.0), t_wall_bot=0.0, t_wall_top=0.0,
+                droplets=[(drop_x, -0.5, nz / 2.0, R)],
+                heat_sources=[(Q, heater_x, -0.5, nz / 2.0, heater_w, 0.0)],
+                t_init={"kind": "uniform", "value": 0.0}, target=tuple(target), **kw)
+
+
 def laser_capture(dim: int = 3, R: float = 32.0, contact_angle: float = 90.0, q_s: float = 0.2,
                   heaters: str = "single", shift: float = 0.5, precision: str = "fp32", **kw) -> dict:
     """Droplet in shear flow meeting a laser-heated spot (Sec. 3.2 in 2D, Sec. 3.3

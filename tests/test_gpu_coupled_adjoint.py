@@ -1,0 +1,281 @@
+"""Adjoint of the coupled step (tcp_step_taped / tcp_tape_adjoint) through the
+C interface.
+
+The loss is the squared distance of the final droplet centroid to a target
+point; the gradients are those with respect to the heater amplitude and
+position and the wall temperatures.  The map is nonlinear, so the reference is
+central differences of the FP64 oracle's forward run (every input generated
+here and given to both sides), taken along the axes of the heater parameters
+and along random directions of the wall-temperature fields.  The central
+difference at step 1e-4 carries the oracle's round-off of the centroid
+(about 1e-14 of it) divided by the step, a few 1e-6 of the gradients here;
+the bar is the 1e-4 of the design target.  Central differences of the GPU's
+own FP64 forward, taken on the same inputs, check the same gradients more
+tightly (2e-6); FP32 against FP64 on the 96 x 64 x 64 design channel over its
+2000 steps checks the storage precision of the reverse sweep.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from paper_2401_03041_amd import workloads as W
+from tests.helpers import gpu_domain, oracle_domain
+
+pytestmark = pytest.mark.gpu
+
+EPS = 1e-4
+
+
+def _small(kind: str, precision: str = "fp64"):
+    """32 x 24 x 24 copy of the design channel.  'capture': as the design
+    workload (unit ratios, neutral walls), heater off the droplet's mid-plane
+    so that every component of its gradient is sizeable.  'mixed': density,
+    viscosity and conductivity ratios, wetting walls of 60 and 120 degrees,
+    gravity, the D3Q27 phase field with the D3Q15 thermal LB, a second
+    droplet on the moving top wall and a second heater in the bulk."""
+    cfg = W.capture_design((32, 24, 24), R=6.0, drop_x=10.0, heater_x=20.0, heater_w=6.0, precision=precision)
+    cfg["heat_sources"] = [(0.8, 20.0, -0.5, 15.0, 6.0, 0.0)]
+    if kind == "mixed":
+        cfg.update(rho_l=0.5, nu_l=0.15, kappa_l=1.0, contact_angle_bot=60.0, contact_angle_top=120.0,
+                   g=(2e-6, -1e-6, 0.0), q_pf=27, q_thermal=15)
+        cfg["droplets"] = [(10.0, -0.5, 12.0, 6.0), (23.0, 23.5, 9.0, 5.0)]
+        cfg["heat_sources"] = [(0.8, 20.0, -0.5, 15.0, 6.0, 0.0), (0.3, 14.0, 11.0, 6.0, 4.0, 0.0)]
+    nx, ny, nz = cfg["shape"]
+    rng = np.random.default_rng(11)
+    zz, xx = np.meshgrid(np.arange(nz), np.arange(nx), indexing="ij")
+    twb = 0.2 * np.sin(2 * np.pi * xx / nx) * np.cos(2 * np.pi * zz / nz)
+    twt = 0.1 * np.cos(2 * np.pi * (xx / nx + zz / nz))
+    # the top wall is far from the droplets: a longer direction there keeps the
+    # difference quotient's round-off small against the derivative along it
+    dirs_b = rng.standard_normal((2, nz, nx)) * np.array([1.0, 10.0])[:, None, None]
+    return cfg, twb, twt, dirs_b
+
+
+def _centroid_gpu(cfg, src, twb, twt, steps, taped=False, segment=0):
+    d = gpu_domain(cfg)
+    d.set_heat_sources(src)
+    d.set_wall_temperature(0, twb)
+    d.set_wall_temperature(1, twt)
+    if taped:
+        d.step_taped(steps, segment)
+    else:
+        d.step(steps)
+    c = d.reduce()[1]
+    return d, c
+
+
+def _loss_gpu(cfg, src, twb, twt, steps, target):
+    d, c = _centroid_gpu(cfg, src, twb, twt, steps)
+    d.close()
+    return float(np.sum((c - target) ** 2))
+
+
+def _loss_oracle(cfg, src, twb, twt, steps, target):
+    d = oracle_domain(cfg)
+    d.set_heat_sources(src)
+    d.set_wall_temperature(0, twb)
+    d.set_wall_temperature(1, twt)
+    d.initialize()
+    d.step(steps)
+    c = d.reduce()[1]
+    d.close()
+    return float(np.sum((c - target) ** 2))
+
+
+def _target(cfg):
+    d = gpu_domain(cfg)
+    c0 = d.reduce()[1]
+    d.close()
+    return np.array([c0[0] + 8.0, c0[1] + 0.5, c0[2] - 1.0])
+
+
+def _adjoint(cfg, src, twb, twt, steps, target, segment=0):
+    d, c = _centroid_gpu(cfg, src, twb, twt, steps, taped=True, segment=segment)
+    grads = d.tape_adjoint(2.0 * (c - target))
+    d.close()
+    return grads
+
+
+def _directions(src, dirs_b):
+    """(name, source perturbation, bottom-wall perturbation, top-wall perturbation)"""
+    out = []
+    zero = np.zeros_like(dirs_b[0])
+    for k in range(len(src)):
+        for j, name in ((0, "Q"), (1, "x"), (2, "y"), (3, "z")):
+            if name == "y" and src[k][2] < 0:
+                continue  # a heater on the wall plane: its y-gradient is not a design variable here
+            ds = np.zeros((len(src), 6))
+            ds[k, j] = 1.0
+            out.append((f"{name}{k}", ds, zero, zero))
+    out.append(("Tw_bot", np.zeros((len(src), 6)), dirs_b[0], zero))
+    out.append(("Tw_top", np.zeros((len(src), 6)), zero, dirs_b[1]))
+    return out
+
+
+def _fd(loss, cfg, src, twb, twt, steps, target, direction, eps=EPS):
+    _, ds, db, dt = direction
+    s = np.asarray(src, dtype=np.float64)
+    lp = loss(cfg, (s + eps * ds).tolist(), twb + eps * db, twt + eps * dt, steps, target)
+    lm = loss(cfg, (s - eps * ds).tolist(), twb - eps * db, twt - eps * dt, steps, target)
+    return (lp - lm) / (2.0 * eps)
+
+
+def _along(grads, direction):
+    dsrc, dbot, dtop = grads
+    _, ds, db, dt = direction
+    return float(np.sum(dsrc * ds[:, :4]) + np.sum(dbot * db) + np.sum(dtop * dt))
+
+
+def _check(grads, directions, fd_of, tol, what):
+    """Directional derivatives of the adjoint against difference quotients:
+    |adjoint - FD| <= tol max(|FD|, |FD|_max / 100), so that a direction along
+    which the loss hardly changes is held to the scale of the gradient."""
+    rows = [(d[0], _along(grads, d), fd_of(d)) for d in directions]
+    scale = max(abs(fd) for _, _, fd in rows) / 100.0
+    for name, ad, fd in rows:
+        err = abs(ad - fd) / max(abs(fd), scale)
+        print(f"{what} {name}: adjoint {ad:.12e} FD {fd:.12e} err {err:.2e}", flush=True)
+    for name, ad, fd in rows:
+        assert abs(ad - fd) <= tol * max(abs(fd), scale), (what, name, ad, fd)
+
+
+@pytest.mark.parametrize("kind,steps", [("capture", 150), ("mixed", 100)])
+def test_gradients_match_oracle_central_differences(kind, steps):
+    cfg, twb, twt, dirs_b = _small(kind)
+    src = [list(s) for s in cfg["heat_sources"]]
+    target = _target(cfg)
+    grads = _adjoint(cfg, src, twb, twt, steps, target)
+    # the mixed case checks a subset against the oracle (each direction costs two
+    # oracle runs); the GPU test below covers all its directions
+    only = {"x0", "Q1", "y1", "Tw_top"} if kind == "mixed" else None
+    _check(grads, [d for d in _directions(src, dirs_b) if only is None or d[0] in only],
+           lambda d: _fd(_loss_oracle, cfg, src, twb, twt, steps, target, d), 1e-4, f"{kind} oracle FD")
+
+
+@pytest.mark.parametrize("kind,steps", [("capture", 150), ("mixed", 100)])
+def test_gradients_match_gpu_central_differences(kind, steps):
+    cfg, twb, twt, dirs_b = _small(kind)
+    src = [list(s) for s in cfg["heat_sources"]]
+    target = _target(cfg)
+    grads = _adjoint(cfg, src, twb, twt, steps, target)
+    _check(grads, _directions(src, dirs_b), lambda d: _fd(_loss_gpu, cfg, src, twb, twt, steps, target, d), 2e-6,
+           f"{kind} GPU FD")
+
+
+def test_checkpoint_segments_give_identical_gradients():
+    """The recomputation from checkpoints reproduces the taped states bitwise,
+    so every segment length gives the same gradients (a ragged last segment
+    included)."""
+    cfg, twb, twt, _ = _small("mixed")
+    src = [list(s) for s in cfg["heat_sources"]]
+    target = _target(cfg)
+    ref = _adjoint(cfg, src, twb, twt, 60, target, segment=60)
+    for seg in (1, 7, 0):
+        g = _adjoint(cfg, src, twb, twt, 60, target, segment=seg)
+        for a, b in zip(ref, g):
+            assert np.array_equal(a, b), seg
+
+
+def test_taped_run_is_the_plain_run():
+    """tcp_step_taped advances the state exactly as tcp_step does."""
+    cfg, twb, twt, _ = _small("mixed")
+    src = [list(s) for s in cfg["heat_sources"]]
+    d1, c1 = _centroid_gpu(cfg, src, twb, twt, 37, taped=True, segment=5)
+    d2, c2 = _centroid_gpu(cfg, src, twb, twt, 37)
+    for name in ("phi", "ux", "uy", "uz", "T"):
+        assert np.array_equal(d1.get_field(name), d2.get_field(name)), name
+    assert np.array_equal(c1, c2)
+    d1.close()
+    d2.close()
+
+
+def test_per_cell_loss_term():
+    """The optional per-cell dL/dphi^N enters like the centroid term: with
+    dL/dphi = a . (x - c) / M it reproduces the centroid seed a."""
+    cfg, twb, twt, _ = _small("capture")
+    src = [list(s) for s in cfg["heat_sources"]]
+    d, c = _centroid_gpu(cfg, src, twb, twt, 40, taped=True)
+    M, _ = d.reduce()
+    a = np.array([0.7, -0.2, 0.4])
+    nx, ny, nz = cfg["shape"]
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    dphi = (a[0] * (x - c[0]) + a[1] * (y - c[1]) + a[2] * (z - c[2])) / M
+    g1 = d.tape_adjoint(a)
+    g2 = d.tape_adjoint(np.zeros(3), dphi)
+    d.close()
+    for u, v in zip(g1, g2):
+        assert np.max(np.abs(u - v)) <= 1e-12 * max(np.max(np.abs(u)), 1e-300)
+
+
+def test_design_channel_fp32_matches_fp64():
+    """The 96 x 64 x 64 design channel over 2000 steps (checkpoints every 45
+    steps): FP32 forward and reverse against FP64 on the same GPU."""
+    out = {}
+    for prec in ("fp64", "fp32"):
+        cfg = W.capture_design(precision=prec)
+        nx, ny, nz = cfg["shape"]
+        src = [list(s) for s in cfg["heat_sources"]]
+        d = gpu_domain(cfg)
+        c0 = d.reduce()[1]
+        target = np.array([44.0, c0[1], c0[2]])
+        d.step_taped(2000)
+        c = d.reduce()[1]
+        out[prec] = (c, d.tape_adjoint(2.0 * (c - target)))
+        d.close()
+    c64, (s64, b64, t64) = out["fp64"]
+    c32, (s32, b32, t32) = out["fp32"]
+    print("centroid", c64, c32, "dsrc", s64, s32, flush=True)
+    assert np.max(np.abs(c32 - c64)) <= 1e-5
+    # Q, x, y, z of the heater; z is ~1e-10 by the mirror symmetry of the set-up
+    # in z, so each is held to the scale of the largest
+    scale = np.max(np.abs(s64)) / 100.0
+    for j in range(4):
+        assert abs(s32[0, j] - s64[0, j]) <= 1e-4 * max(abs(s64[0, j]), scale), j
+    assert np.max(np.abs(b32 - b64)) <= 1e-4 * np.max(np.abs(b64))
+    assert np.max(np.abs(t32 - t64)) <= 1e-4 * np.max(np.abs(t64))
+
+
+def test_torch_function_two_forwards_then_backward():
+    """centroid_run: the backward of a call made before another call re-tapes
+    its own inputs; its gradients equal tcp_tape_adjoint's on those inputs."""
+    import torch
+    from paper_2401_03041_amd import tcplb
+    cfg, twb, twt, _ = _small("capture")
+    steps = 30
+    d = gpu_domain(cfg)
+    fn = tcplb.centroid_run(d, steps)
+    src_a = torch.tensor([[0.8, 20.0, -0.5, 15.0, 6.0, 0.0]], dtype=torch.float64, requires_grad=True)
+    src_b = torch.tensor([[0.5, 18.0, -0.5, 10.0, 6.0, 0.0]], dtype=torch.float64, requires_grad=True)
+    bot = torch.tensor(twb, requires_grad=True)
+    top = torch.tensor(twt, requires_grad=True)
+    target = torch.tensor([20.0, 3.0, 12.0], dtype=torch.float64)
+    la = torch.sum((fn(src_a, bot, top) - target) ** 2)
+    lb = torch.sum((fn(src_b, bot, top) - target) ** 2)
+    la.backward()
+    g_src, g_bot = src_a.grad.numpy().copy(), bot.grad.numpy().copy()
+    ref = _adjoint(cfg, src_a.detach().tolist(), twb, twt, steps, target.numpy())
+    assert np.array_equal(g_src[:, :4], ref[0])
+    assert np.array_equal(g_bot, ref[1])
+    bot.grad = None
+    lb.backward()
+    ref_b = _adjoint(cfg, src_b.detach().tolist(), twb, twt, steps, target.numpy())
+    assert np.array_equal(src_b.grad.numpy()[:, :4], ref_b[0])
+    assert np.array_equal(bot.grad.numpy(), ref_b[1])
+    d.close()
+
+
+def test_errors():
+    from paper_2401_03041_amd import tcplb
+    cfg, _, _, _ = _small("capture")
+    d = gpu_domain(cfg)
+    with pytest.raises(tcplb.TcpError, match="call out of order"):
+        d.tape_adjoint(np.ones(3))
+    with pytest.raises(tcplb.TcpError, match="invalid argument"):
+        d.step_taped(0)
+    d.close()
+    rk = dict(cfg, thermal="rk2", kappa_h=0.2, kappa_l=0.2)
+    d = gpu_domain(rk)
+    with pytest.raises(tcplb.TcpError, match="unsupported"):
+        d.step_taped(10)
+    d.close()
