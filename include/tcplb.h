@@ -277,6 +277,17 @@ int tcp_tape_adjoint(tcp_domain *d, const double dL_dcentroid[3], const double *
  * array of nx*ny*nz values, asynchronous); exactly one is non-NULL. */
 int tcp_get_field(tcp_domain *d, int which, double *host, void *dev);
 
+/* For callers that cannot allocate device memory: serving loops and
+ * harnesses that forbid hipMalloc.  Same result as tcp_get_field with a host
+ * destination, which allocates and frees a device staging buffer on every
+ * call; this variant stages through a fixed 32 MiB device array of the
+ * library (one per GPU, held until the process ends) and allocates nothing.
+ * At most 4194304 cells (TCP_ERR_UNSUPPORTED beyond).  Runs on the device
+ * that was current at tcp_create (made current for the call).  Synchronises.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (from several threads or streams) race. */
+int tcp_get_field_noalloc(tcp_domain *d, int which, double *host);
+
 /* Passage: App. B (stencil order), Eq. lb_interface, Sec. 2.2, Eq. lb_thermal.
  * Post-collision PDFs of the current step, unshifted FP64, component-major:
  * out[i*N + cell], i in the stencil order of App. B.  Synchronises. */

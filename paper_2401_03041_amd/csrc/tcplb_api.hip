@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -26,6 +27,7 @@ struct tcp_domain {
     tcp_allocator A{};
     bool own_alloc = true;
     hipStream_t stream = nullptr;
+    int device = 0; // the device current at creation
     size_t sb = 8; // bytes per stored field value and hydrodynamic PDF
     size_t pb = 8; // bytes per stored phase-field or thermal PDF
 
@@ -634,6 +636,54 @@ void run_rk_adjoint(tcp_domain *d, int64_t nsteps)
 
 } // namespace
 
+// ---- read-back without allocation ---------------------------------------------
+// Staging array of tcp_get_field_noalloc: FP64 values of one field, one array
+// per GPU (each device holds its own copy), held until the process ends.
+constexpr size_t kNoAllocCells = (size_t)1 << 22; // 4 Mi values, 32 MiB
+static __device__ __align__(256) double scratch[kNoAllocCells];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current: looked up
+// once per device with hipGetSymbolAddress (the array's name is only a host
+// stand-in and must never be passed to a kernel or a copy).
+int scratch_address(tcp_domain *d, int dev, void **out)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        TCP_HIP(d, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(d, TCP_ERR_HIP, "hipGetSymbolAddress returned no address for the staging array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TCP_OK;
+}
+
+// read field `which` of the current state into dev_out (FP64, N values)
+int read_field(tcp_domain *d, int which, double *dev_out)
+{
+    ReadArgs a{};
+    a.geo = d->geo;
+    a.which = which; // TCP_PHI..TCP_RHO use the read-kernel codes 0..7
+    a.phi = d->phi[d->cur];
+    a.T = d->T[d->cur];
+    a.g = d->g[d->cur];
+    for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
+    a.rho_l = d->P.rho_l;
+    a.drho = d->P.rho_h - d->P.rho_l;
+    a.out = dev_out;
+    if (d->sb == 8) launch_read<double>(a, d->stream);
+    else launch_read<float>(a, d->stream);
+    return check_launch(d);
+}
+
+} // namespace
+
 namespace {
 
 // advance nsteps coupled steps from the current state (step graphs on small grids)
@@ -910,6 +960,10 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
         d->own_alloc = false;
     }
     d->stream = static_cast<hipStream_t>(stream);
+    if (hipGetDevice(&d->device) != hipSuccess) {
+        delete d;
+        return fail(nullptr, TCP_ERR_HIP, "hipGetDevice failed");
+    }
     d->sb = p->precision == TCP_FP64 ? 8 : 4;
     d->pb = p->precision == TCP_FP64 ? 8 : (p->precision == TCP_FP32 ? 4 : 2);
     d->geo.nx = p->nx;
@@ -1331,6 +1385,32 @@ int tcp_get_field(tcp_domain *d, int which, double *host, void *dev)
         }
         return TCP_OK;
     });
+}
+
+int tcp_get_field_noalloc(tcp_domain *d, int which, double *host)
+{
+    if (!d || !host) return fail(d, TCP_ERR_ARG, "a domain and a host destination are required");
+    if (which < TCP_PHI || which > TCP_RHO) return fail(d, TCP_ERR_ARG, "unknown field");
+    const size_t N = (size_t)d->geo.N;
+    if (N > kNoAllocCells)
+        return fail(d, TCP_ERR_UNSUPPORTED,
+                    "tcp_get_field_noalloc reads at most 4194304 cells (its 32 MiB staging array); use tcp_get_field");
+    if (d->device < 0 || d->device >= kMaxDevices) return fail(d, TCP_ERR_UNSUPPORTED, "device index out of range");
+    int prev = 0;
+    TCP_HIP(d, hipGetDevice(&prev));
+    if (prev != d->device) TCP_HIP(d, hipSetDevice(d->device));
+    const int rc = guarded(d, [&]() -> int {
+        void *ptr = nullptr;
+        int r = scratch_address(d, d->device, &ptr);
+        if (r != TCP_OK) return r;
+        r = read_field(d, which, static_cast<double *>(ptr));
+        if (r != TCP_OK) return r;
+        TCP_HIP(d, hipMemcpyAsync(host, ptr, N * sizeof(double), hipMemcpyDeviceToHost, d->stream));
+        TCP_HIP(d, hipStreamSynchronize(d->stream));
+        return TCP_OK;
+    });
+    if (prev != d->device) (void)hipSetDevice(prev);
+    return rc;
 }
 
 int tcp_get_pdfs(tcp_domain *d, int which, double *host_out)

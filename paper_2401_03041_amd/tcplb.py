@@ -26,7 +26,7 @@ KERNELS = ("phase", "hydro", "thermal", "rk", "step", "adjoint", "coupled_adjoin
 EXPORTS = (
     "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_droplets",
     "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_step_taped", "tcp_tape_adjoint",
-    "tcp_warm_temperature", "tcp_thermal_adjoint", "tcp_get_field",
+    "tcp_warm_temperature", "tcp_thermal_adjoint", "tcp_get_field", "tcp_get_field_noalloc",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
     "tcp_set_profiling", "tcp_set_fusion", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
     "tcp_last_error",
@@ -100,6 +100,7 @@ def load() -> C.CDLL:
         "tcp_warm_temperature": [vp, i64, C.c_double, i64, C.POINTER(i64), dp],
         "tcp_thermal_adjoint": [vp, i64, dp, dp, dp, dp],
         "tcp_get_field": [vp, C.c_int, dp, vp],
+        "tcp_get_field_noalloc": [vp, C.c_int, dp],
         "tcp_get_pdfs": [vp, C.c_int, dp],
         "tcp_reduce": [vp, dp, dp],
         "tcp_state_bytes": [vp, C.POINTER(C.c_size_t)],
@@ -314,6 +315,13 @@ class Domain:
             return out
         a = np.empty(self.shape3, dtype=np.float64)
         self._check(self._lib.tcp_get_field(self._h, which, _dptr(a), None), "get_field")
+        return a
+
+    def get_field_noalloc(self, name: str):
+        """FP64 field, shape (nz, ny, nx), read back through the library's fixed
+        staging array (no device allocation; at most 4194304 cells)."""
+        a = np.empty(self.shape3, dtype=np.float64)
+        self._check(self._lib.tcp_get_field_noalloc(self._h, FIELDS[name], _dptr(a)), "get_field_noalloc")
         return a
 
     def fields(self, names=("phi", "ux", "uy", "uz", "p", "T")) -> dict:
