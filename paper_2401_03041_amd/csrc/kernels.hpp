@@ -76,6 +76,9 @@ struct RkArgs {
     double wet[2];        // (4/xi) cos(contact angle) of the bottom and top wall
     int first, last;
     HeatSources src;
+    void *coef;           // per-step coefficients a_x, a_y, a_z, kappa, q (five fields)
+    int gk;               // kappa_H != kappa_L: a and kappa come from coef
+    int hq;               // heat sources present: q comes from coef
 };
 
 // Wave priority (s_setprio) while a cell update issues its PDF pull and its
@@ -108,6 +111,9 @@ template <int Q, typename P, typename S, typename R>
 void launch_thermal(const ThermalArgs &a, hipStream_t s);
 template <typename S, typename R>
 void launch_rk(const RkArgs &a, hipStream_t s);
+// once per step before the stages: the coefficient fields the stages read
+template <typename S, typename R>
+void launch_rk_coef(const RkArgs &a, hipStream_t s);
 
 // K1 + K2 + K3 (thermal LB) of one step fused into one kernel (kernels_step.hip)
 struct StepArgs {

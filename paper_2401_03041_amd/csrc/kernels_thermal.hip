@@ -13,7 +13,9 @@
 //   R(theta) = -u . grad theta + (kappa_H - kappa_L) grad phi . grad theta
 //              + kappa(phi) lap theta + q_T
 // with the isotropic D3Q27 stencils, ghost 2 T_w - theta at walls and the
-// contact-angle ghost for phi.
+// contact-angle ghost for phi.  Everything but theta is constant within a
+// step, so a coefficient pass per step evaluates the phi stencil and the
+// heat source once, and the stages read the result.
 #include "cell_thermal.hpp"
 
 namespace tcp {
@@ -42,13 +44,59 @@ void launch_thermal(const ThermalArgs &a, hipStream_t s)
     hipLaunchKernelGGL((k_thermal<Q, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
+// Coefficients of the right-hand side, constant within a step (phi^{n+1},
+// u^{n+1} and the sources are held while the stages run):
+//   R(theta) = a . grad theta + kappa lap theta + q,  a = -u + (kappa_H - kappa_L) grad phi,
+// written once per step as five fields (a_x, a_y, a_z, kappa, q); the stages
+// then read a and kappa only with a conductivity ratio (gk) and q only with
+// heat sources (hq), and otherwise take a = -u^{n+1} and kappa = kappa_L.
 template <typename S, typename R, bool WALL>
-__device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb, int x, int y, int z)
+__device__ __forceinline__ void rk_coef_cell(const RkArgs &a, const Nbr &nb, int x, int y, int z)
+{
+    S *co = static_cast<S *>(a.coef);
+    const int64_t N = a.geo.N;
+    if (a.gk) {
+        const S *pp = static_cast<const S *>(a.phi);
+        R gp[3] = {R(0), R(0), R(0)};
+#pragma unroll
+        for (int i = 1; i < 27; ++i) {
+            const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+            const R w = R(weight<27>(i));
+            R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+            if (WALL && nb.ghost(ey)) pv = nb.phi_ghost(pv, ey, a.wet);
+            gp[0] += R(ex) * w * pv;
+            gp[1] += R(ey) * w * pv;
+            gp[2] += R(ez) * w * pv;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+            st(elem(co + k * N, nb.c), -ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c)) + R(3) * R(a.dkappa) * gp[k]);
+        const R phic = fmin(fmax(ld<R>(elem(pp, nb.c)), R(0)), R(1));
+        st(elem(co + 3 * N, nb.c), R(a.kappa_l) + phic * R(a.dkappa));
+    }
+    if (a.hq) st(elem(co + 4 * N, nb.c), heat_source<R>(a.src, x, y, z));
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_rk_coef(const RkArgs a, const Tiling t)
+{
+    int x, y, z;
+    if (!cell_of_thread(t, a.geo, x, y, z)) return;
+    const Nbr nb(a.geo, x, y, z);
+    if (nb.below || nb.above)
+        rk_coef_cell<S, R, true>(a, nb, x, y, z);
+    else
+        rk_coef_cell<S, R, false>(a, nb, x, y, z);
+}
+
+template <typename S, typename R, bool WALL, bool GK, bool HQ>
+__device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb)
 {
     const S *th = static_cast<const S *>(a.theta_in);
-    const S *pp = static_cast<const S *>(a.phi);
+    const S *co = static_cast<const S *>(a.coef);
+    const int64_t N = a.geo.N;
     const R tc = ld<R>(elem(th, nb.c));
-    R gt[3] = {R(0), R(0), R(0)}, gp[3] = {R(0), R(0), R(0)}, lap = R(0);
+    R gt[3] = {R(0), R(0), R(0)}, lap = R(0);
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
@@ -58,29 +106,19 @@ __device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb, int x, i
             const double *tw = ey < 0 ? a.twb : a.twt;
             tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;
         }
-        R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
-        if (WALL && nb.ghost(ey)) pv = nb.phi_ghost(pv, ey, a.wet);
-        gt[0] += R(ex) * w * tv;
-        gt[1] += R(ey) * w * tv;
-        gt[2] += R(ez) * w * tv;
-        lap += w * (tv - tc);
-        gp[0] += R(ex) * w * pv;
-        gp[1] += R(ey) * w * pv;
-        gp[2] += R(ez) * w * pv;
+        if (ex) gt[0] += R(ex) * w * tv;
+        if (ey) gt[1] += R(ey) * w * tv;
+        if (ez) gt[2] += R(ez) * w * tv;
+        lap += w * tv;
     }
-    R u[3];
+    lap = R(6) * (lap - R(1.0 - weight<27>(0)) * tc);
+    R av[3], kap;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        gt[k] *= R(3);
-        gp[k] *= R(3);
-        u[k] = ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
-    }
-    lap *= R(6);
-    const R phic = fmin(fmax(ld<R>(elem(pp, nb.c)), R(0)), R(1));
-    const R kap = R(a.kappa_l) + phic * R(a.dkappa);
-    const R k = -(u[0] * gt[0] + u[1] * gt[1] + u[2] * gt[2]) +
-                R(a.dkappa) * (gp[0] * gt[0] + gp[1] * gt[1] + gp[2] * gt[2]) + kap * lap +
-                heat_source<R>(a.src, x, y, z);
+    for (int k = 0; k < 3; ++k)
+        av[k] = GK ? ld<R>(elem(co + k * N, nb.c)) : -ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
+    kap = GK ? ld<R>(elem(co + 3 * N, nb.c)) : R(a.kappa_l);
+    R k = R(3) * (av[0] * gt[0] + av[1] * gt[1] + av[2] * gt[2]) + kap * lap;
+    if (HQ) k += ld<R>(elem(co + 4 * N, nb.c));
     S *ap = static_cast<S *>(a.acc);
     const R T = ld<R>(elem(static_cast<const S *>(a.T), nb.c));
     const R acc = (a.first ? R(0) : ld<R>(elem(ap, nb.c))) + R(a.w_acc) * k;
@@ -92,23 +130,34 @@ __device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb, int x, i
     }
 }
 
-template <typename S, typename R>
+template <typename S, typename R, bool GK, bool HQ>
 __global__ void __launch_bounds__(kTX *kTY) k_rk_stage(const RkArgs a, const Tiling t)
 {
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
     const Nbr nb(a.geo, x, y, z);
     if (nb.below || nb.above)
-        rk_cell<S, R, true>(a, nb, x, y, z);
+        rk_cell<S, R, true, GK, HQ>(a, nb);
     else
-        rk_cell<S, R, false>(a, nb, x, y, z);
+        rk_cell<S, R, false, GK, HQ>(a, nb);
+}
+
+template <typename S, typename R>
+void launch_rk_coef(const RkArgs &a, hipStream_t s)
+{
+    if (!a.gk && !a.hq) return;
+    const Tiling t = make_tiling(a.geo);
+    hipLaunchKernelGGL((k_rk_coef<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
 template <typename S, typename R>
 void launch_rk(const RkArgs &a, hipStream_t s)
 {
     const Tiling t = make_tiling(a.geo);
-    hipLaunchKernelGGL((k_rk_stage<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    if (a.gk && a.hq) hipLaunchKernelGGL((k_rk_stage<S, R, true, true>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    else if (a.gk) hipLaunchKernelGGL((k_rk_stage<S, R, true, false>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    else if (a.hq) hipLaunchKernelGGL((k_rk_stage<S, R, false, true>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    else hipLaunchKernelGGL((k_rk_stage<S, R, false, false>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
 #define TCP_THERMAL_INST(Q)                                                                                  \
@@ -122,5 +171,7 @@ TCP_THERMAL_INST(27)
 #undef TCP_THERMAL_INST
 template void launch_rk<double, double>(const RkArgs &, hipStream_t);
 template void launch_rk<float, float>(const RkArgs &, hipStream_t);
+template void launch_rk_coef<double, double>(const RkArgs &, hipStream_t);
+template void launch_rk_coef<float, float>(const RkArgs &, hipStream_t);
 
 } // namespace tcp

@@ -33,6 +33,7 @@ struct tcp_domain {
 
     void *h[2]{}, *g[2]{}, *f[2]{}, *phi[2]{}, *u[3]{}, *T[2]{}; // [cur]: time level n
     void *rk[3]{}; // theta_a, theta_b, acc
+    void *rkc = nullptr; // RK right-hand side coefficients: a_x, a_y, a_z, kappa, q
     double *twb = nullptr, *twt = nullptr;
     double *partial = nullptr, *out4 = nullptr;
     HeatSources src{};
@@ -304,6 +305,9 @@ void thermal_step(tcp_domain *d)
     a.kappa_l = P.kappa_l;
     a.dkappa = P.kappa_h - P.kappa_l;
     a.src = d->src;
+    a.coef = d->rkc;
+    a.gk = P.kappa_h != P.kappa_l;
+    a.hq = d->src.n > 0;
     if (P.thermal == TCP_THERMAL_RK2) {
         // theta = T + k1/2; T_new = T + R(theta)
         a.theta_in = d->T[d->cur];
@@ -314,7 +318,9 @@ void thermal_step(tcp_domain *d)
         a.a_next = 0.5;
         a.w_acc = 0.0;
         {
+            // the per-step coefficient pass is timed with the first stage
             KernelTimer t(d, TCP_K_RK);
+            launch_rk_coef<S, S>(a, d->stream);
             launch_rk<S, S>(a, d->stream);
         }
         a.theta_in = d->rk[0];
@@ -339,6 +345,7 @@ void thermal_step(tcp_domain *d)
         a.w_acc = wacc[s];
         a.a_next = anext[s];
         KernelTimer t(d, TCP_K_RK);
+        if (s == 0) launch_rk_coef<S, S>(a, d->stream);
         launch_rk<S, S>(a, d->stream);
     }
 }
@@ -991,6 +998,7 @@ int tcp_create(const tcp_params *p, const tcp_allocator *alloc, void *stream, tc
     for (int k = 0; k < 3; ++k) req.push_back({&d->u[k], N * sb});
     if (p->thermal != TCP_THERMAL_LB)
         for (int k = 0; k < (p->thermal == TCP_THERMAL_RK2 ? 1 : 3); ++k) req.push_back({&d->rk[k], N * sb});
+    if (p->thermal != TCP_THERMAL_LB) req.push_back({&d->rkc, 5 * N * sb});
     void *twb = nullptr, *twt = nullptr, *partial = nullptr, *out4 = nullptr;
     req.push_back({&twb, ncol * sizeof(double)});
     req.push_back({&twt, ncol * sizeof(double)});
@@ -1565,7 +1573,20 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     b[TCP_K_HYDRO] = (54.0 + 5.0) * sb;                // g in/out, phi^n, T^n in, u out
     // f in/out, u and phi^{n+1} in, T out; FP32/FP16 deviation storage also reads T^n
     b[TCP_K_THERMAL] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * pb + (d->pb <= 4 ? 6.0 : 5.0) * sb : 0.0;
-    b[TCP_K_RK] = d->P.thermal == TCP_THERMAL_RK2 ? 13.0 * sb : (d->P.thermal == TCP_THERMAL_RK4 ? 33.0 * sb : 0.0);
+    {
+        // whole step of RK stages: each stage reads theta, a (or u), T and the
+        // accumulator, kappa with a conductivity ratio and q with heat sources,
+        // and writes the next argument / accumulator (stage 1 reads T once as
+        // theta and T); the per-step coefficient pass reads phi and u and writes
+        // a, kappa (conductivity ratio) and writes q (heat sources)
+        const double gk = d->P.kappa_h != d->P.kappa_l ? 1.0 : 0.0, hq = d->src.n > 0 ? 1.0 : 0.0;
+        if (d->P.thermal == TCP_THERMAL_RK2)
+            b[TCP_K_RK] = (11.0 + 2.0 * (gk + hq) + 8.0 * gk + hq) * sb;
+        else if (d->P.thermal == TCP_THERMAL_RK4)
+            b[TCP_K_RK] = (29.0 + 4.0 * (gk + hq) + 8.0 * gk + hq) * sb;
+        else
+            b[TCP_K_RK] = 0.0;
+    }
     // fused step: all PDFs in/out; phi^n, T^n, u^n in; phi^{n+1}, u^{n+1}, T^{n+1} out
     b[TCP_K_STEP] = d->P.thermal == TCP_THERMAL_LB
                         ? 2.0 * (d->P.q_pf + d->P.q_thermal) * pb + 54.0 * sb + 10.0 * sb
