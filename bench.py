@@ -151,6 +151,75 @@ def adjoint_cost(cfg: dict, updates: int, precision: str) -> dict:
             "adjoint_bytes_per_cell_update": a_bytes}
 
 
+def coupled_adjoint_cost(precision: str, steps: int = 2000, segment: int = 0) -> dict:
+    """Adjoint of the coupled step on the heater-design channel (96 x 64 x 64,
+    walls, moving lid, heater, hemisphere; D3Q15 phase field + D3Q27 hydro +
+    D3Q7 thermal LB): the gradient of the final centroid's squared distance to
+    a target with respect to the heater (Q, x, y, z) and the wall
+    temperatures.  Times the plain forward run of `steps` steps, the taped run
+    (checkpoints every `segment` steps, 0: ceil(sqrt(steps)); 1 stores every
+    state) and the reverse sweep (segment recomputation plus the reverse
+    kernels); cost = (taped + reverse) / plain.
+    Inputs are resident in HBM; the tape is allocated by an untimed warm-up."""
+    import numpy as np
+    import torch
+
+    from paper_2401_03041_amd import tcplb
+    from paper_2401_03041_amd import workloads as W
+    cfg = W.capture_design(precision=precision, steps=steps)
+    d = tcplb.domain_from_workload(cfg)
+    c0 = d.reduce()[1]
+    target = np.array([44.0, c0[1], c0[2]])
+    st = d.save_state()
+    d.step_taped(steps, segment)  # warm-up: allocates the tape, builds the step graphs
+    d.tape_adjoint(np.zeros(3))
+
+    def timed(fn):
+        d.load_state(st)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        d.synchronize()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, out
+
+    t_fwd, _ = timed(lambda: d.step(steps))
+    t_tape, _ = timed(lambda: d.step_taped(steps, segment))
+    c = d.reduce()[1]
+    t0 = time.perf_counter()
+    g = d.tape_adjoint(2.0 * (c - target))
+    t_rev = time.perf_counter() - t0
+    d.set_profiling(True)
+    d.kernel_times()
+    d.load_state(st)
+    d.step_taped(steps, segment)
+    d.tape_adjoint(2.0 * (c - target))
+    kt = d.kernel_times()
+    d.set_profiling(False)
+    bpc = d.algorithmic_bytes()
+    ncell = d.ncell
+    d.close()
+    del d
+    torch.cuda.empty_cache()
+    rev_ms, rev_n = kt["coupled_adjoint"]
+    fwd_ms, fwd_n = kt["step"]
+    rev_avg, fwd_avg = rev_ms / rev_n, fwd_ms / fwd_n
+    cost = (t_tape + t_rev) / t_fwd
+    _log(f"{precision} coupled adjoint: forward {1e3 * t_fwd:.1f} ms, taped {1e3 * t_tape:.1f} ms, "
+         f"reverse {1e3 * t_rev:.1f} ms ({steps} steps): cost {cost:.2f}x")
+    return {"workload": "heater-design channel 96x64x64 (walls, lid 0.02, heater Q=0.8 w=8, hemisphere R=8), "
+                        "D3Q15 phase field + D3Q27 hydro + D3Q7 thermal LB; loss |centroid(phi^N) - target|^2; "
+                        "gradients w.r.t. heater Q, x, y, z and both wall-temperature fields",
+            "precision": precision, "steps": steps, "segment": segment if segment > 0 else int(np.ceil(np.sqrt(steps))),
+            "forward_ms": round(1e3 * t_fwd, 2), "taped_forward_ms": round(1e3 * t_tape, 2),
+            "reverse_ms": round(1e3 * t_rev, 2), "adjoint_over_forward": round(cost, 3),
+            "reverse_step_kernels_avg_ms": round(rev_avg, 5), "forward_step_kernel_avg_ms": round(fwd_avg, 5),
+            "reverse_step_over_forward_step": round(rev_avg / fwd_avg, 3),
+            "reverse_step_bytes_per_cell": bpc["coupled_adjoint"],
+            "reverse_step_algorithmic_GBs": round(bpc["coupled_adjoint"] * ncell / (rev_avg * 1e-3) / 1e9, 1),
+            "dL_dsource": [round(float(v), 9) for v in g[0][0]]}
+
+
 def roofline(res: dict, precision: str) -> dict:
     k = res["kernels"]["step"]
     achieved = k["achieved_GBs"]
@@ -302,6 +371,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-paper-block", action="store_true",
                     help="skip the FP64 runs on the paper's 512 x 256 x 256 benchmark shape")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-cost legs")
     ap.add_argument("--oracle-box", type=int, default=64)
     ap.add_argument("--oracle-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernel")
@@ -324,9 +394,14 @@ def main() -> int:
     fp64 = run_gpu(cfg, fp64_steps, max(2, args.warmup // 4), "fp64") if fp64_steps > 0 else None
     fp16_steps = args.steps // 2 if args.fp16_steps is None else args.fp16_steps
     fp16 = run_gpu(cfg, fp16_steps, max(2, args.warmup // 4), "fp16") if fp16_steps > 0 else None
-    adjoint = adjoint_cost(cfg, 20, "fp32")
-    adjoint["adjoint_update_over_coupled_step"] = round(adjoint["adjoint_ms_per_update"] / fp32["ms_per_step"], 3)
-    adjoint["rk4"] = adjoint_cost(dict(cfg, thermal="rk4"), 10, "fp32")
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = {"coupled": coupled_adjoint_cost("fp32"), "coupled_fp64": coupled_adjoint_cost("fp64")}
+        thermal = adjoint_cost(cfg, 20, "fp32")
+        thermal["adjoint_update_over_coupled_step"] = round(thermal["adjoint_ms_per_update"] / fp32["ms_per_step"],
+                                                            3)
+        adjoint["thermal_lb"] = thermal
+        adjoint["thermal_rk4"] = adjoint_cost(dict(cfg, thermal="rk4"), 10, "fp32")
     pblock = None if args.no_paper_block else paper_block(10, 2)
     base = None if args.no_cpu_baseline else cpu_baseline(cfg, args.oracle_box, args.oracle_steps)
 
@@ -360,7 +435,8 @@ def main() -> int:
                         "ms_per_step": round(fp64["ms_per_step"], 4), "dtype": "f64",
                         "roofline": roofline(fp64, "fp64"), "effective_GBs": round(fp64["effective_GBs"], 1),
                         "step_bytes_per_cell": fp64["step_bytes_per_cell"]}
-    line["adjoint"] = adjoint
+    if adjoint is not None:
+        line["adjoint"] = adjoint
     if pblock is not None:
         line["paper_block"] = pblock
     if fp16 is not None:

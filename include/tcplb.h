@@ -239,13 +239,17 @@ int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, doub
 
 /* Passage: Algorithm 1 (the steps that are taped); Sec. 3.3 (heater design
  * by the droplet's capture, which the gradients of tcp_tape_adjoint serve).
- * Advance nsteps coupled steps exactly as tcp_step does, and keep what their
- * adjoint needs: the state (all PDFs, phi, T, u) at the start of every
- * segment of `segment` steps (segment <= 0: ceil(sqrt(nsteps))), and the heat
- * sources and wall temperatures in force.  Replaces any earlier tape; the
- * device memory (nseg + segment + 1 states plus the reverse sweep's
- * workspace, about 2.2 states) is allocated through the domain's allocator on
- * the first call and again when the sizes change.  Thermal LB only
+ * Advance nsteps coupled steps (the fused step kernel, bitwise the steps
+ * tcp_step takes with fusion on) and keep what their adjoint needs: the
+ * state (all PDFs, phi, T, u) at the start of every segment of `segment`
+ * steps and at the end (segment <= 0: ceil(sqrt(nsteps))), the inner states
+ * of the last segment, and the heat sources and wall temperatures in force.
+ * The reverse sweep recomputes the inner states of every other segment from
+ * its checkpoint; segment = 1 stores every state and recomputes nothing.
+ * Replaces any earlier tape; the device memory (nseg + segment states of the
+ * domain's state size plus the reverse sweep's workspace, about 2.2 states)
+ * is allocated through the domain's allocator on the first call and again
+ * when the sizes change (TCP_ERR_OOM if it does not fit).  Thermal LB only
  * (TCP_ERR_UNSUPPORTED for RK).  Asynchronous.  TCP_ERR_ARG for nsteps < 1,
  * TCP_ERR_STATE before tcp_initialize. */
 int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment);
@@ -260,11 +264,12 @@ int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment);
  * nx*ny*nz values, or NULL).  Returns, as tcp_thermal_adjoint does, dL/dQ_k,
  * dL/dx_k, dL/dy_k, dL/dz_k for every taped heat source (dL_dsource, 4 per
  * source) and dL/dT_w of every column of the bottom and top walls (nx*nz
- * values each, x fastest); each output may be NULL.  Each segment is
- * recomputed from its checkpoint, then undone step by step, last to first,
- * with three reverse kernels per step (thermal, hydrodynamic, phase field:
- * recompute of the cell's update and its vector-Jacobian product, with link
- * and stencil adjoints gathered from the neighbours); arithmetic in the
+ * values each, x fastest); each output may be NULL.  Segments are undone
+ * last to first, each recomputed from its checkpoint unless its states are
+ * at hand, then step by step with one reverse kernel per step (the thermal,
+ * hydrodynamic and phase-field updates of a cell in turn: recompute of the
+ * cell's update and its vector-Jacobian product, with link and stencil
+ * adjoints gathered from the neighbours); arithmetic in the
  * domain's precision (FP32 for FP16 PDFs), gradient sums in FP64.  The
  * domain's current state is not touched.  Synchronises.  TCP_ERR_STATE
  * without a tape; TCP_ERR_ARG for a missing or non-finite dL_dcentroid. */

@@ -151,19 +151,38 @@ __host__ __device__ __forceinline__ R pf_forward(const PfCoef &c, const R h[Q], 
     return phi;
 }
 
-// a: adjoint of h*; aphi: adjoint of phi^{n+1}.  Writes mu = adjoint of the
-// pulled h, aG = adjoint of the gradient, au = adjoint of u^n.
+// zeroth and first moments of a pulled PDF vector
 template <int Q, typename R>
-__host__ __device__ __forceinline__ void pf_vjp(const PfCoef &c, const R h[Q], const R G[3], const R u[3],
-                                                const R a[Q], R aphi, R mu[Q], R aG[3], R au[3])
+__host__ __device__ __forceinline__ void moments01(const R f[Q], R &m0, R m1[3])
 {
-    // forward intermediates
-    R phi = R(0), j[3] = {R(0), R(0), R(0)};
+    m0 = R(0);
+    for (int b = 0; b < 3; ++b) m1[b] = R(0);
+#pragma unroll
     for (int i = 0; i < Q; ++i) {
-        phi += h[i];
+        m0 += f[i];
         for (int b = 0; b < 3; ++b)
-            if (vel<Q>(i, b)) j[b] += R(vel<Q>(i, b)) * h[i];
+            if (vel<Q>(i, b)) m1[b] += R(vel<Q>(i, b)) * f[i];
     }
+}
+
+// dL/df_i of a pulled PDF from the adjoints of its zeroth and first moments
+template <int Q, typename R>
+__host__ __device__ __forceinline__ R moment01_adjoint(R a0, const R a1[3], int i)
+{
+    R m = a0;
+    for (int b = 0; b < 3; ++b)
+        if (vel<Q>(i, b)) m += R(vel<Q>(i, b)) * a1[b];
+    return m;
+}
+
+// phi, j: zeroth and first moments of the pulled h; a: adjoint of h*; aphi:
+// adjoint of phi^{n+1}.  Returns the adjoints of phi and j (moment01_adjoint
+// turns them into dL/dh per direction), aG = adjoint of the gradient, au =
+// adjoint of u^n.
+template <int Q, typename R>
+__host__ __device__ __forceinline__ void pf_vjp(const PfCoef &c, R phi, const R j[3], const R G[3], const R u[3],
+                                                const R a[Q], R &aphi, R aj[3], R aG[3], R au[3])
+{
     const R inv = R(1) / sqrt(G[0] * G[0] + G[1] * G[1] + G[2] * G[2] + R(c.eps2));
     const R lam = R(4) * phi * (R(1) - phi) * R(c.inv_xi);
     const R F[3] = {lam * inv * G[0], lam * inv * G[1], lam * inv * G[2]};
@@ -182,7 +201,7 @@ __host__ __device__ __forceinline__ void pf_vjp(const PfCoef &c, const R h[Q], c
     first_order_du<Q, R>(u, v, a, au);
     aphi += A0 * (R(1) - R(1.5) * uu) + R(3) * (A1[0] * u[0] + A1[1] * u[1] + A1[2] * u[2]) +
             R(4.5) * (u[0] * A2u[0] + u[1] * A2u[1] + u[2] * A2u[2]);
-    R aF[3], aj[3];
+    R aF[3];
     for (int b = 0; b < 3; ++b) {
         au[b] += phi * (R(3) * A1[b] + R(9) * A2u[b] - R(3) * A0 * u[b]);
         aF[b] = R(0.5) * A1[b];
@@ -200,13 +219,6 @@ __host__ __device__ __forceinline__ void pf_vjp(const PfCoef &c, const R h[Q], c
     for (int b = 0; b < 3; ++b) aG[b] = lam * inv * aF[b] - lam * inv * inv * inv * p * G[b];
     // lam = 4 phi (1 - phi) / xi
     aphi += alam * R(4) * R(c.inv_xi) * (R(1) - R(2) * phi);
-    // phi = sum h, j = sum h e
-    for (int i = 0; i < Q; ++i) {
-        R m = aphi;
-        for (int b = 0; b < 3; ++b)
-            if (vel<Q>(i, b)) m += R(vel<Q>(i, b)) * aj[b];
-        mu[i] = m;
-    }
 }
 
 // ============================================================================
@@ -243,18 +255,13 @@ __host__ __device__ __forceinline__ R thermal_forward(const ThCoef &c, const R f
     return T;
 }
 
-// a: adjoint of f*; aT: adjoint of T^{n+1}.  Writes mu = adjoint of the pulled
-// f, au / aphi = adjoints of u^{n+1}, phi^{n+1}, aq = adjoint of q.
+// T, j: zeroth and first moments of the pulled f; a: adjoint of f*; aT:
+// adjoint of T^{n+1} on entry, of T (the zeroth moment) on return; aj:
+// adjoint of j; au / aphi = adjoints of u^{n+1}, phi^{n+1}; aq = adjoint of q.
 template <int Q, typename R>
-__host__ __device__ __forceinline__ void thermal_vjp(const ThCoef &c, const R f[Q], const R u[3], R phi,
-                                                     const R a[Q], R aT, R mu[Q], R au[3], R &aphi, R &aq)
+__host__ __device__ __forceinline__ void thermal_vjp(const ThCoef &c, R T, const R j[3], const R u[3], R phi,
+                                                     const R a[Q], R &aT, R aj[3], R au[3], R &aphi, R &aq)
 {
-    R T = R(0), j[3] = {R(0), R(0), R(0)};
-    for (int i = 0; i < Q; ++i) {
-        T += f[i];
-        for (int b = 0; b < 3; ++b)
-            if (vel<Q>(i, b)) j[b] += R(vel<Q>(i, b)) * f[i];
-    }
     const R phic = fmin(fmax(phi, R(0)), R(1));
     const R kap = R(c.kappa_l) + phic * R(c.dkappa);
     const R den = R(0.5) + R(3) * kap;
@@ -274,7 +281,6 @@ __host__ __device__ __forceinline__ void thermal_vjp(const ThCoef &c, const R f[
     aT += A0 * (R(1) - R(1.5) * uu) + R(3) * (A1[0] * u[0] + A1[1] * u[1] + A1[2] * u[2]) +
           R(4.5) * (u[0] * A2u[0] + u[1] * A2u[1] + u[2] * A2u[2]);
     aT -= om1 * (s[0] * u[0] + s[1] * u[1] + s[2] * u[2]);
-    R aj[3];
     for (int b = 0; b < 3; ++b) {
         au[b] += T * (R(3) * A1[b] + R(9) * A2u[b] - R(3) * A0 * u[b]) - om1 * T * s[b];
         aj[b] = om1 * s[b];
@@ -283,12 +289,6 @@ __host__ __device__ __forceinline__ void thermal_vjp(const ThCoef &c, const R f[
     const R aom1 = s[0] * (j[0] - T * u[0]) + s[1] * (j[1] - T * u[1]) + s[2] * (j[2] - T * u[2]);
     const R akap = aom1 * R(3) / (den * den);
     aphi = (phi > R(0) && phi < R(1)) ? R(c.dkappa) * akap : R(0);
-    for (int i = 0; i < Q; ++i) {
-        R m = aT;
-        for (int b = 0; b < 3; ++b)
-            if (vel<Q>(i, b)) m += R(vel<Q>(i, b)) * aj[b];
-        mu[i] = m;
-    }
 }
 
 // ============================================================================
@@ -321,22 +321,54 @@ struct HyFwd {
 __host__ __device__ constexpr int mom_a(int k) { return k < 3 ? k : (k == 5 ? 1 : 0); }
 __host__ __device__ constexpr int mom_b(int k) { return k < 3 ? k : (k == 3 ? 1 : 2); }
 
+// Raw moments of the pulled g the update depends on: p* = sum g, u0 = sum g e,
+// m = sum g e e (slots xx yy zz xy xz yz).
 template <typename R>
-__host__ __device__ __forceinline__ void hydro_intermediates(const HyCoef &c, const R g[27], const HyIn<R> &in,
-                                                             HyFwd<R> &f)
+struct HyMom {
+    R ps, u0[3], m[6];
+};
+
+template <typename R>
+__host__ __device__ __forceinline__ HyMom<R> hydro_moments(const R g[27])
 {
-    f.ps = R(0);
-    for (int a = 0; a < 3; ++a) f.u0[a] = R(0);
-    for (int k = 0; k < 6; ++k) f.m[k] = R(0);
+    HyMom<R> M;
+    M.ps = R(0);
+    for (int a = 0; a < 3; ++a) M.u0[a] = R(0);
+    for (int k = 0; k < 6; ++k) M.m[k] = R(0);
+#pragma unroll
     for (int i = 0; i < 27; ++i) {
-        f.ps += g[i];
+        M.ps += g[i];
         for (int a = 0; a < 3; ++a)
-            if (vel27(i, a)) f.u0[a] += R(vel27(i, a)) * g[i];
+            if (vel27(i, a)) M.u0[a] += R(vel27(i, a)) * g[i];
         for (int k = 0; k < 6; ++k) {
             const int e = vel27(i, mom_a(k)) * vel27(i, mom_b(k));
-            if (e) f.m[k] += R(e) * g[i];
+            if (e) M.m[k] += R(e) * g[i];
         }
     }
+    return M;
+}
+
+// dL/dg_i of the pulled PDFs from the adjoints of their raw moments
+template <typename R>
+__host__ __device__ __forceinline__ R hydro_moment_adjoint(const HyMom<R> &A, int i)
+{
+    R m = A.ps;
+    for (int b = 0; b < 3; ++b)
+        if (vel27(i, b)) m += R(vel27(i, b)) * A.u0[b];
+    for (int k = 0; k < 6; ++k) {
+        const int e = vel27(i, mom_a(k)) * vel27(i, mom_b(k));
+        if (e) m += R(e) * A.m[k];
+    }
+    return m;
+}
+
+template <typename R>
+__host__ __device__ __forceinline__ void hydro_intermediates(const HyCoef &c, const HyMom<R> &M, const HyIn<R> &in,
+                                                             HyFwd<R> &f)
+{
+    f.ps = M.ps;
+    for (int a = 0; a < 3; ++a) f.u0[a] = M.u0[a];
+    for (int k = 0; k < 6; ++k) f.m[k] = M.m[k];
     const R third = R(1.0 / 3.0);
     const R phic = fmin(fmax(in.phi, R(0)), R(1));
     f.rho = R(c.rho_l) + phic * R(c.drho);
@@ -409,13 +441,55 @@ __host__ __device__ constexpr int mom_exp(int k, int axis)
     return (k < 3) ? (axis == k ? 2 : 0) : (axis == mom_a(k) || axis == mom_b(k) ? 1 : 0);
 }
 
+// For an adjoint vector a over the D3Q27 directions and the six relaxed
+// moments k (exponents p, q, r): ac[k] = sum_i a_i X_p Y_q Z_r (the transpose
+// of the inverse transform) and du[axis] = sum_k c_k sum_i a_i d/du_axis
+// (X_p Y_q Z_r) (its u-derivative), contracted one axis at a time (z, then y,
+// then x), about a fifth of the work of contracting each product separately.
 template <typename R>
-__host__ __device__ __forceinline__ R contract3(const R a[27], const R *X, const R *Y, const R *Z)
+__host__ __device__ __forceinline__ void transform_adjoint(const R a[27], const Cols1D<R> &X, const Cols1D<R> &Y,
+                                                           const Cols1D<R> &Z, const R c[6], R ac[6], R du[3])
 {
-    R s = R(0);
-    for (int i = 0; i < 27; ++i)
-        s += a[i] * X[vel27(i, 0) + 1] * Y[vel27(i, 1) + 1] * Z[vel27(i, 2) + 1];
-    return s;
+    // z: P[r][xa][ya] with the columns and Pd[r][xa][ya] with their derivatives
+    R P[3][3][3], Pd[2][3][3];
+    for (int r = 0; r < 3; ++r)
+        for (int xa = 0; xa < 3; ++xa)
+            for (int ya = 0; ya < 3; ++ya) {
+                P[r][xa][ya] = R(0);
+                if (r < 2) Pd[r][xa][ya] = R(0);
+            }
+#pragma unroll
+    for (int i = 0; i < 27; ++i) {
+        const int xa = vel27(i, 0) + 1, ya = vel27(i, 1) + 1, za = vel27(i, 2) + 1;
+        for (int r = 0; r < 3; ++r) P[r][xa][ya] += a[i] * Z.m[r][za];
+        for (int r = 0; r < 2; ++r) Pd[r][xa][ya] += a[i] * Z.dm[r][za];
+    }
+    for (int b = 0; b < 3; ++b) du[b] = R(0);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const int p = mom_exp(k, 0), q = mom_exp(k, 1), r = mom_exp(k, 2);
+        // y: the three x-slices for this (q, r), and with Y' or Z'
+        R s[3], sy[3], sz[3];
+        for (int xa = 0; xa < 3; ++xa) {
+            s[xa] = sy[xa] = sz[xa] = R(0);
+            for (int ya = 0; ya < 3; ++ya) {
+                s[xa] += P[r][xa][ya] * Y.m[q][ya];
+                if (q < 2) sy[xa] += P[r][xa][ya] * Y.dm[q][ya];
+                if (r < 2) sz[xa] += Pd[r < 2 ? r : 0][xa][ya] * Y.m[q][ya];
+            }
+        }
+        R v = R(0), vx = R(0), vy = R(0), vz = R(0);
+        for (int xa = 0; xa < 3; ++xa) {
+            v += s[xa] * X.m[p][xa];
+            if (p < 2) vx += s[xa] * X.dm[p][xa];
+            if (q < 2) vy += sy[xa] * X.m[p][xa];
+            if (r < 2) vz += sz[xa] * X.m[p][xa];
+        }
+        ac[k] = v;
+        du[0] += c[k] * vx;
+        du[1] += c[k] * vy;
+        du[2] += c[k] * vz;
+    }
 }
 
 template <typename R>
@@ -423,7 +497,7 @@ __host__ __device__ __forceinline__ void hydro_forward(const HyCoef &c, const R 
                                                        R u[3])
 {
     HyFwd<R> f;
-    hydro_intermediates(c, g, in, f);
+    hydro_intermediates(c, hydro_moments(g), in, f);
     const Cols1D<R> X(f.u[0]), Y(f.u[1]), Z(f.u[2]);
     const R uu = f.u[0] * f.u[0] + f.u[1] * f.u[1] + f.u[2] * f.u[2];
     const R ua = f.u[0] * f.acc[0] + f.u[1] * f.acc[1] + f.u[2] * f.acc[2];
@@ -449,14 +523,15 @@ struct HyAdj {
     R phi, gp[3], lap, T, gT[3];
 };
 
-// a: adjoint of g*; au_out: adjoint of u^{n+1}.  Writes mu = adjoint of the
-// pulled g and the adjoints of the stencil inputs.
+// M: raw moments of the pulled g; a: adjoint of g*; au_out: adjoint of
+// u^{n+1}.  Writes the adjoints of the raw moments (hydro_moment_adjoint turns
+// them into dL/dg per direction) and of the stencil inputs.
 template <typename R>
-__host__ __device__ __forceinline__ void hydro_vjp(const HyCoef &c, const R g[27], const HyIn<R> &in, const R a[27],
-                                                   const R au_out[3], R mu[27], HyAdj<R> &ad)
+__host__ __device__ __forceinline__ void hydro_vjp(const HyCoef &c, const HyMom<R> &M, const HyIn<R> &in,
+                                                   const R a[27], const R au_out[3], HyMom<R> &am, HyAdj<R> &ad)
 {
     HyFwd<R> f;
-    hydro_intermediates(c, g, in, f);
+    hydro_intermediates(c, M, in, f);
     const R third = R(1.0 / 3.0);
     const Cols1D<R> X(f.u[0]), Y(f.u[1]), Z(f.u[2]);
 
@@ -474,12 +549,10 @@ __host__ __device__ __forceinline__ void hydro_vjp(const HyCoef &c, const R g[27
         a_acc[b] = R(-1.5) * A0 * f.u[b] + R(1.5) * A1[b] + R(4.5) * A2u[b];
     }
     // corr_i = sum_k c_k X_p[e_x] Y_q[e_y] Z_r[e_z]
-    for (int k = 0; k < 6; ++k) {
-        const int p = mom_exp(k, 0), q = mom_exp(k, 1), r = mom_exp(k, 2);
-        a_c[k] = contract3(a, X.m[p], Y.m[q], Z.m[r]);
-        if (p < 2) a_u[0] += f.c[k] * contract3(a, X.dm[p], Y.m[q], Z.m[r]);
-        if (q < 2) a_u[1] += f.c[k] * contract3(a, X.m[p], Y.dm[q], Z.m[r]);
-        if (r < 2) a_u[2] += f.c[k] * contract3(a, X.m[p], Y.m[q], Z.dm[r]);
+    {
+        R du[3];
+        transform_adjoint(a, X, Y, Z, f.c, a_c, du);
+        for (int b = 0; b < 3; ++b) a_u[b] += du[b];
     }
     // relaxation: c_xx = (tr + d1 + d2)/3, c_yy = c_xx - d1, c_zz = c_xx - d2, c_off = om1 p_off
     const R sc = (a_c[0] + a_c[1] + a_c[2]) * third;
@@ -587,17 +660,9 @@ __host__ __device__ __forceinline__ void hydro_vjp(const HyCoef &c, const R g[27
     const R a_tau = -f.omega * f.omega * a_omega + a_nu * third;
     const R a_phic = R(c.drho) * a_rho + R(c.dtau) * a_tau;
     if (phi > R(0) && phi < R(1)) ad.phi += a_phic;
-    // raw moments of the pulled g
-    for (int i = 0; i < 27; ++i) {
-        R m = a_ps;
-        for (int b = 0; b < 3; ++b)
-            if (vel27(i, b)) m += R(vel27(i, b)) * a_u0[b];
-        for (int k = 0; k < 6; ++k) {
-            const int e = vel27(i, mom_a(k)) * vel27(i, mom_b(k));
-            if (e) m += R(e) * a_m[k];
-        }
-        mu[i] = m;
-    }
+    am.ps = a_ps;
+    for (int b = 0; b < 3; ++b) am.u0[b] = a_u0[b];
+    for (int k = 0; k < 6; ++k) am.m[k] = a_m[k];
 }
 
 } // namespace tcp

@@ -247,8 +247,7 @@ struct StateSlot {
 // from step n+1, dst for step n), sphi (five fields: dL/d grad phi (3),
 // dL/d lap phi, dL/d phi at the cell) and sT (four fields: dL/d grad T (3),
 // dL/d T at the cell) of the stencil reads of K1/K2, lu1 = dL/du from K1 (in
-// place); lu3 / lphi3 pass K3's local adjoints of u^{n+1} and phi^{n+1} to
-// R2 / R1.  grad_q (per cell) and the wall-column adjoints accumulate in FP64.
+// place).  grad_q (per cell) and the wall-column adjoints accumulate in FP64.
 struct CoupledAdjointArgs {
     Geometry geo;
     StateSlot s0, s1;
@@ -258,7 +257,7 @@ struct CoupledAdjointArgs {
     void *sphi_dst;
     const void *sT_src;
     void *sT_dst;
-    void *lu1, *lu3, *lphi3;
+    void *lu1;
     const double *twb, *twt;
     double uw_bot[3], uw_top[3];
     double wet[2];

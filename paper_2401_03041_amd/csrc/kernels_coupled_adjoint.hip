@@ -13,22 +13,23 @@
 //          cell's own phi^{n+1} as K2 of step n+1 reads it;
 //   sT   = (GammaT_x, GammaT_y, GammaT_z, PiT): the same for T^{n+1};
 //   lu1  = dL/du^{n+1} from K1 of step n+1.
-// Reverse step n, each kernel one thread per cell:
+// Reverse step n, one thread per cell, three phases in turn:
 //   R3 gathers dL/df*^{n+1}(x, i) = mu_f(x + e_i, i) (or -mu_f(x, opp i)
 //      across a wall: anti-bounce-back) and dL/dT^{n+1}(x) from sT (the
 //      transpose of the gradient stencil, with the wall ghosts 2 T_w - T),
 //      recomputes K3 of step n at x and runs it backwards: mu_f, the local
-//      adjoints of u^{n+1}, phi^{n+1} (lu3, lphi3), the heat-source adjoint
+//      adjoints of u^{n+1} and phi^{n+1}, the heat-source adjoint
 //      sum_i w_i dL/df*_i and the wall-temperature adjoints of the reflected
 //      links and of the ghosts;
-//   R2 gathers dL/dg*^{n+1} (bounce-back across walls), adds lu1 + lu3 for
-//      u^{n+1}, recomputes K2 and writes mu_g, sphi and sT of step n;
+//   R2 gathers dL/dg*^{n+1} (bounce-back across walls), adds lu1 and R3's
+//      adjoint for u^{n+1}, recomputes K2 and writes mu_g and sT of step n;
 //   R1 gathers dL/dh*^{n+1} and dL/dphi^{n+1} (transposed gradient and
 //      Laplacian of sphi, with the derivative of the contact-angle ghost,
-//      plus lphi3), recomputes K1, writes mu_h and lu1 and adds its gradient
-//      adjoint to sphi's Gamma.
-// Every gather reads values a cell's neighbours wrote in an earlier launch,
-// so there are no atomics and the result does not depend on scheduling.
+//      plus R3's adjoint), recomputes K1, writes mu_h and lu1, and writes
+//      sphi of step n (R2's stencil adjoints plus K1's gradient adjoint).
+// Every gather reads values the neighbours wrote in the previous reverse
+// step (the src buffers), so there are no atomics, the result does not
+// depend on scheduling, and the three phases can run in one kernel.
 #include "adjoint_math.hpp"
 #include "kernels.hpp"
 
@@ -60,28 +61,57 @@ __device__ __forceinline__ void gather_links(const A *mu, const Geometry &g, con
     }
 }
 
-template <int Q, typename A, typename R>
-__device__ __forceinline__ void store_links(A *mu, const Geometry &g, const Nbr &nb, const R m[Q])
+// A copy of the neighbour offsets that the compiler cannot prove equal to the
+// original, so that it does not keep the offsets the three phases share live
+// from the first phase to the last.
+__device__ __forceinline__ Nbr opaque(const Nbr &nb)
 {
-    const PdfLanes<Q> pl(nb);
+    Nbr o = nb;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) st(mu_at<Q>(mu, g, nb, pl, i, 0, 0, 0), m[i]);
+    for (int k = 0; k < 3; ++k) asm volatile("" : "+v"(o.xo[k]));
+    return o;
 }
 
 // ---------------------------------------------------------------------------
-// R3: thermal LB
+// R3: thermal LB.  Returns K3's local adjoints of u^{n+1} and phi^{n+1}.
 // ---------------------------------------------------------------------------
 template <int Q, typename P, typename S, typename R, bool WALL>
-__device__ __forceinline__ void adj_thermal_cell(const CoupledAdjointArgs &a, const Nbr &nb, int x, int y, int z)
+__device__ __forceinline__ void adj_thermal_cell(const CoupledAdjointArgs &a, const Nbr &nb, R (&au)[3], R &aphi)
 {
     constexpr bool dev = deviation_storage<P>();
     const Geometry &g = a.geo;
     const int64_t N = g.N;
     const uint32_t col = nb.col(0, 0, g);
 
-    // dL/df*^{n+1}
-    R lam[Q];
-    gather_links<Q, S, R, WALL>(static_cast<const S *>(a.mu_src[2]), g, nb, R(-1), lam);
+    // recompute K3 of step n: moments of the pulled f (actual values,
+    // anti-bounce-back), u^{n+1}, phi^{n+1}
+    R T0, j[3];
+    {
+        const P *fs = static_cast<const P *>(a.s0.f);
+        const S *to = static_cast<const S *>(a.s0.T);
+        const PdfLanes<Q> pl(nb);
+        const R t_own = dev ? ld<R>(elem(to, nb.c)) : R(0);
+        R f[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+            const R w = R(weight<Q>(i));
+            if (WALL && nb.ghost(-ey)) {
+                const double *tw = ey > 0 ? a.twb : a.twt;
+                const R fo = ld<R>(elem(pdf_row<Q>(fs, g, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1])) +
+                             w * (dev ? t_own : R(a.t_shift));
+                f[i] = R(2) * w * R(tw[col]) - fo;
+            } else {
+                f[i] = ld<R>(elem(pdf_row<Q>(fs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+                f[i] += w * (dev ? ld<R>(nb.ptr(to, -ex, -ey, -ez)) : R(a.t_shift));
+            }
+        }
+        moments01<Q, R>(f, T0, j);
+    }
+    R u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.s1.u[k]), nb.c));
+    const R phi = ld<R>(elem(static_cast<const S *>(a.s1.phi), nb.c));
 
     // dL/dT^{n+1}: own PiT plus the transposed gradient stencil of K2 of step n+1
     const S *sT = static_cast<const S *>(a.sT_src);
@@ -115,186 +145,189 @@ __device__ __forceinline__ void adj_thermal_cell(const CoupledAdjointArgs &a, co
         gtw[1] = 2.0 * (double)ghost_sum[1];
     }
 
-    // recompute K3 of step n: pulled f (actual values, anti-bounce-back)
-    const P *fs = static_cast<const P *>(a.s0.f);
-    const S *to = static_cast<const S *>(a.s0.T);
-    const PdfLanes<Q> pl(nb);
-    const R t_own = dev ? ld<R>(elem(to, nb.c)) : R(0);
-    R f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
-        const R w = R(weight<Q>(i));
-        if (WALL && nb.ghost(-ey)) {
-            const double *tw = ey > 0 ? a.twb : a.twt;
-            const R fo = ld<R>(elem(pdf_row<Q>(fs, g, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1])) +
-                         w * (dev ? t_own : R(a.t_shift));
-            f[i] = R(2) * w * R(tw[col]) - fo;
-        } else {
-            f[i] = ld<R>(elem(pdf_row<Q>(fs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
-            f[i] += w * (dev ? ld<R>(nb.ptr(to, -ex, -ey, -ez)) : R(a.t_shift));
-        }
-    }
-    R u[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.s1.u[k]), nb.c));
-    const R phi = ld<R>(elem(static_cast<const S *>(a.s1.phi), nb.c));
-
-    R mu[Q], au[3], aphi, aq;
-    thermal_vjp<Q, R>(a.th, f, u, phi, lam, aT, mu, au, aphi, aq);
-    store_links<Q, S, R>(static_cast<S *>(a.mu_dst[2]), g, nb, mu);
-    S *lu3 = static_cast<S *>(a.lu3);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) st(elem(lu3 + k * N, nb.c), au[k]);
-    st(elem(static_cast<S *>(a.lphi3), nb.c), aphi);
-    a.grad_q[nb.c] += (double)aq;
-    if (WALL) {
-        // anti-bounce-back links of step n: f_i = 2 w_i T_w - f*_opp
+    // dL/df*^{n+1}
+    R lam[Q];
+    gather_links<Q, S, R, WALL>(static_cast<const S *>(a.mu_src[2]), g, nb, R(-1), lam);
+    R aj[3], aq;
+    au[0] = au[1] = au[2] = R(0);
+    thermal_vjp<Q, R>(a.th, T0, j, u, phi, lam, aT, aj, au, aphi, aq);
+    {
+        S *mu = static_cast<S *>(a.mu_dst[2]);
+        const PdfLanes<Q> pl(nb);
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const int ey = vel<Q>(i, 1);
-            if (nb.ghost(-ey)) gtw[ey < 0] += 2.0 * weight<Q>(i) * (double)mu[i];
+            const R m = moment01_adjoint<Q, R>(aT, aj, i);
+            st(mu_at<Q>(mu, g, nb, pl, i, 0, 0, 0), m);
+            // anti-bounce-back links of step n: f_i = 2 w_i T_w - f*_opp
+            if (WALL && nb.ghost(-vel<Q>(i, 1))) gtw[vel<Q>(i, 1) < 0] += 2.0 * weight<Q>(i) * (double)m;
         }
+    }
+    a.grad_q[nb.c] += (double)aq;
+    if (WALL) {
         if (nb.below) a.grad_twb[col] += gtw[0];
         if (nb.above) a.grad_twt[col] += gtw[1];
     }
 }
 
-template <int Q, typename P, typename S, typename R>
-__global__ void __launch_bounds__(kTX *kTY) k_adj_thermal(const CoupledAdjointArgs a, const Tiling t)
-{
-    int x, y, z;
-    if (!cell_of_thread(t, a.geo, x, y, z)) return;
-    const Nbr nb(a.geo, x, y, z);
-    if (nb.below || nb.above)
-        adj_thermal_cell<Q, P, S, R, true>(a, nb, x, y, z);
-    else
-        adj_thermal_cell<Q, P, S, R, false>(a, nb, x, y, z);
-}
-
 // ---------------------------------------------------------------------------
-// R2: hydrodynamics
+// R2: hydrodynamics.  au3: K3's adjoint of u^{n+1}; returns the adjoints of
+// the phi^n stencil reads (gradient, Laplacian, own value).
 // ---------------------------------------------------------------------------
 template <typename S, typename R, bool WALL>
-__device__ __forceinline__ void adj_hydro_cell(const CoupledAdjointArgs &a, const Nbr &nb)
+__device__ __forceinline__ void adj_hydro_cell(const CoupledAdjointArgs &a, const Nbr &nb, const R (&au3)[3],
+                                               R (&sp)[5])
 {
     const Geometry &g = a.geo;
     const int64_t N = g.N;
+
+    // recompute K2 of step n: raw moments of the pulled g (bounce-back, moving wall)
+    HyMom<R> M;
+    {
+        const S *gs = static_cast<const S *>(a.s0.g);
+        const PdfLanes<27> pl(nb);
+        R gp[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+            if (WALL && nb.ghost(-ey)) {
+                const double *uw = ey > 0 ? a.uw_bot : a.uw_top;
+                const double eu = ex * uw[0] + ey * uw[1] + ez * uw[2];
+                gp[i] = ld<R>(elem(pdf_row<27>(gs, g, nb.yr[1], nb.zi[1], opposite<27>(i)), pl.xq[1])) +
+                        R(6.0 * weight<27>(i) * eu);
+            } else {
+                gp[i] = ld<R>(elem(pdf_row<27>(gs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+            }
+        }
+        M = hydro_moments<R>(gp);
+    }
+    // stencils of phi^n and T^n (wall ghosts as in the forward kernel)
+    HyIn<R> in;
+    {
+        const S *pp = static_cast<const S *>(a.s0.phi);
+        const S *tp = static_cast<const S *>(a.s0.T);
+        in.phi = ld<R>(elem(pp, nb.c));
+        in.T = ld<R>(elem(tp, nb.c));
+        R lap = R(0);
+        for (int k = 0; k < 3; ++k) in.gp[k] = in.gT[k] = R(0);
+#pragma unroll
+        for (int i = 1; i < 27; ++i) {
+            const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+            const R w = R(weight<27>(i));
+            R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
+            R tv = ld<R>(nb.ptr(tp, ex, ey, ez));
+            if (WALL && nb.ghost(ey)) {
+                pv = nb.phi_ghost(pv, ey, a.wet);
+                const double *tw = ey < 0 ? a.twb : a.twt;
+                tv = R(2) * R(tw[nb.col(ex, ez, g)]) - tv;
+            }
+            if (ex) { in.gp[0] += R(ex) * w * pv; in.gT[0] += R(ex) * w * tv; }
+            if (ey) { in.gp[1] += R(ey) * w * pv; in.gT[1] += R(ey) * w * tv; }
+            if (ez) { in.gp[2] += R(ez) * w * pv; in.gT[2] += R(ez) * w * tv; }
+            lap += w * pv;
+        }
+        for (int k = 0; k < 3; ++k) {
+            in.gp[k] *= R(3);
+            in.gT[k] *= R(3);
+        }
+        in.lap = R(6) * (lap - R(1.0 - weight<27>(0)) * in.phi);
+    }
+    // dL/dg*^{n+1} and dL/du^{n+1}
     R lam[27];
     gather_links<27, S, R, WALL>(static_cast<const S *>(a.mu_src[1]), g, nb, R(1), lam);
     R au[3];
-    const S *lu1 = static_cast<const S *>(a.lu1), *lu3 = static_cast<const S *>(a.lu3);
+    const S *lu1 = static_cast<const S *>(a.lu1);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) au[k] = ld<R>(elem(lu1 + k * N, nb.c)) + ld<R>(elem(lu3 + k * N, nb.c));
+    for (int k = 0; k < 3; ++k) au[k] = ld<R>(elem(lu1 + k * N, nb.c)) + au3[k];
 
-    // recompute K2 of step n: pulled g (bounce-back, moving wall)
-    const S *gs = static_cast<const S *>(a.s0.g);
-    const PdfLanes<27> pl(nb);
-    R gp[27];
-#pragma unroll
-    for (int i = 0; i < 27; ++i) {
-        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        if (WALL && nb.ghost(-ey)) {
-            const double *uw = ey > 0 ? a.uw_bot : a.uw_top;
-            const double eu = ex * uw[0] + ey * uw[1] + ez * uw[2];
-            gp[i] = ld<R>(elem(pdf_row<27>(gs, g, nb.yr[1], nb.zi[1], opposite<27>(i)), pl.xq[1])) +
-                    R(6.0 * weight<27>(i) * eu);
-        } else {
-            gp[i] = ld<R>(elem(pdf_row<27>(gs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
-        }
-    }
-    // stencils of phi^n and T^n (wall ghosts as in the forward kernel)
-    const S *pp = static_cast<const S *>(a.s0.phi);
-    const S *tp = static_cast<const S *>(a.s0.T);
-    HyIn<R> in;
-    in.phi = ld<R>(elem(pp, nb.c));
-    in.T = ld<R>(elem(tp, nb.c));
-    R lap = R(0);
-    for (int k = 0; k < 3; ++k) in.gp[k] = in.gT[k] = R(0);
-#pragma unroll
-    for (int i = 1; i < 27; ++i) {
-        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        const R w = R(weight<27>(i));
-        R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
-        R tv = ld<R>(nb.ptr(tp, ex, ey, ez));
-        if (WALL && nb.ghost(ey)) {
-            pv = nb.phi_ghost(pv, ey, a.wet);
-            const double *tw = ey < 0 ? a.twb : a.twt;
-            tv = R(2) * R(tw[nb.col(ex, ez, g)]) - tv;
-        }
-        if (ex) { in.gp[0] += R(ex) * w * pv; in.gT[0] += R(ex) * w * tv; }
-        if (ey) { in.gp[1] += R(ey) * w * pv; in.gT[1] += R(ey) * w * tv; }
-        if (ez) { in.gp[2] += R(ez) * w * pv; in.gT[2] += R(ez) * w * tv; }
-        lap += w * pv;
-    }
-    for (int k = 0; k < 3; ++k) {
-        in.gp[k] *= R(3);
-        in.gT[k] *= R(3);
-    }
-    in.lap = R(6) * (lap - R(1.0 - weight<27>(0)) * in.phi);
-
-    R mu[27];
+    HyMom<R> am;
     HyAdj<R> ad;
-    hydro_vjp<R>(a.hy, gp, in, lam, au, mu, ad);
-    store_links<27, S, R>(static_cast<S *>(a.mu_dst[1]), g, nb, mu);
-    S *sp = static_cast<S *>(a.sphi_dst);
+    hydro_vjp<R>(a.hy, M, in, lam, au, am, ad);
+    {
+        S *mu = static_cast<S *>(a.mu_dst[1]);
+        const PdfLanes<27> pl(nb);
+#pragma unroll
+        for (int i = 0; i < 27; ++i) st(mu_at<27>(mu, g, nb, pl, i, 0, 0, 0), hydro_moment_adjoint<R>(am, i));
+    }
     S *sT = static_cast<S *>(a.sT_dst);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        st(elem(sp + k * N, nb.c), ad.gp[k]);
-        st(elem(sT + k * N, nb.c), ad.gT[k]);
-    }
-    st(elem(sp + 3 * N, nb.c), ad.lap);
-    st(elem(sp + 4 * N, nb.c), ad.phi);
+    for (int k = 0; k < 3; ++k) st(elem(sT + k * N, nb.c), ad.gT[k]);
     st(elem(sT + 3 * N, nb.c), ad.T);
-}
-
-template <typename S, typename R>
-__global__ void __launch_bounds__(kTX *kTY) k_adj_hydro(const CoupledAdjointArgs a, const Tiling t)
-{
-    int x, y, z;
-    if (!cell_of_thread(t, a.geo, x, y, z)) return;
-    const Nbr nb(a.geo, x, y, z);
-    if (nb.below || nb.above)
-        adj_hydro_cell<S, R, true>(a, nb);
-    else
-        adj_hydro_cell<S, R, false>(a, nb);
+    for (int k = 0; k < 3; ++k) sp[k] = ad.gp[k];
+    sp[3] = ad.lap;
+    sp[4] = ad.phi;
 }
 
 // ---------------------------------------------------------------------------
-// R1: phase field
+// R1: phase field.  aphi3: K3's adjoint of phi^{n+1}; sp: K2's adjoints of
+// the phi^n stencil reads, completed here with K1's gradient adjoint and stored.
 // ---------------------------------------------------------------------------
 template <int Q, typename P, typename S, typename R, bool WALL>
-__device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const Nbr &nb)
+__device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const Nbr &nb, R aphi3, const R (&sp)[5])
 {
     constexpr bool dev = deviation_storage<P>();
     const Geometry &g = a.geo;
     const int64_t N = g.N;
-    R lam[Q];
-    gather_links<Q, S, R, WALL>(static_cast<const S *>(a.mu_src[0]), g, nb, R(1), lam);
+
+    // recompute K1 of step n: phi^n stencil, moments of the pulled h (actual values)
+    R G[3] = {R(0), R(0), R(0)}, phi1, j[3];
+    {
+        const S *po = static_cast<const S *>(a.s0.phi);
+        R pn[27];
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+            pn[k] = ld<R>(nb.ptr(po, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
+            if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);
+        }
+        const P *hs = static_cast<const P *>(a.s0.h);
+        const PdfLanes<Q> pl(nb);
+        R h[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
+            const R w = R(weight<Q>(i));
+            if (WALL && nb.ghost(-ey)) {
+                h[i] = ld<R>(elem(pdf_row<Q>(hs, g, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1]));
+                if (dev) h[i] += w * pn[0];
+            } else {
+                h[i] = ld<R>(elem(pdf_row<Q>(hs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
+                if (dev) h[i] += w * pn[opposite<27>(index27<Q>(i))];
+            }
+        }
+        moments01<Q, R>(h, phi1, j);
+#pragma unroll
+        for (int k = 1; k < 27; ++k) {
+            const R v = R(weight<27>(k)) * pn[k];
+            G[0] += R(vel27(k, 0)) * v;
+            G[1] += R(vel27(k, 1)) * v;
+            G[2] += R(vel27(k, 2)) * v;
+        }
+        for (int k = 0; k < 3; ++k) G[k] *= R(3);
+    }
+    R u[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.s0.u[k]), nb.c));
 
     // dL/dphi^{n+1}: the transposed gradient and Laplacian of step n+1 (K1 and
     // K2 read the same stencil), the cell's own Pi, and K3's local adjoint
-    const S *sp = static_cast<const S *>(a.sphi_src);
-    R aphi = ld<R>(elem(sp + 4 * N, nb.c)) - R(6.0 * (1.0 - weight<27>(0))) * ld<R>(elem(sp + 3 * N, nb.c)) +
-             ld<R>(elem(static_cast<const S *>(a.lphi3), nb.c));
+    const S *spn = static_cast<const S *>(a.sphi_src);
+    R aphi = ld<R>(elem(spn + 4 * N, nb.c)) - R(6.0 * (1.0 - weight<27>(0))) * ld<R>(elem(spn + 3 * N, nb.c)) + aphi3;
     R ghost_sum[2] = {R(0), R(0)};
 #pragma unroll
     for (int k = 1; k < 27; ++k) {
         const int ex = vel27(k, 0), ey = vel27(k, 1), ez = vel27(k, 2);
         const R w = R(weight<27>(k));
         if (!(WALL && nb.ghost(-ey))) {
-            R v = R(6) * ld<R>(nb.ptr(sp + 3 * N, -ex, -ey, -ez));
-            if (ex) v += R(3 * ex) * ld<R>(nb.ptr(sp, -ex, -ey, -ez));
-            if (ey) v += R(3 * ey) * ld<R>(nb.ptr(sp + N, -ex, -ey, -ez));
-            if (ez) v += R(3 * ez) * ld<R>(nb.ptr(sp + 2 * N, -ex, -ey, -ez));
+            R v = R(6) * ld<R>(nb.ptr(spn + 3 * N, -ex, -ey, -ez));
+            if (ex) v += R(3 * ex) * ld<R>(nb.ptr(spn, -ex, -ey, -ez));
+            if (ey) v += R(3 * ey) * ld<R>(nb.ptr(spn + N, -ex, -ey, -ez));
+            if (ez) v += R(3 * ez) * ld<R>(nb.ptr(spn + 2 * N, -ex, -ey, -ez));
             aphi += w * v;
         }
         if (WALL && nb.ghost(ey)) {
-            R v = R(6) * ld<R>(nb.ptr(sp + 3 * N, -ex, 0, -ez));
-            if (ex) v += R(3 * ex) * ld<R>(nb.ptr(sp, -ex, 0, -ez));
-            v += R(3 * ey) * ld<R>(nb.ptr(sp + N, -ex, 0, -ez));
-            if (ez) v += R(3 * ez) * ld<R>(nb.ptr(sp + 2 * N, -ex, 0, -ez));
+            R v = R(6) * ld<R>(nb.ptr(spn + 3 * N, -ex, 0, -ez));
+            if (ex) v += R(3 * ex) * ld<R>(nb.ptr(spn, -ex, 0, -ez));
+            v += R(3 * ey) * ld<R>(nb.ptr(spn + N, -ex, 0, -ez));
+            if (ez) v += R(3 * ez) * ld<R>(nb.ptr(spn + 2 * N, -ex, 0, -ez));
             ghost_sum[ey > 0] += w * v;
         }
     }
@@ -305,64 +338,53 @@ __device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const N
                 ghost_sum[1] * (R(1) + R(a.wet[1]) * (R(1) - R(2) * p1));
     }
 
-    // recompute K1 of step n: phi^n stencil, pulled h (actual values)
-    const S *po = static_cast<const S *>(a.s0.phi);
-    R pn[27];
+    R lam[Q];
+    gather_links<Q, S, R, WALL>(static_cast<const S *>(a.mu_src[0]), g, nb, R(1), lam);
+    R aj[3], aG[3], au[3];
+    pf_vjp<Q, R>(a.pf, phi1, j, G, u, lam, aphi, aj, aG, au);
+    {
+        S *mu = static_cast<S *>(a.mu_dst[0]);
+        const PdfLanes<Q> pl(nb);
 #pragma unroll
-    for (int k = 0; k < 27; ++k) {
-        pn[k] = ld<R>(nb.ptr(po, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
-        if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);
+        for (int i = 0; i < Q; ++i) st(mu_at<Q>(mu, g, nb, pl, i, 0, 0, 0), moment01_adjoint<Q, R>(aphi, aj, i));
     }
-    const P *hs = static_cast<const P *>(a.s0.h);
-    const PdfLanes<Q> pl(nb);
-    R h[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int ex = vel<Q>(i, 0), ey = vel<Q>(i, 1), ez = vel<Q>(i, 2);
-        const R w = R(weight<Q>(i));
-        if (WALL && nb.ghost(-ey)) {
-            h[i] = ld<R>(elem(pdf_row<Q>(hs, g, nb.yr[1], nb.zi[1], opposite<Q>(i)), pl.xq[1]));
-            if (dev) h[i] += w * pn[0];
-        } else {
-            h[i] = ld<R>(elem(pdf_row<Q>(hs, g, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
-            if (dev) h[i] += w * pn[opposite<27>(index27<Q>(i))];
-        }
-    }
-    R G[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int k = 1; k < 27; ++k) {
-        const R v = R(weight<27>(k)) * pn[k];
-        G[0] += R(vel27(k, 0)) * v;
-        G[1] += R(vel27(k, 1)) * v;
-        G[2] += R(vel27(k, 2)) * v;
-    }
-    for (int k = 0; k < 3; ++k) G[k] *= R(3);
-    R u[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) u[k] = ld<R>(elem(static_cast<const S *>(a.s0.u[k]), nb.c));
-
-    R mu[Q], aG[3], au[3];
-    pf_vjp<Q, R>(a.pf, h, G, u, lam, aphi, mu, aG, au);
-    store_links<Q, S, R>(static_cast<S *>(a.mu_dst[0]), g, nb, mu);
     S *sd = static_cast<S *>(a.sphi_dst);
     S *lu1 = static_cast<S *>(a.lu1);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        st(elem(sd + k * N, nb.c), ld<R>(elem(sd + k * N, nb.c)) + aG[k]);
+        st(elem(sd + k * N, nb.c), sp[k] + aG[k]);
         st(elem(lu1 + k * N, nb.c), au[k]);
     }
+    st(elem(sd + 3 * N, nb.c), sp[3]);
+    st(elem(sd + 4 * N, nb.c), sp[4]);
 }
 
-template <int Q, typename P, typename S, typename R>
-__global__ void __launch_bounds__(kTX *kTY) k_adj_pf(const CoupledAdjointArgs a, const Tiling t)
+// One reverse step, the three reverse updates of a cell in one thread (K3, K2,
+// K1 in turn): every value a thread reads from another cell comes from the
+// previous reverse step's buffers, and the adjoints passed between the phases
+// (of u^{n+1}, phi^{n+1} and the phi^n stencil) stay in registers.
+template <int QH, int QF, typename P, typename S, typename R, bool WALL>
+__device__ __forceinline__ void adj_step_cell(const CoupledAdjointArgs &a, const Nbr &nb)
+{
+    R au3[3], aphi3;
+    adj_thermal_cell<QF, P, S, R, WALL>(a, opaque(nb), au3, aphi3);
+    __builtin_amdgcn_sched_barrier(0);
+    R sp[5];
+    adj_hydro_cell<S, R, WALL>(a, opaque(nb), au3, sp);
+    __builtin_amdgcn_sched_barrier(0);
+    adj_pf_cell<QH, P, S, R, WALL>(a, opaque(nb), aphi3, sp);
+}
+
+template <int QH, int QF, typename P, typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_adj_step(const CoupledAdjointArgs a, const Tiling t)
 {
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
     const Nbr nb(a.geo, x, y, z);
     if (nb.below || nb.above)
-        adj_pf_cell<Q, P, S, R, true>(a, nb);
+        adj_step_cell<QH, QF, P, S, R, true>(a, nb);
     else
-        adj_pf_cell<Q, P, S, R, false>(a, nb);
+        adj_step_cell<QH, QF, P, S, R, false>(a, nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -420,9 +442,7 @@ template <int QH, int QF, typename P, typename S, typename R>
 void launch_coupled_adjoint_step(const CoupledAdjointArgs &a, hipStream_t s)
 {
     const Tiling t = make_tiling(a.geo);
-    hipLaunchKernelGGL((k_adj_thermal<QF, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
-    hipLaunchKernelGGL((k_adj_hydro<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
-    hipLaunchKernelGGL((k_adj_pf<QH, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
 template <typename S>

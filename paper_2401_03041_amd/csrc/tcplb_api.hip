@@ -61,18 +61,20 @@ struct tcp_domain {
     void *adj_rk = nullptr;
 
     // tape of a coupled run for its adjoint (tcp_step_taped / tcp_tape_adjoint):
-    // checkpoints of the state every `seg` steps, a ring of seg + 1 states for
-    // recomputing one segment, the heat sources and wall temperatures in force,
-    // and the reverse sweep's workspace
+    // the states at the start of every segment of `seg` steps and the final
+    // state (nseg + 1 checkpoints), a ring of seg - 1 states for the inner
+    // states of one segment (ring_seg: the segment it holds, -1 none), the
+    // heat sources and wall temperatures in force, and the reverse sweep's
+    // workspace
     struct Tape {
         bool valid = false;
-        int64_t nsteps = 0, seg = 0, nseg = 0;
+        int64_t nsteps = 0, seg = 0, nseg = 0, ring_seg = -1;
         void *mem = nullptr;
         size_t mem_bytes = 0;
         std::vector<StateSlot> ckpt, ring;
         HeatSources src{};
         double *twb = nullptr, *twt = nullptr;
-        void *mu[3][2]{}, *sphi[2]{}, *sT[2]{}, *lu1 = nullptr, *lu3 = nullptr, *lphi3 = nullptr;
+        void *mu[3][2]{}, *sphi[2]{}, *sT[2]{}, *lu1 = nullptr;
         double *grad_q = nullptr, *grad_tw = nullptr, *gsrc = nullptr, *dphi = nullptr;
     } tape;
 
@@ -757,8 +759,8 @@ int copy_slot(tcp_domain *d, StateSlot dst, StateSlot src)
     return TCP_OK;
 }
 
-// One allocation holds nseg checkpoints, seg + 1 ring states, the taped wall
-// temperatures and the reverse sweep's workspace.
+// One allocation holds nseg + 1 checkpoints, seg - 1 ring states, the taped
+// wall temperatures and the reverse sweep's workspace.
 int ensure_tape(tcp_domain *d, int64_t nseg, int64_t seg)
 {
     auto &tp = d->tape;
@@ -772,10 +774,10 @@ int ensure_tape(tcp_domain *d, int64_t nseg, int64_t seg)
     std::vector<size_t> work;
     for (int k = 0; k < 3; ++k) work.insert(work.end(), {qb[k], qb[k]});          // mu[k][0..1]
     work.insert(work.end(), {5 * N * sb, 5 * N * sb, 4 * N * sb, 4 * N * sb}); // sphi, sT
-    work.insert(work.end(), {3 * N * sb, 3 * N * sb, N * sb});                // lu1, lu3, lphi3
+    work.push_back(3 * N * sb);                                               // lu1
     work.insert(work.end(), {N * sizeof(double), 2 * ncol * sizeof(double), 4 * kMaxSources * sizeof(double),
                              N * sizeof(double), ncol * sizeof(double), ncol * sizeof(double)});
-    const size_t nslots = (size_t)(nseg + seg + 1);
+    const size_t nckpt = (size_t)nseg + 1, nring = (size_t)seg - 1, nslots = nckpt + nring;
     size_t total = nslots * slot;
     for (size_t w : work) total += round256(w);
     if (tp.mem && tp.mem_bytes != total) {
@@ -789,19 +791,20 @@ int ensure_tape(tcp_domain *d, int64_t nseg, int64_t seg)
         tp.mem_bytes = total;
     }
     char *p = static_cast<char *>(tp.mem);
-    tp.ckpt.assign((size_t)nseg, StateSlot{});
-    tp.ring.assign((size_t)seg + 1, StateSlot{});
+    tp.ckpt.assign(nckpt, StateSlot{});
+    tp.ring.assign(nring, StateSlot{});
+    tp.ring_seg = -1;
     for (size_t j = 0; j < nslots; ++j) {
-        StateSlot &s = j < (size_t)nseg ? tp.ckpt[j] : tp.ring[j - (size_t)nseg];
+        StateSlot &st = j < nckpt ? tp.ckpt[j] : tp.ring[j - nckpt];
         for (int k = 0; k < kSlotPieces; ++k) {
-            slot_piece(s, k) = p;
+            slot_piece(st, k) = p;
             p += round256(sz[k]);
         }
     }
     void **dst[] = {&tp.mu[0][0], &tp.mu[0][1], &tp.mu[1][0], &tp.mu[1][1], &tp.mu[2][0], &tp.mu[2][1],
-                    &tp.sphi[0], &tp.sphi[1], &tp.sT[0], &tp.sT[1], &tp.lu1, &tp.lu3, &tp.lphi3};
+                    &tp.sphi[0], &tp.sphi[1], &tp.sT[0], &tp.sT[1], &tp.lu1};
     size_t k = 0;
-    for (; k < 13; ++k) {
+    for (; k < 11; ++k) {
         *dst[k] = p;
         p += round256(work[k]);
     }
@@ -878,8 +881,6 @@ void reverse_step(tcp_domain *d, const StateSlot &s0, const StateSlot &s1, int b
     a.sT_src = tp.sT[b];
     a.sT_dst = tp.sT[1 - b];
     a.lu1 = tp.lu1;
-    a.lu3 = tp.lu3;
-    a.lphi3 = tp.lphi3;
     a.twb = tp.twb;
     a.twt = tp.twt;
     a.wet[0] = wetting(P.contact_angle_bot, P.xi);
@@ -897,30 +898,60 @@ void reverse_step(tcp_domain *d, const StateSlot &s0, const StateSlot &s1, int b
     else reverse_step_q<27, S, Pdf>(d, a);
 }
 
-// Reverse sweep over the taped steps, last segment first: restore the
-// segment's checkpoint into ring state 0, recompute the segment's states,
-// then undo its steps last to first.  The loss enters through the final phase
-// field (seeded before the first reverse step).
+// State s (0 .. k_j) of segment j: its first and last are checkpoints, the
+// inner ones live in the ring.
+const StateSlot &seg_state(const tcp_domain *d, int64_t j, int64_t s, int64_t kj)
+{
+    const auto &tp = d->tape;
+    if (s == 0) return tp.ckpt[(size_t)j];
+    if (s == kj) return tp.ckpt[(size_t)j + 1];
+    return tp.ring[(size_t)s - 1];
+}
+
+// the steps of segment j from its checkpoint: the inner states into the ring,
+// the last into the next checkpoint (if `last`)
+template <typename S, typename Pdf>
+void run_segment(tcp_domain *d, int64_t j, int64_t kj, bool last)
+{
+    for (int64_t s = 0; s < (last ? kj : kj - 1); ++s) slot_step<S, Pdf>(d, seg_state(d, j, s, kj), seg_state(d, j, s + 1, kj));
+    d->tape.ring_seg = j;
+}
+
+// The taped run: the domain's state becomes checkpoint 0, every segment runs
+// from its checkpoint into the ring and the next checkpoint, and the final
+// checkpoint is copied back into the domain.
+template <typename S, typename Pdf>
+int run_taped(tcp_domain *d)
+{
+    auto &tp = d->tape;
+    int rc = copy_slot(d, tp.ckpt[0], domain_slot(d));
+    if (rc != TCP_OK) return rc;
+    for (int64_t j = 0; j < tp.nseg; ++j) run_segment<S, Pdf>(d, j, std::min(tp.seg, tp.nsteps - j * tp.seg), true);
+    rc = copy_slot(d, domain_slot(d), tp.ckpt[(size_t)tp.nseg]);
+    if (rc != TCP_OK) return rc;
+    return check_launch(d);
+}
+
+// Reverse sweep over the taped steps, last segment first: recompute the inner
+// states of a segment from its checkpoint (unless the ring holds them
+// already), then undo its steps last to first.  The loss enters through the
+// final phase field (seeded before the first reverse step).
 template <typename S, typename Pdf>
 int run_tape_adjoint(tcp_domain *d, const double gc[3], const double *dphi)
 {
     auto &tp = d->tape;
     const size_t ncol = (size_t)d->P.nx * d->P.nz;
+    launch_reduce<S>(d->geo, tp.ckpt[(size_t)tp.nseg].phi, d->partial, d->out4, d->stream);
+    launch_coupled_adjoint_seed<S>(d->geo, d->out4, gc, dphi, tp.sphi[0], d->stream);
     int b = 0;
     for (int64_t j = tp.nseg - 1; j >= 0; --j) {
         const int64_t kj = std::min(tp.seg, tp.nsteps - j * tp.seg);
-        int rc = copy_slot(d, tp.ring[0], tp.ckpt[(size_t)j]);
-        if (rc != TCP_OK) return rc;
-        for (int64_t s = 0; s < kj; ++s) slot_step<S, Pdf>(d, tp.ring[(size_t)s], tp.ring[(size_t)s + 1]);
-        if (j == tp.nseg - 1) {
-            launch_reduce<S>(d->geo, tp.ring[(size_t)kj].phi, d->partial, d->out4, d->stream);
-            launch_coupled_adjoint_seed<S>(d->geo, d->out4, gc, dphi, tp.sphi[0], d->stream);
-        }
+        if (tp.ring_seg != j) run_segment<S, Pdf>(d, j, kj, false);
         for (int64_t s = kj - 1; s >= 0; --s) {
-            reverse_step<S, Pdf>(d, tp.ring[(size_t)s], tp.ring[(size_t)s + 1], b);
+            reverse_step<S, Pdf>(d, seg_state(d, j, s, kj), seg_state(d, j, s + 1, kj), b);
             b = 1 - b;
         }
-        rc = check_launch(d);
+        const int rc = check_launch(d);
         if (rc != TCP_OK) return rc;
     }
     launch_coupled_adjoint_tw<S>(d->geo, tp.sT[b], tp.grad_tw, tp.grad_tw + ncol, d->stream);
@@ -1201,16 +1232,17 @@ int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment)
         const size_t ncol = (size_t)d->P.nx * d->P.nz;
         TCP_HIP(d, hipMemcpyAsync(tp.twb, d->twb, ncol * sizeof(double), hipMemcpyDeviceToDevice, d->stream));
         TCP_HIP(d, hipMemcpyAsync(tp.twt, d->twt, ncol * sizeof(double), hipMemcpyDeviceToDevice, d->stream));
-        for (int64_t j = 0; j < nseg; ++j) {
-            rc = copy_slot(d, tp.ckpt[(size_t)j], domain_slot(d));
-            if (rc == TCP_OK) rc = advance(d, std::min(seg, nsteps - j * seg));
-            if (rc != TCP_OK) return rc;
-        }
         tp.nsteps = nsteps;
         tp.seg = seg;
         tp.nseg = nseg;
+        switch (d->P.precision) {
+        case TCP_FP64: rc = run_taped<double, double>(d); break;
+        case TCP_FP32: rc = run_taped<float, float>(d); break;
+        default: rc = run_taped<float, _Float16>(d); break;
+        }
+        if (rc != TCP_OK) return rc;
         tp.valid = true;
-        return check_launch(d);
+        return TCP_OK;
     });
 }
 
@@ -1598,19 +1630,14 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     // and writes acc and the stage field; the FP64 source adjoint is read and
     // written.
     b[TCP_K_ADJOINT] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * sb + 4.0 * sb + 16.0 : 20.0 * sb + 16.0;
-    // reverse step of the coupled adjoint (link and field adjoints in the
-    // arithmetic type, sb bytes), per kernel: thermal reads the f link
-    // adjoints, sT, the PDFs f (and T^n with deviation storage), u^{n+1},
-    // phi^{n+1}, and writes the link adjoints, lu3, lphi3, plus the FP64
-    // source adjoint read and written; hydrodynamic reads the g link
-    // adjoints, lu1, lu3, the PDFs g, phi^n, T^n and writes the link
-    // adjoints, sphi, sT; phase field reads the h link adjoints, sphi,
-    // lphi3, the PDFs h, phi^n, u^n, the gradient part of the new sphi, and
-    // writes the link adjoints, that part of sphi and lu1
+    // reverse step of the coupled adjoint (one kernel; link and field adjoints
+    // in the arithmetic type, sb bytes): reads the link adjoints of h, g, f,
+    // sphi, sT and lu1, the PDFs h, g, f of step n, phi^n, T^n, u^n, and
+    // phi^{n+1}, u^{n+1}; writes the link adjoints, sphi, sT and lu1; the FP64
+    // source adjoint is read and written
     if (d->P.thermal == TCP_THERMAL_LB) {
-        const double qf = d->P.q_thermal, qh = d->P.q_pf;
-        b[TCP_K_COUPLED_ADJOINT] = (2.0 * qf * sb + qf * pb + (12.0 + (d->pb <= 4 ? 1.0 : 0.0)) * sb + 16.0) +
-                                   98.0 * sb + (2.0 * qh * sb + qh * pb + 19.0 * sb);
+        const double q = d->P.q_thermal + d->P.q_pf;
+        b[TCP_K_COUPLED_ADJOINT] = (2.0 * q + 2.0 * 39.0 + 27.0 + 9.0) * sb + q * pb + 16.0;
     } else {
         b[TCP_K_COUPLED_ADJOINT] = 0.0;
     }
