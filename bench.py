@@ -396,7 +396,8 @@ def main() -> int:
     fp16 = run_gpu(cfg, fp16_steps, max(2, args.warmup // 4), "fp16") if fp16_steps > 0 else None
     adjoint = None
     if not args.no_adjoint:
-        adjoint = {"coupled": coupled_adjoint_cost("fp32"), "coupled_fp64": coupled_adjoint_cost("fp64")}
+        adjoint = {"coupled": coupled_adjoint_cost("fp32"), "coupled_fp64": coupled_adjoint_cost("fp64"),
+                   "coupled_every_state": coupled_adjoint_cost("fp32", segment=1)}
         thermal = adjoint_cost(cfg, 20, "fp32")
         thermal["adjoint_update_over_coupled_step"] = round(thermal["adjoint_ms_per_update"] / fp32["ms_per_step"],
                                                             3)
