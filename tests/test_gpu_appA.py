@@ -1,23 +1,87 @@
-"""The paper's own verification case at its full size (Sec. 3.1, App. A): the 2D
-planar heated channel, 512 x 256 cells, thermal LB (D3Q7), k* = 1, 4e5 steps in
-FP64, against the closed form.  The paper prints l2 errors of 1.1164e-3
-(temperature) and 9.2165e-2 (velocity) for this case."""
+"""The paper's own verification case at its full size (Sec. 3.1, App. A): the
+planar heated two-layer channel, 512 x 256 cells, 4e5 steps in FP64, against
+the closed form, for every row of the paper's two tables:
+
+* Tab. planarflowDP2D: the thermal LB (D3Q7), RK2 and RK4 at conductivity
+  ratios k* = 1 and 1/5;
+* Tab. planarflowDP3D: the pseudo-3D channel with the thermal LB on D3Q15,
+  D3Q19 and D3Q27 at k* = 1 and 1/5 (its D3Q7 rows are the 2D LB rows: the
+  closed form does not depend on z and the channel is periodic in z, so its
+  extent in z does not change the solution; test_pseudo3d_thickness checks
+  that one, two and ten cells give the same fields, and the rows run one cell
+  thick).
+
+The rows of a test run side by side, each on a HIP stream of its own.  Each
+row is gated at its own error as measured on an MI355X plus 20 % (the printed
+numbers are the paper's, beside them in the output).  The temperature errors
+are below the paper's in every row; the velocity errors are 1.2 - 1.4 times
+the paper's and fall as the interface widens (the width is not stated in the
+section; xi = 4 here): test_velocity_error_against_interface_width.
+"""
 from __future__ import annotations
 
 import os
 
+import numpy as np
 import pytest
 
-from tests.appA_channel import load_table, run
+from tests.appA_channel import load_table, run, run_many
 
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "appA_planar_channel.txt")
 
+# (table, case, k*) -> (l2 temperature, l2 velocity) measured on an MI355X (FP64)
+MEASURED = {
+    ("2D", "LB", 1.0): (1.53e-4, 0.129), ("2D", "RK2", 1.0): (1.52e-4, 0.129),
+    ("2D", "RK4", 1.0): (1.52e-4, 0.129), ("2D", "LB", 0.2): (2.07e-3, 0.173),
+    ("2D", "RK2", 0.2): (3.16e-3, 0.169), ("2D", "RK4", 0.2): (3.16e-3, 0.169),
+    ("3D", "Q7", 1.0): (1.531e-4, 0.1294), ("3D", "Q15", 1.0): (1.530e-4, 0.1294),
+    ("3D", "Q19", 1.0): (1.530e-4, 0.1294), ("3D", "Q27", 1.0): (1.530e-4, 0.1294),
+    ("3D", "Q7", 0.2): (2.072e-3, 0.1731), ("3D", "Q15", 0.2): (2.072e-3, 0.1731),
+    ("3D", "Q19", 0.2): (2.072e-3, 0.1731), ("3D", "Q27", 0.2): (2.072e-3, 0.1731),
+}
 
-def test_planar_heated_channel_full_size_lb():
-    paper_T, paper_u = load_table(GOLDEN)[("2D", "LB", 1.0)]
-    eT, eu = run(thermal="lb", q_thermal=7, k_star=1.0, nz=1, precision="fp64")
-    print(f"l2 temperature {eT:.4e} (paper {paper_T:.4e}), l2 velocity {eu:.4e} (paper {paper_u:.4e})")
-    assert eT < 2.0 * paper_T
-    assert eu < 2.0 * paper_u
+
+def _check(key, eT, eu):
+    paper_T, paper_u = load_table(GOLDEN)[key]
+    mT, mu = MEASURED[key]
+    print(f"{key}: l2 T {eT:.4e} (paper {paper_T:.4e}), l2 |u| {eu:.4e} (paper {paper_u:.4e})", flush=True)
+    assert eT < 1.2 * mT, key
+    assert eu < 1.2 * mu, key
+
+
+@pytest.mark.parametrize("k_star", [1.0, 0.2])
+def test_planar_heated_channel_2d(k_star):
+    schemes = ("LB", "RK2", "RK4")
+    res = run_many([dict(thermal=sch.lower(), q_thermal=7, k_star=k_star, nz=1) for sch in schemes])
+    for sch, (eT, eu) in zip(schemes, res):
+        _check(("2D", sch, k_star), eT, eu)
+
+
+@pytest.mark.parametrize("k_star", [1.0, 0.2])
+def test_planar_heated_channel_pseudo3d(k_star):
+    stencils = (15, 19, 27)
+    res = run_many([dict(thermal="lb", q_thermal=q, k_star=k_star, nz=1) for q in stencils])
+    for q, (eT, eu) in zip(stencils, res):
+        _check(("3D", f"Q{q}", k_star), eT, eu)
+
+
+def test_pseudo3d_thickness():
+    """The z-independent channel gives the same fields one, two and ten cells
+    thick (D3Q27 thermal LB, whose links reach every z neighbour)."""
+    b = run(thermal="lb", q_thermal=27, k_star=0.2, nz=10, steps=2000, fields=True)
+    for nz in (1, 2):
+        a = run(thermal="lb", q_thermal=27, k_star=0.2, nz=nz, steps=2000, fields=True)
+        for name in a:
+            assert np.max(np.abs(a[name] - b[name])) <= 1e-12 * max(np.max(np.abs(b[name])), 1e-300), (nz, name)
+
+
+def test_velocity_error_against_interface_width():
+    """The velocity error against the sharp-interface closed form falls as the
+    diffuse interface widens from xi = 3 to 6 (thermal LB, k* = 1, 4e5 steps)."""
+    widths = (3.0, 4.0, 6.0)
+    res = run_many([dict(thermal="lb", q_thermal=7, k_star=1.0, nz=1, xi=xi) for xi in widths])
+    errs = {xi: r[1] for xi, r in zip(widths, res)}
+    print("l2 T, l2 |u| against xi:", {xi: (f"{r[0]:.3e}", f"{r[1]:.4f}") for xi, r in zip(widths, res)}, flush=True)
+    assert errs[3.0] > errs[4.0] > errs[6.0]
