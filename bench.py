@@ -352,11 +352,17 @@ def paper_block(steps: int, warmup: int) -> dict:
 
 def copy_calibration(gib: float = 4.0, reps: int = 3) -> None:
     """The library's streaming copy kernel on a buffer of known size, for
-    scaling the HBM byte counters: every dispatch reads and writes `gib` GiB."""
+    scaling the HBM byte counters: every dispatch reads and writes `gib` GiB;
+    then the 27-component blocked copy (the step kernel's access pattern) on
+    512^3 cells, every dispatch reading and writing 14.5 GB."""
     from paper_2401_03041_amd import tcplb
     nbytes = int(gib * (1 << 30))
     gbs = tcplb.bandwidth_probe(nbytes, reps)
     _log(f"copy calibration: {reps + 1} dispatches, each reading and writing {nbytes} bytes; best {gbs:.0f} GB/s")
+    cells = 1 << 27
+    gbs = tcplb.pdf_copy_probe(cells, reps)
+    _log(f"blocked 27-component copy: {reps + 1} dispatches, each reading and writing {cells * 27 * 4} bytes; "
+         f"best {gbs:.0f} GB/s")
 
 
 def main() -> int:
@@ -388,6 +394,8 @@ def main() -> int:
     from paper_2401_03041_amd import workloads as W
     copy_gbs = tcplb.bandwidth_probe()
     _log(f"streaming copy probe: {copy_gbs:.0f} GB/s")
+    pdf_copy_gbs = tcplb.pdf_copy_probe(args.n ** 3 if args.n % 4 == 0 else 1 << 27)
+    _log(f"blocked 27-component copy probe: {pdf_copy_gbs:.0f} GB/s")
     cfg = W.droplet_block(n=args.n, precision="fp32")
     fp32 = run_gpu(cfg, args.steps, args.warmup, "fp32")
     fp64_steps = args.steps // 2 if args.fp64_steps is None else args.fp64_steps
@@ -425,6 +433,8 @@ def main() -> int:
         "roofline": roofline(fp32, "fp32"),
         "copy_probe_GBs": round(copy_gbs, 1),
         "step_kernel_frac_of_copy": round(fp32["kernels"]["step"]["achieved_GBs"] / copy_gbs, 4),
+        "pdf_copy_probe_GBs": round(pdf_copy_gbs, 1),
+        "step_kernel_frac_of_pdf_copy": round(fp32["kernels"]["step"]["achieved_GBs"] / pdf_copy_gbs, 4),
         "cpu_baseline": base,
         "step_bytes_per_cell": fp32["step_bytes_per_cell"],
         "effective_GBs": round(fp32["effective_GBs"], 1),

@@ -356,6 +356,15 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *bytes_per_cell);
  * second, in GB/s).  Synchronises; frees its buffers before returning. */
 int tcp_bandwidth_probe(size_t bytes, int reps, double *gbs);
 
+/* Passage: Sec. 4.2 (memory bandwidth as the bound of the LB updates).
+ * Ceiling of the step kernel's own access pattern: copy a 27-component FP32
+ * field of ncells cells (a multiple of 64) in the blocked PDF layout (runs of
+ * 64 cells per component, one thread per cell, 4 bytes per lane,
+ * non-temporal stores) between two device buffers, `reps` times on the
+ * default stream, and return the best rate (read + write, GB/s).
+ * Synchronises; frees its buffers before returning. */
+int tcp_pdf_copy_probe(int64_t ncells, int reps, double *gbs);
+
 /* Passage: none (error reporting).  Text of a TCP_* code. */
 const char *tcp_error_string(int code);
 /* Passage: none (error reporting).  Message of the last failed call on d, or

@@ -22,9 +22,12 @@
 
 namespace tcp {
 
-// Update of one cell.  Writes g* and u^{n+1}, and returns u^{n+1}.
-template <typename S, typename R, bool WALL>
-__device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R (&u)[3])
+// Update of one cell.  Writes g* and u^{n+1}, and returns u^{n+1}.  With
+// GIVEN the phi^n stencil quantities come from the phase-field update of the
+// same cell (fused step) instead of being loaded.
+template <typename S, typename R, bool WALL, bool GIVEN = false>
+__device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R (&u)[3],
+                                           const PhiStencil<R> &given = PhiStencil<R>{})
 {
     const S *gs = static_cast<const S *>(a.g_src);
     const PdfLanes<27> pl(nb);
@@ -69,37 +72,40 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
     // phi^n: value, gradient, Laplacian; T^n: value, gradient
     const S *pp = static_cast<const S *>(a.phi);
     const S *tp = static_cast<const S *>(a.T);
-    const R phi = ld<R>(elem(pp, nb.c));
     const R T = ld<R>(elem(tp, nb.c));
-    R gp[3] = {R(0), R(0), R(0)}, gT[3] = {R(0), R(0), R(0)}, lap = R(0);
+    PhiStencil<R> sten;
+    R gT[3] = {R(0), R(0), R(0)};
     __builtin_amdgcn_s_setprio(kPullPriority);
+    if constexpr (GIVEN) {
+        sten = given;
+    } else {
+        R pn[27];
+#pragma unroll
+        for (int i = 0; i < 27; ++i) {
+            pn[i] = ld<R>(nb.ptr(pp, vel27(i, 0), vel27(i, 1), vel27(i, 2)));
+            if (WALL && nb.ghost(vel27(i, 1))) pn[i] = nb.phi_ghost(pn[i], vel27(i, 1), a.wet);
+        }
+        phi_stencil(pn, sten);
+    }
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
         const R w = R(weight<27>(i));
-        R pv = ld<R>(nb.ptr(pp, ex, ey, ez));
-        if (WALL && nb.ghost(ey)) pv = nb.phi_ghost(pv, ey, a.wet);
         R tv = ld<R>(nb.ptr(tp, ex, ey, ez));
         if (WALL && nb.ghost(ey)) {
             const double *tw = ey < 0 ? a.twb : a.twt;
             tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;
         }
-        if (ex) gp[0] += R(ex) * w * pv;
-        if (ey) gp[1] += R(ey) * w * pv;
-        if (ez) gp[2] += R(ez) * w * pv;
-        lap += w * pv;
         if (ex) gT[0] += R(ex) * w * tv;
         if (ey) gT[1] += R(ey) * w * tv;
         if (ez) gT[2] += R(ez) * w * tv;
     }
     __builtin_amdgcn_s_setprio(0);
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        gp[k] *= R(3);
-        gT[k] *= R(3);
-    }
-    // sum over the 26 neighbours of w (psi_nb - psi) = sum w psi_nb - (1 - w_0) psi
-    lap = R(6) * (lap - R(1.0 - weight<27>(0)) * phi);
+    for (int k = 0; k < 3; ++k) gT[k] *= R(3);
+    const R phi = sten.phi;
+    const R(&gp)[3] = sten.gp;
+    const R lap = sten.lap;
 
     // material laws
     const R phic = fmin(fmax(phi, R(0)), R(1));

@@ -20,9 +20,10 @@
 
 namespace tcp {
 
-// Update of one cell; returns phi^{n+1}.
+// Update of one cell; returns phi^{n+1} and, in sten, phi^n at the cell with
+// its isotropic gradient and Laplacian.
 template <int Q, typename P, typename S, typename R, bool WALL>
-__device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
+__device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb, PhiStencil<R> &sten)
 {
     constexpr bool dev = deviation_storage<P>();
     const P *hs = static_cast<const P *>(a.h_src);
@@ -35,7 +36,7 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
     __builtin_amdgcn_s_setprio(kPullPriority);
     R pn[27];
 #pragma unroll
-    for (int k = dev ? 0 : 1; k < 27; ++k) {
+    for (int k = 0; k < 27; ++k) {
         pn[k] = ld<R>(nb.ptr(po, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
         if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);
     }
@@ -72,17 +73,8 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb)
     if constexpr (dev) phi += pn[0];
 
     // interface normal from the isotropic gradient of phi^n
-    R gr[3] = {R(0), R(0), R(0)};
-#pragma unroll
-    for (int k = 1; k < 27; ++k) {
-        const R v = R(weight<27>(k)) * pn[k];
-        gr[0] += R(vel27(k, 0)) * v;
-        gr[1] += R(vel27(k, 1)) * v;
-        gr[2] += R(vel27(k, 2)) * v;
-    }
-    gr[0] *= R(3);
-    gr[1] *= R(3);
-    gr[2] *= R(3);
+    phi_stencil(pn, sten);
+    const R(&gr)[3] = sten.gp;
     const R inv = R(1) / sqrt(gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2] + R(a.eps2));
     const R lam = R(4) * phi * (R(1) - phi) * R(a.inv_xi);
     const R F[3] = {lam * gr[0] * inv, lam * gr[1] * inv, lam * gr[2] * inv};

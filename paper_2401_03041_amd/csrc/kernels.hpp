@@ -81,6 +81,35 @@ struct RkArgs {
     int hq;               // heat sources present: q comes from coef
 };
 
+// phi^n at a cell, its isotropic gradient and Laplacian (the D3Q27 stencils
+// of the updates, contact-angle ghosts applied): the phase-field update
+// computes them for its interface normal and hands them to the hydrodynamic
+// update of the same cell in the fused step, which then loads no phi stencil
+template <typename R>
+struct PhiStencil {
+    R phi, gp[3], lap;
+};
+
+// pn: phi^n on the 27-point neighbourhood in D3Q27 order (ghosts applied)
+template <typename R>
+__device__ __forceinline__ void phi_stencil(const R (&pn)[27], PhiStencil<R> &s)
+{
+    R gp[3] = {R(0), R(0), R(0)}, lap = R(0);
+#pragma unroll
+    for (int k = 1; k < 27; ++k) {
+        const int ex = vel27(k, 0), ey = vel27(k, 1), ez = vel27(k, 2);
+        const R w = R(weight<27>(k));
+        if (ex) gp[0] += R(ex) * w * pn[k];
+        if (ey) gp[1] += R(ey) * w * pn[k];
+        if (ez) gp[2] += R(ez) * w * pn[k];
+        lap += w * pn[k];
+    }
+    for (int a = 0; a < 3; ++a) s.gp[a] = R(3) * gp[a];
+    s.phi = pn[0];
+    // sum over the 26 neighbours of w (psi_nb - psi) = sum w psi_nb - (1 - w_0) psi
+    s.lap = R(6) * (lap - R(1.0 - weight<27>(0)) * pn[0]);
+}
+
 // Wave priority (s_setprio) while a cell update issues its PDF pull and its
 // stencil loads of phi and T: a wave that is loading goes ahead of waves that
 // are computing, which keeps more loads in flight (measured +2 to +2.5 % on
@@ -281,5 +310,8 @@ void launch_coupled_adjoint_tw(const Geometry &g, const void *sT, double *grad_t
 
 // streaming copy of n16 16-byte words (bandwidth probe)
 void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);
+// copy of a 27-component FP32 field in the blocked PDF layout, ncells a
+// multiple of 64 (bandwidth probe of the step kernel's access pattern)
+void launch_copy_blocked27(const void *src, void *dst, int64_t ncells, hipStream_t s);
 
 } // namespace tcp

@@ -279,6 +279,31 @@ void launch_maxdiff(int64_t n, const void *a, const void *b, double *partial, do
     hipLaunchKernelGGL(k_max_final, dim3(1), dim3(kThreads), 0, s, partial, kReduceBlocks, out);
 }
 
+// Copy of a Q-component FP32 field in the blocked PDF layout (runs of 64 cells
+// per component): one thread per cell loads its Q values, 4 bytes per lane
+// from Q runs of one block, then stores them with the non-temporal hint, the
+// access pattern of the step kernel's PDF pull and store without the
+// neighbour offsets.
+template <int Q>
+__global__ void __launch_bounds__(kThreads) k_copy_blocked(const float *__restrict__ src, float *__restrict__ dst,
+                                                            int64_t ncells)
+{
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (c >= ncells) return;
+    const int64_t base = (c >> 6) * (64 * Q) + (c & 63);
+    float v[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) v[i] = src[base + 64 * i];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) __builtin_nontemporal_store(v[i], dst + base + 64 * i);
+}
+
+void launch_copy_blocked27(const void *src, void *dst, int64_t ncells, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_copy_blocked<27>), dim3(blocks_for(ncells)), dim3(kThreads), 0, s,
+                       static_cast<const float *>(src), static_cast<float *>(dst), ncells);
+}
+
 void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
 {
     hipLaunchKernelGGL(k_copy16, dim3(blocks_for(n16)), dim3(kThreads), 0, s, static_cast<const f32x4 *>(src),

@@ -12,10 +12,11 @@ __global__ void __launch_bounds__(kTX *kTY) k_phase_field(const PfArgs a, const 
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
     const Nbr nb(a.geo, x, y, z);
+    PhiStencil<R> ps;
     if (nb.below || nb.above)
-        phase_field_cell<Q, P, S, R, true>(a, nb);
+        phase_field_cell<Q, P, S, R, true>(a, nb, ps);
     else
-        phase_field_cell<Q, P, S, R, false>(a, nb);
+        phase_field_cell<Q, P, S, R, false>(a, nb, ps);
 }
 
 template <int Q, typename P, typename S, typename R>

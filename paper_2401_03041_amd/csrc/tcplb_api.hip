@@ -958,6 +958,41 @@ int run_tape_adjoint(tcp_domain *d, const double gc[3], const double *dphi)
     return check_launch(d);
 }
 
+// best rate (read + write bytes per second, GB/s) of reps launches of a copy
+// between two fresh device buffers of `bytes` each (one untimed warm-up)
+template <typename Launch>
+int copy_probe(size_t bytes, int reps, double *gbs, Launch launch)
+{
+    void *a = nullptr, *b = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = TCP_OK;
+    if (hipMalloc(&a, bytes) != hipSuccess || hipMalloc(&b, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        rc = fail(nullptr, TCP_ERR_OOM, "probe allocation failed");
+    } else if (hipMemset(a, 0, bytes) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+               hipEventCreate(&e1) != hipSuccess) {
+        rc = fail(nullptr, TCP_ERR_HIP, "probe set-up failed");
+    } else {
+        double best = 0.0;
+        launch(a, b); // warm-up
+        for (int r = 0; r < reps && rc == TCP_OK; ++r) {
+            float ms = 0.0f;
+            if (hipEventRecord(e0, nullptr) != hipSuccess) rc = TCP_ERR_HIP;
+            launch(a, b);
+            if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = TCP_ERR_HIP;
+            if (rc == TCP_OK && ms > 0.0f) best = std::max(best, 2.0 * (double)bytes / (ms * 1e-3) / 1e9);
+        }
+        if (rc != TCP_OK) fail(nullptr, rc, "probe timing failed");
+        *gbs = best;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    return rc;
+}
 } // namespace
 
 extern "C" {
@@ -1647,35 +1682,17 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
 int tcp_bandwidth_probe(size_t bytes, int reps, double *gbs)
 {
     if (!gbs || bytes < 16 || reps < 1) return fail(nullptr, TCP_ERR_ARG, "bandwidth probe needs bytes >= 16, reps >= 1");
-    void *a = nullptr, *b = nullptr;
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    int rc = TCP_OK;
     const int64_t n16 = (int64_t)(bytes / 16);
-    if (hipMalloc(&a, n16 * 16) != hipSuccess || hipMalloc(&b, n16 * 16) != hipSuccess) {
-        rc = fail(nullptr, TCP_ERR_OOM, "probe allocation failed");
-    } else if (hipMemset(a, 0, n16 * 16) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
-               hipEventCreate(&e1) != hipSuccess) {
-        rc = fail(nullptr, TCP_ERR_HIP, "probe set-up failed");
-    } else {
-        double best = 0.0;
-        launch_copy16(a, b, n16, nullptr); // warm-up
-        for (int r = 0; r < reps && rc == TCP_OK; ++r) {
-            float ms = 0.0f;
-            if (hipEventRecord(e0, nullptr) != hipSuccess) rc = TCP_ERR_HIP;
-            launch_copy16(a, b, n16, nullptr);
-            if (hipEventRecord(e1, nullptr) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-                rc = TCP_ERR_HIP;
-            if (rc == TCP_OK && ms > 0.0f) best = std::max(best, 2.0 * n16 * 16 / (ms * 1e-3) / 1e9);
-        }
-        if (rc != TCP_OK) fail(nullptr, rc, "probe timing failed");
-        *gbs = best;
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    if (a) (void)hipFree(a);
-    if (b) (void)hipFree(b);
-    return rc;
+    return copy_probe((size_t)n16 * 16, reps, gbs,
+                      [n16](void *a, void *b) { launch_copy16(a, b, n16, nullptr); });
+}
+
+int tcp_pdf_copy_probe(int64_t ncells, int reps, double *gbs)
+{
+    if (!gbs || ncells < 64 || ncells % 64 != 0 || reps < 1)
+        return fail(nullptr, TCP_ERR_ARG, "PDF copy probe needs ncells a positive multiple of 64, reps >= 1");
+    return copy_probe((size_t)ncells * 27 * sizeof(float), reps, gbs,
+                      [ncells](void *a, void *b) { launch_copy_blocked27(a, b, ncells, nullptr); });
 }
 
 const char *tcp_error_string(int code)

@@ -28,7 +28,8 @@ EXPORTS = (
     "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_step_taped", "tcp_tape_adjoint",
     "tcp_warm_temperature", "tcp_thermal_adjoint", "tcp_get_field", "tcp_get_field_noalloc",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
-    "tcp_set_profiling", "tcp_set_fusion", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_error_string",
+    "tcp_set_profiling", "tcp_set_fusion", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_pdf_copy_probe",
+    "tcp_error_string",
     "tcp_last_error",
 )
 
@@ -113,6 +114,7 @@ def load() -> C.CDLL:
         "tcp_kernel_times": [vp, dp, C.POINTER(i64)],
         "tcp_algorithmic_bytes": [vp, dp],
         "tcp_bandwidth_probe": [C.c_size_t, C.c_int, dp],
+        "tcp_pdf_copy_probe": [C.c_int64, C.c_int, dp],
         "tcp_error_string": [C.c_int],
         "tcp_last_error": [vp],
     }
@@ -389,6 +391,17 @@ def bandwidth_probe(nbytes: int = 1 << 32, reps: int = 10) -> float:
     rc = lib.tcp_bandwidth_probe(int(nbytes), int(reps), _dptr(out))
     if rc != 0:
         raise TcpError(f"bandwidth probe: {lib.tcp_last_error(None).decode()}")
+    return float(out[0])
+
+
+def pdf_copy_probe(ncells: int = 1 << 27, reps: int = 5) -> float:
+    """Best rate (GB/s, read + write) of copying a 27-component FP32 field of
+    ncells cells in the blocked PDF layout: the step kernel's access pattern."""
+    lib = load()
+    out = np.zeros(1)
+    rc = lib.tcp_pdf_copy_probe(int(ncells), int(reps), _dptr(out))
+    if rc != 0:
+        raise TcpError(f"PDF copy probe: {lib.tcp_last_error(None).decode()}")
     return float(out[0])
 
 

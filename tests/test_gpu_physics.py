@@ -43,7 +43,7 @@ def test_laplace_pressure_jump_3d(radius):
     d.close()
 
 
-@pytest.mark.parametrize("thermal,q", [("lb", 7), ("lb", 19), ("rk2", 7), ("rk4", 7)])
+@pytest.mark.parametrize("thermal,q", [("lb", 7), ("lb", 15), ("lb", 19), ("lb", 27), ("rk2", 7), ("rk4", 7)])
 def test_ygb_migration_velocity(thermal, q):
     """Droplet R = 16 in a channel 128 x 256 x 128 between walls at T = 0 and 1
     (G = 1/256), sigma_T = -1.6e-3, unit ratios, Ma = 1, each thermal scheme.  It
