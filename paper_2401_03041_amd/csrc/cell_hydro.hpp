@@ -24,10 +24,12 @@ namespace tcp {
 
 // Update of one cell.  Writes g* and u^{n+1}, and returns u^{n+1}.  With
 // GIVEN the phi^n stencil quantities come from the phase-field update of the
-// same cell (fused step) instead of being loaded.
-template <typename S, typename R, bool WALL, bool GIVEN = false>
+// same cell (fused step) instead of being loaded.  With QT > 0, tsrc[i]
+// returns T^n at x - e_i for the QT directions of the thermal stencil (the
+// values the thermal pull needs with deviation storage).
+template <typename S, typename R, bool WALL, bool GIVEN = false, int QT = 0>
 __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R (&u)[3],
-                                           const PhiStencil<R> &given = PhiStencil<R>{})
+                                           const PhiStencil<R> &given = PhiStencil<R>{}, R *tsrc = nullptr)
 {
     const S *gs = static_cast<const S *>(a.g_src);
     const PdfLanes<27> pl(nb);
@@ -72,7 +74,6 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
     // phi^n: value, gradient, Laplacian; T^n: value, gradient
     const S *pp = static_cast<const S *>(a.phi);
     const S *tp = static_cast<const S *>(a.T);
-    const R T = ld<R>(elem(tp, nb.c));
     PhiStencil<R> sten;
     R gT[3] = {R(0), R(0), R(0)};
     __builtin_amdgcn_s_setprio(kPullPriority);
@@ -80,18 +81,27 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
         sten = given;
     } else {
         R pn[27];
+        nb.stencil27(pp, pn);
 #pragma unroll
-        for (int i = 0; i < 27; ++i) {
-            pn[i] = ld<R>(nb.ptr(pp, vel27(i, 0), vel27(i, 1), vel27(i, 2)));
+        for (int i = 0; i < 27; ++i)
             if (WALL && nb.ghost(vel27(i, 1))) pn[i] = nb.phi_ghost(pn[i], vel27(i, 1), a.wet);
-        }
         phi_stencil(pn, sten);
+    }
+    R tn[27];
+    nb.stencil27(tp, tn);
+    const R T = tn[0];
+    if constexpr (QT > 0) {
+#pragma unroll
+        for (int i = 0; i < QT; ++i) {
+            const int j = index27<QT>(i);
+            tsrc[i] = tn[index_of(-vel27(j, 0), -vel27(j, 1), -vel27(j, 2))];
+        }
     }
 #pragma unroll
     for (int i = 1; i < 27; ++i) {
         const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
         const R w = R(weight<27>(i));
-        R tv = ld<R>(nb.ptr(tp, ex, ey, ez));
+        R tv = tn[i];
         if (WALL && nb.ghost(ey)) {
             const double *tw = ey < 0 ? a.twb : a.twt;
             tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;

@@ -35,11 +35,10 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb, Ph
     const S *po = static_cast<const S *>(a.phi_old);
     __builtin_amdgcn_s_setprio(kPullPriority);
     R pn[27];
+    nb.stencil27(po, pn);
 #pragma unroll
-    for (int k = 0; k < 27; ++k) {
-        pn[k] = ld<R>(nb.ptr(po, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
+    for (int k = 0; k < 27; ++k)
         if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);
-    }
 
     // pull; a link that crosses a wall returns the cell's own opposite PDF
     R h[Q];

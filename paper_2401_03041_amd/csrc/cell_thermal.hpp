@@ -12,17 +12,20 @@
 
 namespace tcp {
 
-// Update of one cell at (x, y, z) given the cell's phi^{n+1} and u^{n+1}.
-template <int Q, typename P, typename S, typename R, bool WALL>
+// Update of one cell at (x, y, z) given the cell's phi^{n+1} and u^{n+1}.  With
+// GIVEN_T (deviation storage), tsrc[i] holds T^n at x - e_i, handed over by the
+// hydrodynamic update of the same cell, instead of being loaded.
+template <int Q, typename P, typename S, typename R, bool WALL, bool GIVEN_T = false>
 __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb, int x, int y, int z, R phi,
-                                             const R (&u)[3])
+                                             const R (&u)[3], const R *tsrc = nullptr)
 {
     constexpr bool dev = deviation_storage<P>();
     const P *fs = static_cast<const P *>(a.f_src);
     const PdfLanes<Q> pl(nb);
     const S *to = static_cast<const S *>(a.T_old);
     const R ts = dev ? R(0) : R(a.t_shift);
-    const R t_own = dev ? ld<R>(elem(to, nb.c)) : R(0);
+    R t_own = R(0);
+    if constexpr (dev) t_own = GIVEN_T ? tsrc[0] : ld<R>(elem(to, nb.c));
 
     // f[] holds f - w ts (constant shift) or f - w T^n(own) (deviation storage:
     // stored + w (T^n(source) - T^n(own)), exactly zero in a uniform region at rest)
@@ -40,7 +43,7 @@ __device__ __forceinline__ void thermal_cell(const ThermalArgs &a, const Nbr &nb
         } else {
             f[i] = ld<R>(elem(pdf_row<Q>(fs, a.geo, nb.yr[1 - ey], nb.zi[1 - ez], i), pl.xq[1 - ex]));
             if constexpr (dev) {
-                if (i != 0) f[i] += w * (ld<R>(nb.ptr(to, -ex, -ey, -ez)) - t_own);
+                if (i != 0) f[i] += w * ((GIVEN_T ? tsrc[i] : ld<R>(nb.ptr(to, -ex, -ey, -ez))) - t_own);
             }
         }
     }

@@ -10,9 +10,10 @@
 // written (u^{n+1} by K2) only at the thread's own cell; and K3 needs
 // phi^{n+1} and u^{n+1} only at its own cell, where this thread has just
 // computed them.  Fusing saves the second read of the phi^n stencil (K1 hands
-// phi^n at the cell, its gradient and Laplacian to K2, 26 fewer loads per
-// cell), the re-reads of u and phi^{n+1} by K3 (field traffic 10 instead of 15
-// values per cell) and two launches per step.
+// phi^n at the cell, its gradient and Laplacian to K2), the T^n values the
+// thermal pull needs with deviation storage (K2 has them from its stencil),
+// the re-reads of u and phi^{n+1} by K3 (field traffic 10 instead of 15 values
+// per cell) and two launches per step.
 #include "cell_hydro.hpp"
 #include "cell_pf.hpp"
 #include "cell_thermal.hpp"
@@ -39,9 +40,13 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, const Nbr &nb, int 
     // holds both phases' PDFs in registers at once and costs occupancy
     __builtin_amdgcn_sched_barrier(0);
     R u[3];
-    hydro_cell<S, R, WALL, true>(a.hy, opaque(nb), u, ps);
+    // with deviation storage the thermal pull needs T^n at x - e_i: the
+    // hydrodynamic update has it from its T^n stencil
+    constexpr bool dev = deviation_storage<P>();
+    R tsrc[QF];
+    hydro_cell<S, R, WALL, true, dev ? QF : 0>(a.hy, opaque(nb), u, ps, tsrc);
     __builtin_amdgcn_sched_barrier(0);
-    thermal_cell<QF, P, S, R, WALL>(a.th, opaque(nb), x, y, z, phi_new, u);
+    thermal_cell<QF, P, S, R, WALL, dev>(a.th, opaque(nb), x, y, z, phi_new, u, tsrc);
 }
 
 // FP64 needs 174 registers per lane; capping it at 168 lets three wavefronts

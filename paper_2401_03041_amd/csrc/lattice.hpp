@@ -85,6 +85,15 @@ __device__ __forceinline__ void st_pdf(S *p, R v)
 }
 
 // ----------------------------------------------------------------------------
+// D3Q27 index of the offset (dx, dy, dz)
+__host__ __device__ constexpr int index_of(int dx, int dy, int dz)
+{
+    for (int i = 0; i < 27; ++i)
+        if (vel27(i, 0) == dx && vel27(i, 1) == dy && vel27(i, 2) == dz) return i;
+    return -1;
+}
+
+// ----------------------------------------------------------------------------
 // geometry and neighbour addressing
 // ----------------------------------------------------------------------------
 struct Geometry {
@@ -172,6 +181,17 @@ struct Nbr {
     __device__ __forceinline__ uint32_t col(int dx, int dz, const Geometry &g) const
     {
         return xo[dx + 1] + zi[dz + 1] * (uint32_t)g.nx;
+    }
+    // A field on the 3x3x3 neighbourhood of the cell, in D3Q27 order (rows
+    // beyond a wall are the clamped own row, as ptr()).  (Taking the x - 1
+    // and x + 1 values from the neighbouring lanes of one row load, with DPP
+    // wave shifts, loads 18 instead of 27 values but made the fused FP32 step
+    // 6 % slower on MI355X; loads it is.)
+    template <typename R, typename S>
+    __device__ __forceinline__ void stencil27(const S *f, R (&v)[27]) const
+    {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) v[k] = ld<R>(ptr(f, vel27(k, 0), vel27(k, 1), vel27(k, 2)));
     }
 };
 
