@@ -231,7 +231,6 @@ struct RkAdjointArgs {
     const void *phi;
     const void *u[3];
     void *coeff;
-    void *packed; // B_x, B_y, B_z, D, kappa of the stage (five fields)
     const void *lam;
     const void *theta_in;
     void *theta_out;

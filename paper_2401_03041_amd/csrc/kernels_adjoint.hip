@@ -30,9 +30,10 @@
 // with dL/dq(x) += kappa_s(x) and dL/dT_w += 2 C_k kappa_s over the ghost links.
 // A^T is applied as a gather: cell x collects C_k(x - e_k) kappa(x - e_k) over
 // the links that reach it, minus C_k(c) kappa(c) over the ghost links whose
-// mirror cell it is (c in its own row, shifted by -e_k in x and z).  A first
-// per-cell pass packs C_k(c) kappa(c) = w_k (e_k . B(c) + D(c)) into four
-// fields, so the gather reads four values per link.
+// mirror cell it is (c in its own row, shifted by -e_k in x and z).  The
+// stage kernel stages C_k(c) kappa(c) = w_k (e_k . B(c) + D(c)) as four values
+// per cell in LDS, so the gather reads four values per link from LDS and
+// every input from memory once.
 #include "kernels.hpp"
 
 namespace tcp {
@@ -228,70 +229,146 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_coeff(const RkAdjointArgs a
     st(elem(co + 3 * N, nb.c), R(a.kappa_l) + phic * R(a.dkappa));
 }
 
-// one reverse RK stage, first pass (per cell): kappa = w_s lambda' + a_s theta_in
-// and the packed link sources B = 3 kappa a, D = 6 kappa_diff kappa, so that
-// C_k(c) kappa(c) = w_k (e_k . B(c) + D(c)); packed = (B_x, B_y, B_z, D, kappa)
-template <typename S, typename R>
-__global__ void __launch_bounds__(kTX *kTY) k_rk_adj_pack(const RkAdjointArgs a, const Tiling t)
+// One reverse RK stage in one pass.  A work-group owns a 64 x 4 tile of cells
+// and marches up kAdjZ planes of it.  For every plane it stages, for the tile
+// and a one-cell halo in x and y, the packed link sources of the stage,
+//   kappa = w_s lambda' + a_s theta_in,  B = 3 kappa a,  D = 6 kappa kappa(phi),
+// so that C_k(c) kappa(c) = w_k (e_k . B(c) + D(c)), in LDS; three planes
+// (z - 1, z, z + 1) are held at a time, each read from memory once per
+// column.  Each cell then gathers theta_out = A^T kappa from LDS, adds it to
+// acc (which starts from lambda' in the last stage) and collects the source
+// and wall gradients of the stage.
+constexpr int kAdjZ = 16;                       // planes per work-group
+constexpr int kHX = kTX + 2, kHY = kTY + 2;     // tile with its halo
+constexpr int kHalo = kHX * kHY;                // 396 cells per staged plane
+
+struct AdjMarch {
+    int tiles_x, tiles_y, chunks_z;
+    int total, per_xcd;
+};
+
+inline AdjMarch make_adj_march(const Geometry &g)
 {
-    int x, y, z;
-    if (!cell_of_thread(t, a.geo, x, y, z)) return;
-    const uint32_t c = (uint32_t)x + (uint32_t)y * (uint32_t)a.geo.nx + (uint32_t)z * (uint32_t)a.geo.plane;
-    const int64_t N = a.geo.N;
-    R k = R(a.w_s) * ld<R>(elem(static_cast<const S *>(a.lam), c));
-    if (a.theta_in) k += R(a.a_s) * ld<R>(elem(static_cast<const S *>(a.theta_in), c));
-    const S *co = static_cast<const S *>(a.coeff);
-    S *pk = static_cast<S *>(a.packed);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) st(elem(pk + j * N, c), R(3) * k * ld<R>(elem(co + j * N, c)));
-    st(elem(pk + 3 * N, c), R(6) * k * ld<R>(elem(co + 3 * N, c)));
-    st(elem(pk + 4 * N, c), k);
+    AdjMarch m;
+    m.tiles_x = (g.nx + kTX - 1) / kTX;
+    m.tiles_y = (g.ny + kTY - 1) / kTY;
+    m.chunks_z = (g.nz + kAdjZ - 1) / kAdjZ;
+    m.total = m.tiles_x * m.tiles_y * m.chunks_z;
+    m.per_xcd = (m.total + kXCD - 1) / kXCD;
+    return m;
 }
 
-// second pass (gather): theta_out = A^T kappa, acc = (first ? lambda' : acc) + theta_out
-template <typename S, typename R>
-__global__ void __launch_bounds__(kTX *kTY) k_rk_adj_stage(const RkAdjointArgs a, const Tiling t)
+__device__ __forceinline__ int wrap(int v, int n)
 {
-    int x, y, z;
-    if (!cell_of_thread(t, a.geo, x, y, z)) return;
-    const Nbr nb(a.geo, x, y, z);
-    const int64_t N = a.geo.N;
-    const S *pk = static_cast<const S *>(a.packed);
-    const S *bx = pk, *by = pk + N, *bz = pk + 2 * N, *dd = pk + 3 * N;
-    R out = -R(1.0 - 8.0 / 27.0) * ld<R>(elem(dd, nb.c));
-    R refl[2] = {R(0), R(0)}; // ghost links mirrored onto this cell: bottom, top
-#pragma unroll
-    for (int i = 1; i < 27; ++i) {
-        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        const R w = R(weight<27>(i));
-        if (!nb.ghost(-ey)) {
-            // the link from c = x - e_i reaches this cell
-            R v = ld<R>(nb.ptr(dd, -ex, -ey, -ez));
-            if (ex) v += R(ex) * ld<R>(nb.ptr(bx, -ex, -ey, -ez));
-            if (ey) v += R(ey) * ld<R>(nb.ptr(by, -ex, -ey, -ez));
-            if (ez) v += R(ez) * ld<R>(nb.ptr(bz, -ex, -ey, -ez));
-            out += w * v;
-        }
-        if (nb.ghost(ey)) {
-            // the link from c = x - (e_x, 0, e_z) in this row leaves through the wall;
-            // its ghost mirrors onto this cell
-            R v = ld<R>(nb.ptr(dd, -ex, 0, -ez));
-            if (ex) v += R(ex) * ld<R>(nb.ptr(bx, -ex, 0, -ez));
-            v += R(ey) * ld<R>(nb.ptr(by, -ex, 0, -ez));
-            if (ez) v += R(ez) * ld<R>(nb.ptr(bz, -ex, 0, -ez));
-            refl[ey > 0] += w * v;
-        }
-    }
-    out -= refl[0] + refl[1];
-    st(elem(static_cast<S *>(a.theta_out), nb.c), out);
-    S *acc = static_cast<S *>(a.acc);
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// packed sources of plane zz (already wrapped) into LDS slot `slot`; halo rows
+// beyond a wall are never gathered from and hold zeros
+template <typename S, typename R>
+__device__ __forceinline__ void rk_adj_fill(const RkAdjointArgs &a, R (*lds)[4][kHalo], int slot, int x0, int y0,
+                                            int zz, int tid)
+{
+    const Geometry &g = a.geo;
+    const uint32_t N = (uint32_t)g.N;
     const S *lam = static_cast<const S *>(a.lam);
-    st(elem(acc, nb.c), (a.first ? ld<R>(elem(lam, nb.c)) : ld<R>(elem(acc, nb.c))) + out);
-    a.grad_q[nb.c] += static_cast<double>(ld<R>(elem(pk + 4 * N, nb.c)));
-    if (nb.below || nb.above) {
-        const uint32_t col = nb.col(0, 0, a.geo);
-        if (nb.below) a.grad_twb[col] += 2.0 * static_cast<double>(refl[0]);
-        if (nb.above) a.grad_twt[col] += 2.0 * static_cast<double>(refl[1]);
+    const S *thi = static_cast<const S *>(a.theta_in);
+    const S *co = static_cast<const S *>(a.coeff);
+    for (int i = tid; i < kHalo; i += kTX * kTY) {
+        const int gx = wrap(x0 - 1 + i % kHX, g.nx);
+        int gy = y0 - 1 + i / kHX;
+        R b[4] = {R(0), R(0), R(0), R(0)};
+        const bool beyond = gy < 0 || gy >= g.ny;
+        if (!(beyond && g.walls)) {
+            if (beyond) gy = wrap(gy, g.ny);
+            const uint32_t c = (uint32_t)gx + (uint32_t)gy * (uint32_t)g.nx + (uint32_t)zz * (uint32_t)g.plane;
+            R k = R(a.w_s) * ld<R>(elem(lam, c));
+            if (thi) k += R(a.a_s) * ld<R>(elem(thi, c));
+#pragma unroll
+            for (int j = 0; j < 3; ++j) b[j] = R(3) * k * ld<R>(elem(co + j * N, c));
+            b[3] = R(6) * k * ld<R>(elem(co + 3 * N, c));
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) lds[slot][j][i] = b[j];
+    }
+}
+
+template <typename S, typename R>
+__global__ void __launch_bounds__(kTX *kTY) k_rk_adj_march(const RkAdjointArgs a, const AdjMarch m)
+{
+    __shared__ R lds[3][4][kHalo];
+    const Geometry &g = a.geo;
+    const int w = blockIdx.x;
+    const int L = (w % kXCD) * m.per_xcd + w / kXCD;
+    if (L >= m.total) return; // a whole padding work-group: no barrier is reached
+    const int tx = L % m.tiles_x;
+    const int r = L / m.tiles_x;
+    const int ty = r % m.tiles_y;
+    const int cz = r / m.tiles_y;
+    const int x0 = tx * kTX, y0 = ty * kTY, z0 = cz * kAdjZ;
+    const int z1 = z0 + kAdjZ < g.nz ? z0 + kAdjZ : g.nz;
+    const int lx = threadIdx.x, ly = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int tid = lx + kTX * ly;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool live = x < g.nx && y < g.ny;
+    const bool below = g.walls && y == 0, above = g.walls && y == g.ny - 1;
+    const S *lam = static_cast<const S *>(a.lam);
+    const S *thi = static_cast<const S *>(a.theta_in);
+
+    rk_adj_fill<S, R>(a, lds, 0, x0, y0, wrap(z0 - 1, g.nz), tid);
+    rk_adj_fill<S, R>(a, lds, 1, x0, y0, z0, tid);
+    for (int z = z0; z < z1; ++z) {
+        const int k = z - z0;
+        // slots of planes z - 1, z, z + 1
+        const int sl[3] = {k % 3, (k + 1) % 3, (k + 2) % 3};
+        rk_adj_fill<S, R>(a, lds, sl[2], x0, y0, wrap(z + 1, g.nz), tid);
+        __syncthreads();
+        if (live) {
+            // LDS element of the cell at offset (dx, dy, dz), component j
+            auto at = [&](int j, int dx, int dy, int dz) -> R {
+                return lds[sl[dz + 1]][j][(ly + 1 + dy) * kHX + (lx + 1 + dx)];
+            };
+            R out = -R(1.0 - 8.0 / 27.0) * at(3, 0, 0, 0);
+            R refl[2] = {R(0), R(0)}; // ghost links mirrored onto this cell: bottom, top
+#pragma unroll
+            for (int i = 1; i < 27; ++i) {
+                const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+                const R wi = R(weight<27>(i));
+                if (!((ey > 0 && below) || (ey < 0 && above))) {
+                    // the link from c = x - e_i reaches this cell
+                    R v = at(3, -ex, -ey, -ez);
+                    if (ex) v += R(ex) * at(0, -ex, -ey, -ez);
+                    if (ey) v += R(ey) * at(1, -ex, -ey, -ez);
+                    if (ez) v += R(ez) * at(2, -ex, -ey, -ez);
+                    out += wi * v;
+                }
+                if ((ey < 0 && below) || (ey > 0 && above)) {
+                    // the link from c = x - (e_x, 0, e_z) in this row leaves through
+                    // the wall; its ghost mirrors onto this cell
+                    R v = at(3, -ex, 0, -ez);
+                    if (ex) v += R(ex) * at(0, -ex, 0, -ez);
+                    v += R(ey) * at(1, -ex, 0, -ez);
+                    if (ez) v += R(ez) * at(2, -ex, 0, -ez);
+                    refl[ey > 0] += wi * v;
+                }
+            }
+            out -= refl[0] + refl[1];
+            const uint32_t c = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * (uint32_t)g.plane;
+            st(elem(static_cast<S *>(a.theta_out), c), out);
+            S *acc = static_cast<S *>(a.acc);
+            const R l = ld<R>(elem(lam, c));
+            st(elem(acc, c), (a.first ? l : ld<R>(elem(acc, c))) + out);
+            R kc = R(a.w_s) * l;
+            if (thi) kc += R(a.a_s) * ld<R>(elem(thi, c));
+            a.grad_q[c] += static_cast<double>(kc);
+            if (below || above) {
+                const uint32_t col = (uint32_t)x + (uint32_t)z * (uint32_t)g.nx;
+                if (below) a.grad_twb[col] += 2.0 * static_cast<double>(refl[0]);
+                if (above) a.grad_twt[col] += 2.0 * static_cast<double>(refl[1]);
+            }
+        }
+        __syncthreads(); // the next plane's fill overwrites the slot of plane z - 1
     }
 }
 
@@ -307,9 +384,8 @@ void launch_rk_adjoint_coeff(const RkAdjointArgs &a, hipStream_t s)
 template <typename S, typename R>
 void launch_rk_adjoint_stage(const RkAdjointArgs &a, hipStream_t s)
 {
-    const Tiling t = make_tiling(a.geo);
-    hipLaunchKernelGGL((k_rk_adj_pack<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
-    hipLaunchKernelGGL((k_rk_adj_stage<S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    const AdjMarch m = make_adj_march(a.geo);
+    hipLaunchKernelGGL((k_rk_adj_march<S, R>), dim3((unsigned)(m.per_xcd * kXCD)), tiling_block(), 0, s, a, m);
 }
 
 template void launch_rk_adjoint_coeff<double, double>(const RkAdjointArgs &, hipStream_t);

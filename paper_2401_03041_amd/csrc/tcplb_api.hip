@@ -56,8 +56,7 @@ struct tcp_domain {
     void *adj_mu[2]{};
     double *adj_m = nullptr, *adj_g = nullptr, *adj_tw = nullptr, *adj_q = nullptr;
     // RK schemes instead of adj_mu: lambda', acc, two stage fields, and the
-    // right-hand side's coefficients (a_x, a_y, a_z, kappa) and a stage's packed
-    // link sources (five fields), N values each
+    // right-hand side's coefficients (a_x, a_y, a_z, kappa), N values each
     void *adj_rk = nullptr;
 
     // tape of a coupled run for its adjoint (tcp_step_taped / tcp_tape_adjoint):
@@ -603,13 +602,12 @@ void run_rk_adjoint(tcp_domain *d, int64_t nsteps)
     const size_t N = (size_t)d->geo.N;
     S *base = static_cast<S *>(d->adj_rk);
     S *lam = base, *acc = base + N, *th[2] = {base + 2 * N, base + 3 * N};
-    // base + 4N .. 8N: coefficients; 8N .. 13N: packed link sources
+    // base + 4N .. 8N: coefficients
     RkAdjointArgs a{};
     a.geo = d->geo;
     a.phi = d->phi[d->cur];
     for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
     a.coeff = base + 4 * N;
-    a.packed = base + 8 * N;
     a.kappa_l = d->P.kappa_l;
     a.dkappa = d->P.kappa_h - d->P.kappa_l;
     a.wet[0] = wetting(d->P.contact_angle_bot, d->P.xi);
@@ -1382,9 +1380,9 @@ int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, doub
         const size_t N = (size_t)d->geo.N, ncol = (size_t)d->P.nx * d->P.nz;
         const bool lb = d->P.thermal == TCP_THERMAL_LB;
         if (!d->adj_m) {
-            // link adjoints (LB) or thirteen fields (RK: lambda', acc, two stage fields,
-            // four coefficients, five packed link sources), then the FP64 buffers
-            const size_t mb = lb ? (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->sb : 13 * N * d->sb;
+            // link adjoints (LB) or eight fields (RK: lambda', acc, two stage fields,
+            // four coefficients), then the FP64 buffers
+            const size_t mb = lb ? (size_t)pdf_elems(d->geo, d->P.q_thermal) * d->sb : 8 * N * d->sb;
             void *p[6] = {own(d, mb), lb ? own(d, mb) : nullptr, own(d, N * sizeof(double)),
                           own(d, N * sizeof(double)), own(d, 2 * ncol * sizeof(double)),
                           own(d, 4 * kMaxSources * sizeof(double))};
@@ -1659,12 +1657,10 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
                         ? 2.0 * (d->P.q_pf + d->P.q_thermal) * pb + 54.0 * sb + 10.0 * sb
                         : 0.0;
     // per launch.  LB update: link adjoints in/out, u and phi in, the FP64
-    // source adjoint read and written.  RK stage: the packing pass reads
-    // lambda', the next stage's field and the four coefficients and writes
-    // five packed fields; the gather reads the packed fields, lambda' and acc
-    // and writes acc and the stage field; the FP64 source adjoint is read and
-    // written.
-    b[TCP_K_ADJOINT] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * sb + 4.0 * sb + 16.0 : 20.0 * sb + 16.0;
+    // source adjoint read and written.  RK stage (one pass): lambda', the next
+    // stage's field, the four coefficients and acc read, acc and the stage
+    // field written, the FP64 source adjoint read and written.
+    b[TCP_K_ADJOINT] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * sb + 4.0 * sb + 16.0 : 9.0 * sb + 16.0;
     // reverse step of the coupled adjoint (one kernel; link and field adjoints
     // in the arithmetic type, sb bytes): reads the link adjoints of h, g, f,
     // sphi, sT and lu1, the PDFs h, g, f of step n, phi^n, T^n, u^n, and

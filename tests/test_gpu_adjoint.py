@@ -130,13 +130,16 @@ def test_thermal_adjoint_periodic_and_two_rows(thermal, shape, periodic):
         assert close(tb, ob) and close(tt, ot), (tb, ob, tt, ot)
 
 
-def test_thermal_adjoint_against_gpu_forward():
-    """On a ragged 70 x 22 x 14 channel over 200 updates the adjoint's dL/dQ equals
-    the loss of the GPU's own warm-up at unit source amplitude from T = 0 (the map
-    is linear), in FP64; and the wall gradients sum to the loss of a unit
+@pytest.mark.parametrize("thermal", ["lb", "rk4"])
+def test_thermal_adjoint_against_gpu_forward(thermal):
+    """On a ragged 70 x 22 x 37 channel (two tiles in x, several in y and z, each
+    with a ragged end) over 200 updates the adjoint's dL/dQ equals the loss of
+    the GPU's own warm-up at unit source amplitude from T = 0 (the map is
+    linear), in FP64; and the wall gradients sum to the loss of a unit
     temperature on the whole wall."""
-    nx, ny, nz = 70, 22, 14
-    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_thermal=15, kappa_h=0.2, kappa_l=0.1, rho_l=0.5,
+    nx, ny, nz = 70, 22, 37
+    cfg = W.make(shape=(nx, ny, nz), periodic_y=False, q_thermal=15, thermal=thermal, kappa_h=0.2, kappa_l=0.1,
+                 rho_l=0.5,
                  xi=4.0, droplets=[(30.3, 6.7, 4.1, 4.5)],
                  heat_sources=[(0.02, 40.0, 6.0, 7.0, 6.0, 8.0), (0.01, 12.0, 15.0, 2.0, 3.0, 0.0)])
     rng = np.random.default_rng(3)
