@@ -196,7 +196,8 @@ void launch_read_pdfs(const void *src, int q, const Geometry &g, double shift, c
                       hipStream_t s);
 
 // FP64 sums of phi, phi x, phi y, phi z in fixed order: partial sums per
-// work-group, then one work-group adds them up.
+// work-group (wavefronts over whole x-rows, wave64 butterflies), then one
+// work-group adds them up.
 constexpr int kReduceBlocks = 1024;
 template <typename S>
 void launch_reduce(const Geometry &g, const void *phi, double *partial, double *out4, hipStream_t s);

@@ -135,47 +135,67 @@ __global__ void __launch_bounds__(kThreads) k_read_pdfs(const P *src, const Geom
         out[i * g.N + c] = static_cast<double>(src[pdf_index<Q>(g, x, y, z, i)]) + weight<Q>(i) * sh;
 }
 
+// Sum over the 64 lanes of a wavefront: a butterfly of cross-lane exchanges,
+// after which every lane holds the total (the same order on every call).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
+constexpr int kWaves = kThreads / 64;
+
+// the four sums of the wavefronts of this work-group, added in LDS, to out[0..3]
+__device__ __forceinline__ void block_sum4(double (&acc)[4], double *out)
+{
+    __shared__ double sh[kWaves][4];
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) acc[k] = wave_sum(acc[k]);
+    if (lane == 0)
+        for (int k = 0; k < 4; ++k) sh[wv][k] = acc[k];
+    __syncthreads();
+    if (threadIdx.x < 4) {
+        double t = 0.0;
+        for (int w = 0; w < kWaves; ++w) t += sh[w][threadIdx.x];
+        out[threadIdx.x] = t;
+    }
+}
+
+// Sums of phi, phi x, phi y, phi z.  Each wavefront takes whole x-rows (rows
+// dealt round-robin over the wavefronts of the grid), so y and z are uniform
+// across it and no cell needs a division: per row the lanes add phi and
+// phi x, and the row total is weighted by y and z once.
 template <typename S>
 __global__ void __launch_bounds__(kThreads) k_reduce_partial(const Geometry g, const S *phi, double *partial)
 {
-    __shared__ double sh[4][kThreads];
+    const int lane = threadIdx.x % 64;
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    const int rows = g.ny * g.nz;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x; c < g.N; c += (int64_t)gridDim.x * kThreads) {
-        const double p = static_cast<double>(phi[c]);
-        const int x = (int)(c % g.nx);
-        const int y = (int)((c / g.nx) % g.ny);
-        const int z = (int)(c / g.plane);
-        acc[0] += p;
-        acc[1] += p * x;
-        acc[2] += p * y;
-        acc[3] += p * z;
+    for (int r = (int)blockIdx.x * kWaves + wv; r < rows; r += (int)gridDim.x * kWaves) {
+        const S *row = phi + (int64_t)r * g.nx;
+        double rm = 0.0, rx = 0.0;
+        for (int x = lane; x < g.nx; x += 64) {
+            const double p = static_cast<double>(row[x]);
+            rm += p;
+            rx += p * x;
+        }
+        acc[0] += rm;
+        acc[1] += rx;
+        acc[2] += rm * (r % g.ny);
+        acc[3] += rm * (r / g.ny);
     }
-    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) partial[4 * blockIdx.x + k] = sh[k][0];
+    block_sum4(acc, partial + 4 * blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kThreads) k_reduce_final(const double *partial, int nblocks, double *out4)
 {
-    __shared__ double sh[4][kThreads];
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblocks; b += kThreads)
         for (int k = 0; k < 4; ++k) acc[k] += partial[4 * b + k];
-    for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] = acc[k];
-    __syncthreads();
-    for (int s = kThreads / 2; s > 0; s >>= 1) {
-        if ((int)threadIdx.x < s)
-            for (int k = 0; k < 4; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) out4[k] = sh[k][0];
+    block_sum4(acc, out4);
 }
 
 // max |a - b| over the grid; a NaN anywhere makes the result NaN

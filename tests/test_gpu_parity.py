@@ -298,11 +298,19 @@ def test_temperature_warmup_stops_at_tolerance():
     assert np.all(T == 0.0)
 
 
-def test_reduction_matches_host_sum():
-    """FP64 mass and centroid against a host sum of the read-back phase field."""
-    cfg = W.droplet_block(n=64, ndrop=4, radius=(6.0, 9.0), sigma_range=(6.0, 12.0), precision="fp32")
-    g = gpu_domain(cfg)
-    g.step(5)
+@pytest.mark.parametrize("case", ["block64", "ragged"])
+def test_reduction_matches_host_sum(case):
+    """FP64 mass and centroid against a host sum of the read-back phase field:
+    a 64^3 droplet block after five steps, and a random field on a ragged
+    130 x 70 x 90 grid (three 64-lane passes per row, the last partial; more
+    rows than wavefronts, so most wavefronts take two)."""
+    if case == "block64":
+        cfg = W.droplet_block(n=64, ndrop=4, radius=(6.0, 9.0), sigma_range=(6.0, 12.0), precision="fp32")
+        g = gpu_domain(cfg)
+        g.step(5)
+    else:
+        rng = np.random.default_rng(11)
+        g = gpu_domain(W.make(shape=(130, 70, 90)), phi=rng.uniform(0.0, 1.0, (90, 70, 130)))
     m, c = g.reduce()
     phi = g.get_field("phi")
     z, y, x = np.meshgrid(*(np.arange(n, dtype=np.float64) for n in phi.shape), indexing="ij")
