@@ -287,6 +287,7 @@ struct CoupledAdjointArgs {
     const void *sT_src;
     void *sT_dst;
     void *lu1;
+    void *xphi; // one field: K3's phi^{n+1} adjoint between the two halves of a split reverse step
     const double *twb, *twt;
     double uw_bot[3], uw_top[3];
     double wet[2];

@@ -261,7 +261,7 @@ __device__ __forceinline__ void adj_hydro_cell(const CoupledAdjointArgs &a, cons
 // R1: phase field.  aphi3: K3's adjoint of phi^{n+1}; sp: K2's adjoints of
 // the phi^n stencil reads, completed here with K1's gradient adjoint and stored.
 // ---------------------------------------------------------------------------
-template <int Q, typename P, typename S, typename R, bool WALL>
+template <int Q, typename P, typename S, typename R, bool WALL, bool SPLIT>
 __device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const Nbr &nb, R aphi3, const R (&sp)[5])
 {
     constexpr bool dev = deviation_storage<P>();
@@ -352,39 +352,62 @@ __device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const N
     S *lu1 = static_cast<S *>(a.lu1);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        st(elem(sd + k * N, nb.c), sp[k] + aG[k]);
+        // split: the hydrodynamic half has stored its part of the stencil adjoint
+        const R spk = SPLIT ? ld<R>(elem(sd + k * N, nb.c)) : sp[k];
+        st(elem(sd + k * N, nb.c), spk + aG[k]);
         st(elem(lu1 + k * N, nb.c), au[k]);
     }
-    st(elem(sd + 3 * N, nb.c), sp[3]);
-    st(elem(sd + 4 * N, nb.c), sp[4]);
+    if (!SPLIT) {
+        st(elem(sd + 3 * N, nb.c), sp[3]);
+        st(elem(sd + 4 * N, nb.c), sp[4]);
+    }
 }
 
 // One reverse step, the three reverse updates of a cell in one thread (K3, K2,
 // K1 in turn): every value a thread reads from another cell comes from the
 // previous reverse step's buffers, and the adjoints passed between the phases
-// (of u^{n+1}, phi^{n+1} and the phi^n stencil) stay in registers.
-template <int QH, int QF, typename P, typename S, typename R, bool WALL>
+// (of u^{n+1}, phi^{n+1} and the phi^n stencil) stay in registers (PART 0).
+// Split in two launches (PART 1: K3 and K2, PART 2: K1) the halves need fewer
+// registers each; the first stores its part of the phi^n stencil adjoint
+// (sp) where the step's own result goes, and the phi^{n+1} adjoint of K3 in
+// a scratch field, both read back at the same cell by the second.
+template <int QH, int QF, typename P, typename S, typename R, bool WALL, int PART>
 __device__ __forceinline__ void adj_step_cell(const CoupledAdjointArgs &a, const Nbr &nb)
 {
     R au3[3], aphi3;
-    adj_thermal_cell<QF, P, S, R, WALL>(a, opaque(nb), au3, aphi3);
-    __builtin_amdgcn_sched_barrier(0);
     R sp[5];
-    adj_hydro_cell<S, R, WALL>(a, opaque(nb), au3, sp);
+    const int64_t N = a.geo.N;
+    if (PART != 2) {
+        adj_thermal_cell<QF, P, S, R, WALL>(a, opaque(nb), au3, aphi3);
+        __builtin_amdgcn_sched_barrier(0);
+        adj_hydro_cell<S, R, WALL>(a, opaque(nb), au3, sp);
+    }
+    if (PART == 1) {
+        S *sd = static_cast<S *>(a.sphi_dst);
+#pragma unroll
+        for (int k = 0; k < 5; ++k) st(elem(sd + k * N, nb.c), sp[k]);
+        st(elem(static_cast<S *>(a.xphi), nb.c), aphi3);
+        return;
+    }
+    if (PART == 2) {
+        aphi3 = ld<R>(elem(static_cast<const S *>(a.xphi), nb.c));
+#pragma unroll
+        for (int k = 0; k < 5; ++k) sp[k] = R(0); // unused: read back from sphi_dst
+    }
     __builtin_amdgcn_sched_barrier(0);
-    adj_pf_cell<QH, P, S, R, WALL>(a, opaque(nb), aphi3, sp);
+    adj_pf_cell<QH, P, S, R, WALL, PART == 2>(a, opaque(nb), aphi3, sp);
 }
 
-template <int QH, int QF, typename P, typename S, typename R>
+template <int QH, int QF, typename P, typename S, typename R, int PART>
 __global__ void __launch_bounds__(kTX *kTY) k_adj_step(const CoupledAdjointArgs a, const Tiling t)
 {
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
     const Nbr nb(a.geo, x, y, z);
     if (nb.below || nb.above)
-        adj_step_cell<QH, QF, P, S, R, true>(a, nb);
+        adj_step_cell<QH, QF, P, S, R, true, PART>(a, nb);
     else
-        adj_step_cell<QH, QF, P, S, R, false>(a, nb);
+        adj_step_cell<QH, QF, P, S, R, false, PART>(a, nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -442,7 +465,14 @@ template <int QH, int QF, typename P, typename S, typename R>
 void launch_coupled_adjoint_step(const CoupledAdjointArgs &a, hipStream_t s)
 {
     const Tiling t = make_tiling(a.geo);
-    hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    if constexpr (sizeof(R) == 4) {
+        // FP32 arithmetic: two launches of about 170 and 130 registers run three
+        // wavefronts per SIMD where the whole update (188) runs two
+        hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R, 1>), tiling_grid(t), tiling_block(), 0, s, a, t);
+        hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R, 2>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    } else {
+        hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R, 0>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    }
 }
 
 template <typename S>

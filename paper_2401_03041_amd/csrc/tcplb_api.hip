@@ -772,7 +772,7 @@ int ensure_tape(tcp_domain *d, int64_t nseg, int64_t seg)
     std::vector<size_t> work;
     for (int k = 0; k < 3; ++k) work.insert(work.end(), {qb[k], qb[k]});          // mu[k][0..1]
     work.insert(work.end(), {5 * N * sb, 5 * N * sb, 4 * N * sb, 4 * N * sb}); // sphi, sT
-    work.push_back(3 * N * sb);                                               // lu1
+    work.push_back(4 * N * sb);                                               // lu1, xphi
     work.insert(work.end(), {N * sizeof(double), 2 * ncol * sizeof(double), 4 * kMaxSources * sizeof(double),
                              N * sizeof(double), ncol * sizeof(double), ncol * sizeof(double)});
     const size_t nckpt = (size_t)nseg + 1, nring = (size_t)seg - 1, nslots = nckpt + nring;
@@ -879,6 +879,7 @@ void reverse_step(tcp_domain *d, const StateSlot &s0, const StateSlot &s1, int b
     a.sT_src = tp.sT[b];
     a.sT_dst = tp.sT[1 - b];
     a.lu1 = tp.lu1;
+    a.xphi = static_cast<char *>(tp.lu1) + 3 * (size_t)d->geo.N * d->sb;
     a.twb = tp.twb;
     a.twt = tp.twt;
     a.wet[0] = wetting(P.contact_angle_bot, P.xi);

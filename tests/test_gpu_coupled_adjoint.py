@@ -127,17 +127,18 @@ def _along(grads, direction):
     return float(np.sum(dsrc * ds[:, :4]) + np.sum(dbot * db) + np.sum(dtop * dt))
 
 
-def _check(grads, directions, fd_of, tol, what):
+def _check(grads, directions, fd_of, tol, what, floor=0.0):
     """Directional derivatives of the adjoint against difference quotients:
-    |adjoint - FD| <= tol max(|FD|, |FD|_max / 100), so that a direction along
-    which the loss hardly changes is held to the scale of the gradient."""
+    |adjoint - FD| <= tol max(|FD|, |FD|_max / 100) + floor, so that a direction
+    along which the loss hardly changes is held to the scale of the gradient;
+    floor is the difference quotient's own round-off."""
     rows = [(d[0], _along(grads, d), fd_of(d)) for d in directions]
     scale = max(abs(fd) for _, _, fd in rows) / 100.0
     for name, ad, fd in rows:
         err = abs(ad - fd) / max(abs(fd), scale)
-        print(f"{what} {name}: adjoint {ad:.12e} FD {fd:.12e} err {err:.2e}", flush=True)
+        print(f"{what} {name}: adjoint {ad:.12e} FD {fd:.12e} err {err:.2e} (floor {floor:.1e})", flush=True)
     for name, ad, fd in rows:
-        assert abs(ad - fd) <= tol * max(abs(fd), scale), (what, name, ad, fd)
+        assert abs(ad - fd) <= tol * max(abs(fd), scale) + floor, (what, name, ad, fd)
 
 
 @pytest.mark.parametrize("kind,steps", [("capture", 150), ("mixed", 100)])
@@ -155,12 +156,24 @@ def test_gradients_match_oracle_central_differences(kind, steps):
 
 @pytest.mark.parametrize("kind,steps", [("capture", 150), ("mixed", 100)])
 def test_gradients_match_gpu_central_differences(kind, steps):
+    """Against central differences of the GPU's FP64 forward at step 1e-3 (the
+    truncation error, about (1e-3 / w_s)^2 of the derivative, stays far below
+    the bar).  The centroid comes from FP64 sums over about 1.4e4 cells, so
+    each evaluation carries a round-off of a few ulp of |c| that does not vary
+    smoothly with the inputs (about 1.5 ulp measured from the quotients at
+    step 1e-4); the quotient then carries about sum_k 2 |c_k - t_k| m u |c_k| /
+    (2 step), allowed on top of the 2e-6 bar with m = 8 ulp.  It matters only
+    along directions whose derivative is a thousandth of the largest."""
     cfg, twb, twt, dirs_b = _small(kind)
     src = [list(s) for s in cfg["heat_sources"]]
     target = _target(cfg)
     grads = _adjoint(cfg, src, twb, twt, steps, target)
-    _check(grads, _directions(src, dirs_b), lambda d: _fd(_loss_gpu, cfg, src, twb, twt, steps, target, d), 2e-6,
-           f"{kind} GPU FD")
+    d, c = _centroid_gpu(cfg, src, twb, twt, steps)
+    d.close()
+    eps = 1e-3
+    floor = float(np.sum(2.0 * np.abs(c - target) * 8.0 * np.finfo(np.float64).eps * np.abs(c))) / (2.0 * eps)
+    _check(grads, _directions(src, dirs_b),
+           lambda dd: _fd(_loss_gpu, cfg, src, twb, twt, steps, target, dd, eps=eps), 2e-6, f"{kind} GPU FD", floor)
 
 
 def test_checkpoint_segments_give_identical_gradients():
