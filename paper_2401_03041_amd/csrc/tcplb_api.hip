@@ -61,16 +61,20 @@ struct tcp_domain {
 
     // tape of a coupled run for its adjoint (tcp_step_taped / tcp_tape_adjoint):
     // the states at the start of every segment of `seg` steps and the final
-    // state (nseg + 1 checkpoints), a ring of seg - 1 states for the inner
-    // states of one segment (ring_seg: the segment it holds, -1 none), the
-    // heat sources and wall temperatures in force, and the reverse sweep's
-    // workspace
+    // state (nseg + 1 checkpoints), one or two rings of seg - 1 states for the
+    // inner states of a segment (ring_seg: the segment a ring holds, -1 none;
+    // with two, the reverse sweep of one segment overlaps the recomputation of
+    // the next on a second stream), the heat sources and wall temperatures in
+    // force, and the reverse sweep's workspace
     struct Tape {
         bool valid = false;
-        int64_t nsteps = 0, seg = 0, nseg = 0, ring_seg = -1;
+        int64_t nsteps = 0, seg = 0, nseg = 0, ring_seg[2] = {-1, -1};
+        int nrings = 1;
         void *mem = nullptr;
         size_t mem_bytes = 0;
-        std::vector<StateSlot> ckpt, ring;
+        std::vector<StateSlot> ckpt, ring[2];
+        hipStream_t side = nullptr;                  // recomputation stream (default priority)
+        hipEvent_t ready[2] = {}, freed[2] = {}, start = nullptr;
         HeatSources src{};
         double *twb = nullptr, *twt = nullptr;
         void *mu[3][2]{}, *sphi[2]{}, *sT[2]{}, *lu1 = nullptr;
@@ -775,25 +779,45 @@ int ensure_tape(tcp_domain *d, int64_t nseg, int64_t seg)
     work.push_back(4 * N * sb);                                               // lu1, xphi
     work.insert(work.end(), {N * sizeof(double), 2 * ncol * sizeof(double), 4 * kMaxSources * sizeof(double),
                              N * sizeof(double), ncol * sizeof(double), ncol * sizeof(double)});
-    const size_t nckpt = (size_t)nseg + 1, nring = (size_t)seg - 1, nslots = nckpt + nring;
-    size_t total = nslots * slot;
-    for (size_t w : work) total += round256(w);
-    if (tp.mem && tp.mem_bytes != total) {
-        (void)hipStreamSynchronize(d->stream);
-        dev_free(d, tp.mem);
-        tp.mem = nullptr;
-    }
-    if (!tp.mem) {
+    const size_t nckpt = (size_t)nseg + 1, nring = (size_t)seg - 1;
+    size_t wtotal = 0;
+    for (size_t w : work) wtotal += round256(w);
+    // a second ring when there is more than one segment to recompute and it
+    // fits; otherwise one ring and no overlap
+    int nrings = nseg > 1 && nring > 0 ? 2 : 1;
+    for (; nrings >= 1; --nrings) {
+        const size_t total = (nckpt + nrings * nring) * slot + wtotal;
+        if (tp.mem && tp.mem_bytes == total) break;
+        if (tp.mem) {
+            (void)hipStreamSynchronize(d->stream);
+            dev_free(d, tp.mem);
+            tp.mem = nullptr;
+        }
         tp.mem = dev_alloc(d, total);
-        if (!tp.mem) return fail(d, TCP_ERR_OOM, "device allocation failed (tape of the coupled run)");
-        tp.mem_bytes = total;
+        if (tp.mem) {
+            tp.mem_bytes = total;
+            break;
+        }
     }
+    if (!tp.mem) return fail(d, TCP_ERR_OOM, "device allocation failed (tape of the coupled run)");
+    tp.nrings = nrings;
+    if (nrings == 2 && !tp.side) {
+        TCP_HIP(d, hipStreamCreateWithFlags(&tp.side, hipStreamNonBlocking));
+        for (int r = 0; r < 2; ++r) {
+            TCP_HIP(d, hipEventCreateWithFlags(&tp.ready[r], hipEventDisableTiming));
+            TCP_HIP(d, hipEventCreateWithFlags(&tp.freed[r], hipEventDisableTiming));
+        }
+        TCP_HIP(d, hipEventCreateWithFlags(&tp.start, hipEventDisableTiming));
+    }
+    const size_t nslots = nckpt + nrings * nring;
     char *p = static_cast<char *>(tp.mem);
     tp.ckpt.assign(nckpt, StateSlot{});
-    tp.ring.assign(nring, StateSlot{});
-    tp.ring_seg = -1;
+    for (int r = 0; r < 2; ++r) {
+        tp.ring[r].assign(r < nrings ? nring : 0, StateSlot{});
+        tp.ring_seg[r] = -1;
+    }
     for (size_t j = 0; j < nslots; ++j) {
-        StateSlot &st = j < nckpt ? tp.ckpt[j] : tp.ring[j - nckpt];
+        StateSlot &st = j < nckpt ? tp.ckpt[j] : tp.ring[(j - nckpt) / nring][(j - nckpt) % nring];
         for (int k = 0; k < kSlotPieces; ++k) {
             slot_piece(st, k) = p;
             p += round256(sz[k]);
@@ -898,23 +922,32 @@ void reverse_step(tcp_domain *d, const StateSlot &s0, const StateSlot &s1, int b
 }
 
 // State s (0 .. k_j) of segment j: its first and last are checkpoints, the
-// inner ones live in the ring.
-const StateSlot &seg_state(const tcp_domain *d, int64_t j, int64_t s, int64_t kj)
+// inner ones live in ring r.
+const StateSlot &seg_state(const tcp_domain *d, int64_t j, int64_t s, int64_t kj, int r)
 {
     const auto &tp = d->tape;
     if (s == 0) return tp.ckpt[(size_t)j];
     if (s == kj) return tp.ckpt[(size_t)j + 1];
-    return tp.ring[(size_t)s - 1];
+    return tp.ring[r][(size_t)s - 1];
 }
 
-// the steps of segment j from its checkpoint: the inner states into the ring,
+// the steps of segment j from its checkpoint: the inner states into ring r,
 // the last into the next checkpoint (if `last`)
 template <typename S, typename Pdf>
-void run_segment(tcp_domain *d, int64_t j, int64_t kj, bool last)
+void run_segment(tcp_domain *d, int64_t j, int64_t kj, bool last, int r)
 {
-    for (int64_t s = 0; s < (last ? kj : kj - 1); ++s) slot_step<S, Pdf>(d, seg_state(d, j, s, kj), seg_state(d, j, s + 1, kj));
-    d->tape.ring_seg = j;
+    for (int64_t s = 0; s < (last ? kj : kj - 1); ++s)
+        slot_step<S, Pdf>(d, seg_state(d, j, s, kj, r), seg_state(d, j, s + 1, kj, r));
+    d->tape.ring_seg[r] = j;
 }
+
+// Launches of the calling scope go to stream s (kernel timers included).
+struct OnStream {
+    tcp_domain *d;
+    hipStream_t saved;
+    OnStream(tcp_domain *dd, hipStream_t s) : d(dd), saved(dd->stream) { d->stream = s; }
+    ~OnStream() { d->stream = saved; }
+};
 
 // The taped run: the domain's state becomes checkpoint 0, every segment runs
 // from its checkpoint into the ring and the next checkpoint, and the final
@@ -925,16 +958,20 @@ int run_taped(tcp_domain *d)
     auto &tp = d->tape;
     int rc = copy_slot(d, tp.ckpt[0], domain_slot(d));
     if (rc != TCP_OK) return rc;
-    for (int64_t j = 0; j < tp.nseg; ++j) run_segment<S, Pdf>(d, j, std::min(tp.seg, tp.nsteps - j * tp.seg), true);
+    for (int64_t j = 0; j < tp.nseg; ++j) run_segment<S, Pdf>(d, j, std::min(tp.seg, tp.nsteps - j * tp.seg), true, 0);
     rc = copy_slot(d, domain_slot(d), tp.ckpt[(size_t)tp.nseg]);
     if (rc != TCP_OK) return rc;
     return check_launch(d);
 }
 
 // Reverse sweep over the taped steps, last segment first: recompute the inner
-// states of a segment from its checkpoint (unless the ring holds them
-// already), then undo its steps last to first.  The loss enters through the
-// final phase field (seeded before the first reverse step).
+// states of a segment from its checkpoint (unless a ring holds them already),
+// then undo its steps last to first.  With two rings the recomputation of
+// segment j - 1 runs on the side stream into one ring while the reverse steps
+// of segment j read the other: the side stream waits until the reverse sweep
+// that last read its ring is done (`freed`), the main stream until the ring
+// it is about to read is filled (`ready`).  The loss enters through the final
+// phase field (seeded before the first reverse step).
 template <typename S, typename Pdf>
 int run_tape_adjoint(tcp_domain *d, const double gc[3], const double *dphi)
 {
@@ -942,13 +979,38 @@ int run_tape_adjoint(tcp_domain *d, const double gc[3], const double *dphi)
     const size_t ncol = (size_t)d->P.nx * d->P.nz;
     launch_reduce<S>(d->geo, tp.ckpt[(size_t)tp.nseg].phi, d->partial, d->out4, d->stream);
     launch_coupled_adjoint_seed<S>(d->geo, d->out4, gc, dphi, tp.sphi[0], d->stream);
+    const bool overlap = tp.nrings == 2;
+    if (overlap) {
+        // the side stream starts after everything queued so far; both rings
+        // count as released at the start (every event waited on is recorded)
+        TCP_HIP(d, hipEventRecord(tp.start, d->stream));
+        TCP_HIP(d, hipStreamWaitEvent(tp.side, tp.start, 0));
+        for (int k = 0; k < 2; ++k) TCP_HIP(d, hipEventRecord(tp.freed[k], d->stream));
+    }
+    auto kseg = [&](int64_t j) { return std::min(tp.seg, tp.nsteps - j * tp.seg); };
     int b = 0;
+    int r = 0; // ring of segment j (the taped run leaves the last segment in ring 0)
     for (int64_t j = tp.nseg - 1; j >= 0; --j) {
-        const int64_t kj = std::min(tp.seg, tp.nsteps - j * tp.seg);
-        if (tp.ring_seg != j) run_segment<S, Pdf>(d, j, kj, false);
+        const int64_t kj = kseg(j);
+        if (tp.ring_seg[r] != j) run_segment<S, Pdf>(d, j, kj, false, r);
+        if (overlap && j > 0) {
+            // recompute segment j - 1 into the other ring meanwhile
+            const int o = 1 - r;
+            TCP_HIP(d, hipStreamWaitEvent(tp.side, tp.freed[o], 0));
+            {
+                OnStream on(d, tp.side);
+                run_segment<S, Pdf>(d, j - 1, kseg(j - 1), false, o);
+            }
+            TCP_HIP(d, hipEventRecord(tp.ready[o], tp.side));
+        }
         for (int64_t s = kj - 1; s >= 0; --s) {
-            reverse_step<S, Pdf>(d, seg_state(d, j, s, kj), seg_state(d, j, s + 1, kj), b);
+            reverse_step<S, Pdf>(d, seg_state(d, j, s, kj, r), seg_state(d, j, s + 1, kj, r), b);
             b = 1 - b;
+        }
+        if (overlap && j > 0) {
+            TCP_HIP(d, hipEventRecord(tp.freed[r], d->stream));
+            r = 1 - r;
+            TCP_HIP(d, hipStreamWaitEvent(d->stream, tp.ready[r], 0));
         }
         const int rc = check_launch(d);
         if (rc != TCP_OK) return rc;
@@ -1115,6 +1177,12 @@ int tcp_destroy(tcp_domain *d)
     (void)hipStreamSynchronize(d->stream);
     drop_graphs(d);
     if (d->cap_stream) (void)hipStreamDestroy(d->cap_stream);
+    if (d->tape.side) {
+        (void)hipStreamSynchronize(d->tape.side);
+        (void)hipStreamDestroy(d->tape.side);
+    }
+    for (hipEvent_t e : {d->tape.ready[0], d->tape.ready[1], d->tape.freed[0], d->tape.freed[1], d->tape.start})
+        if (e) (void)hipEventDestroy(e);
     for (auto &r : d->records) {
         (void)hipEventDestroy(r.start);
         (void)hipEventDestroy(r.stop);
