@@ -230,7 +230,7 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_coeff(const RkAdjointArgs a
 }
 
 // One reverse RK stage in one pass.  A work-group owns a 64 x 4 tile of cells
-// and marches up kAdjZ planes of it.  For every plane it stages, for the tile
+// and marches up kMarchZ planes of it.  For every plane it stages, for the tile
 // and a one-cell halo in x and y, the packed link sources of the stage,
 //   kappa = w_s lambda' + a_s theta_in,  B = 3 kappa a,  D = 6 kappa kappa(phi),
 // so that C_k(c) kappa(c) = w_k (e_k . B(c) + D(c)), in LDS; three planes
@@ -238,31 +238,6 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_coeff(const RkAdjointArgs a
 // column.  Each cell then gathers theta_out = A^T kappa from LDS, adds it to
 // acc (which starts from lambda' in the last stage) and collects the source
 // and wall gradients of the stage.
-constexpr int kAdjZ = 16;                       // planes per work-group
-constexpr int kHX = kTX + 2, kHY = kTY + 2;     // tile with its halo
-constexpr int kHalo = kHX * kHY;                // 396 cells per staged plane
-
-struct AdjMarch {
-    int tiles_x, tiles_y, chunks_z;
-    int total, per_xcd;
-};
-
-inline AdjMarch make_adj_march(const Geometry &g)
-{
-    AdjMarch m;
-    m.tiles_x = (g.nx + kTX - 1) / kTX;
-    m.tiles_y = (g.ny + kTY - 1) / kTY;
-    m.chunks_z = (g.nz + kAdjZ - 1) / kAdjZ;
-    m.total = m.tiles_x * m.tiles_y * m.chunks_z;
-    m.per_xcd = (m.total + kXCD - 1) / kXCD;
-    return m;
-}
-
-__device__ __forceinline__ int wrap(int v, int n)
-{
-    v %= n;
-    return v < 0 ? v + n : v;
-}
 
 // packed sources of plane zz (already wrapped) into LDS slot `slot`; halo rows
 // beyond a wall are never gathered from and hold zeros
@@ -276,13 +251,9 @@ __device__ __forceinline__ void rk_adj_fill(const RkAdjointArgs &a, R (*lds)[4][
     const S *thi = static_cast<const S *>(a.theta_in);
     const S *co = static_cast<const S *>(a.coeff);
     for (int i = tid; i < kHalo; i += kTX * kTY) {
-        const int gx = wrap(x0 - 1 + i % kHX, g.nx);
-        int gy = y0 - 1 + i / kHX;
         R b[4] = {R(0), R(0), R(0), R(0)};
-        const bool beyond = gy < 0 || gy >= g.ny;
-        if (!(beyond && g.walls)) {
-            if (beyond) gy = wrap(gy, g.ny);
-            const uint32_t c = (uint32_t)gx + (uint32_t)gy * (uint32_t)g.nx + (uint32_t)zz * (uint32_t)g.plane;
+        uint32_t c;
+        if (halo_cell(g, x0, y0, zz, i, c)) {
             R k = R(a.w_s) * ld<R>(elem(lam, c));
             if (thi) k += R(a.a_s) * ld<R>(elem(thi, c));
 #pragma unroll
@@ -295,19 +266,12 @@ __device__ __forceinline__ void rk_adj_fill(const RkAdjointArgs &a, R (*lds)[4][
 }
 
 template <typename S, typename R>
-__global__ void __launch_bounds__(kTX *kTY) k_rk_adj_march(const RkAdjointArgs a, const AdjMarch m)
+__global__ void __launch_bounds__(kTX *kTY) k_rk_adj_march(const RkAdjointArgs a, const March m)
 {
     __shared__ R lds[3][4][kHalo];
     const Geometry &g = a.geo;
-    const int w = blockIdx.x;
-    const int L = (w % kXCD) * m.per_xcd + w / kXCD;
-    if (L >= m.total) return; // a whole padding work-group: no barrier is reached
-    const int tx = L % m.tiles_x;
-    const int r = L / m.tiles_x;
-    const int ty = r % m.tiles_y;
-    const int cz = r / m.tiles_y;
-    const int x0 = tx * kTX, y0 = ty * kTY, z0 = cz * kAdjZ;
-    const int z1 = z0 + kAdjZ < g.nz ? z0 + kAdjZ : g.nz;
+    int x0, y0, z0, z1;
+    if (!march_tile(m, g, x0, y0, z0, z1)) return;
     const int lx = threadIdx.x, ly = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
     const int tid = lx + kTX * ly;
     const int x = x0 + lx, y = y0 + ly;
@@ -384,8 +348,8 @@ void launch_rk_adjoint_coeff(const RkAdjointArgs &a, hipStream_t s)
 template <typename S, typename R>
 void launch_rk_adjoint_stage(const RkAdjointArgs &a, hipStream_t s)
 {
-    const AdjMarch m = make_adj_march(a.geo);
-    hipLaunchKernelGGL((k_rk_adj_march<S, R>), dim3((unsigned)(m.per_xcd * kXCD)), tiling_block(), 0, s, a, m);
+    const March m = make_march(a.geo);
+    hipLaunchKernelGGL((k_rk_adj_march<S, R>), march_grid(m), tiling_block(), 0, s, a, m);
 }
 
 template void launch_rk_adjoint_coeff<double, double>(const RkAdjointArgs &, hipStream_t);

@@ -89,57 +89,90 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_coef(const RkArgs a, const Tili
         rk_coef_cell<S, R, false>(a, nb, x, y, z);
 }
 
-template <typename S, typename R, bool WALL, bool GK, bool HQ>
-__device__ __forceinline__ void rk_cell(const RkArgs &a, const Nbr &nb)
+// The stage at cell c from the stencil sums of its argument theta: gt (the
+// isotropic gradient without its factor 3) and lap (the Laplacian).
+template <typename S, typename R, bool GK, bool HQ>
+__device__ __forceinline__ void rk_tail(const RkArgs &a, uint32_t c, const R (&gt)[3], R lap)
 {
-    const S *th = static_cast<const S *>(a.theta_in);
     const S *co = static_cast<const S *>(a.coef);
     const int64_t N = a.geo.N;
-    const R tc = ld<R>(elem(th, nb.c));
-    R gt[3] = {R(0), R(0), R(0)}, lap = R(0);
-#pragma unroll
-    for (int i = 1; i < 27; ++i) {
-        const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
-        const R w = R(weight<27>(i));
-        R tv = ld<R>(nb.ptr(th, ex, ey, ez));
-        if (WALL && nb.ghost(ey)) {
-            const double *tw = ey < 0 ? a.twb : a.twt;
-            tv = R(2) * R(tw[nb.col(ex, ez, a.geo)]) - tv;
-        }
-        if (ex) gt[0] += R(ex) * w * tv;
-        if (ey) gt[1] += R(ey) * w * tv;
-        if (ez) gt[2] += R(ez) * w * tv;
-        lap += w * tv;
-    }
-    lap = R(6) * (lap - R(1.0 - weight<27>(0)) * tc);
     R av[3], kap;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        av[k] = GK ? ld<R>(elem(co + k * N, nb.c)) : -ld<R>(elem(static_cast<const S *>(a.u[k]), nb.c));
-    kap = GK ? ld<R>(elem(co + 3 * N, nb.c)) : R(a.kappa_l);
+        av[k] = GK ? ld<R>(elem(co + k * N, c)) : -ld<R>(elem(static_cast<const S *>(a.u[k]), c));
+    kap = GK ? ld<R>(elem(co + 3 * N, c)) : R(a.kappa_l);
     R k = R(3) * (av[0] * gt[0] + av[1] * gt[1] + av[2] * gt[2]) + kap * lap;
-    if (HQ) k += ld<R>(elem(co + 4 * N, nb.c));
+    if (HQ) k += ld<R>(elem(co + 4 * N, c));
     S *ap = static_cast<S *>(a.acc);
-    const R T = ld<R>(elem(static_cast<const S *>(a.T), nb.c));
-    const R acc = (a.first ? R(0) : ld<R>(elem(ap, nb.c))) + R(a.w_acc) * k;
+    const R T = ld<R>(elem(static_cast<const S *>(a.T), c));
+    const R acc = (a.first ? R(0) : ld<R>(elem(ap, c))) + R(a.w_acc) * k;
     if (a.last) {
-        st(elem(static_cast<S *>(a.T_new), nb.c), T + acc);
+        st(elem(static_cast<S *>(a.T_new), c), T + acc);
     } else {
-        if (ap) st(elem(ap, nb.c), acc);
-        st(elem(static_cast<S *>(a.theta_out), nb.c), T + R(a.a_next) * k);
+        if (ap) st(elem(ap, c), acc);
+        st(elem(static_cast<S *>(a.theta_out), c), T + R(a.a_next) * k);
     }
 }
 
+// One RK stage (Eq. rk2 / rk4 with the right-hand side of the energy
+// equation): the argument theta is staged plane by plane in LDS for a 64 x 4
+// tile and its halo while the work-group marches up kMarchZ planes (three
+// planes held at a time), so its 27-point stencil costs about 1.55 loads per
+// cell instead of 27.  A neighbour across a wall is the ghost 2 T_w - theta
+// of the mirror cell in the own row.
 template <typename S, typename R, bool GK, bool HQ>
-__global__ void __launch_bounds__(kTX *kTY) k_rk_stage(const RkArgs a, const Tiling t)
+__global__ void __launch_bounds__(kTX *kTY) k_rk_stage(const RkArgs a, const March m)
 {
-    int x, y, z;
-    if (!cell_of_thread(t, a.geo, x, y, z)) return;
-    const Nbr nb(a.geo, x, y, z);
-    if (nb.below || nb.above)
-        rk_cell<S, R, true, GK, HQ>(a, nb);
-    else
-        rk_cell<S, R, false, GK, HQ>(a, nb);
+    __shared__ R lds[3][kHalo];
+    const Geometry &g = a.geo;
+    int x0, y0, z0, z1;
+    if (!march_tile(m, g, x0, y0, z0, z1)) return;
+    const int lx = threadIdx.x, ly = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+    const int tid = lx + kTX * ly;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool live = x < g.nx && y < g.ny;
+    const bool below = g.walls && y == 0, above = g.walls && y == g.ny - 1;
+    const S *th = static_cast<const S *>(a.theta_in);
+    auto fill = [&](int slot, int zz) {
+        for (int i = tid; i < kHalo; i += kTX * kTY) {
+            uint32_t c;
+            lds[slot][i] = halo_cell(g, x0, y0, zz, i, c) ? ld<R>(elem(th, c)) : R(0);
+        }
+    };
+    fill(0, wrap(z0 - 1, g.nz));
+    fill(1, z0);
+    for (int z = z0; z < z1; ++z) {
+        const int k = z - z0;
+        const int sl[3] = {k % 3, (k + 1) % 3, (k + 2) % 3}; // planes z - 1, z, z + 1
+        fill(sl[2], wrap(z + 1, g.nz));
+        __syncthreads();
+        if (live) {
+            auto at = [&](int dx, int dy, int dz) -> R { return lds[sl[dz + 1]][(ly + 1 + dy) * kHX + (lx + 1 + dx)]; };
+            const R tc = at(0, 0, 0);
+            R gt[3] = {R(0), R(0), R(0)}, lap = R(0);
+#pragma unroll
+            for (int i = 1; i < 27; ++i) {
+                const int ex = vel27(i, 0), ey = vel27(i, 1), ez = vel27(i, 2);
+                const R w = R(weight<27>(i));
+                R tv;
+                if ((ey < 0 && below) || (ey > 0 && above)) {
+                    const double *tw = ey < 0 ? a.twb : a.twt;
+                    const uint32_t col = (uint32_t)wrap(x + ex, g.nx) + (uint32_t)wrap(z + ez, g.nz) * (uint32_t)g.nx;
+                    tv = R(2) * R(tw[col]) - at(ex, 0, ez);
+                } else {
+                    tv = at(ex, ey, ez);
+                }
+                if (ex) gt[0] += R(ex) * w * tv;
+                if (ey) gt[1] += R(ey) * w * tv;
+                if (ez) gt[2] += R(ez) * w * tv;
+                lap += w * tv;
+            }
+            lap = R(6) * (lap - R(1.0 - weight<27>(0)) * tc);
+            const uint32_t c = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * (uint32_t)g.plane;
+            rk_tail<S, R, GK, HQ>(a, c, gt, lap);
+        }
+        __syncthreads(); // the next plane's fill overwrites the slot of plane z - 1
+    }
 }
 
 template <typename S, typename R>
@@ -153,11 +186,12 @@ void launch_rk_coef(const RkArgs &a, hipStream_t s)
 template <typename S, typename R>
 void launch_rk(const RkArgs &a, hipStream_t s)
 {
-    const Tiling t = make_tiling(a.geo);
-    if (a.gk && a.hq) hipLaunchKernelGGL((k_rk_stage<S, R, true, true>), tiling_grid(t), tiling_block(), 0, s, a, t);
-    else if (a.gk) hipLaunchKernelGGL((k_rk_stage<S, R, true, false>), tiling_grid(t), tiling_block(), 0, s, a, t);
-    else if (a.hq) hipLaunchKernelGGL((k_rk_stage<S, R, false, true>), tiling_grid(t), tiling_block(), 0, s, a, t);
-    else hipLaunchKernelGGL((k_rk_stage<S, R, false, false>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    const March m = make_march(a.geo);
+    const dim3 gr = march_grid(m), bl = tiling_block();
+    if (a.gk && a.hq) hipLaunchKernelGGL((k_rk_stage<S, R, true, true>), gr, bl, 0, s, a, m);
+    else if (a.gk) hipLaunchKernelGGL((k_rk_stage<S, R, true, false>), gr, bl, 0, s, a, m);
+    else if (a.hq) hipLaunchKernelGGL((k_rk_stage<S, R, false, true>), gr, bl, 0, s, a, m);
+    else hipLaunchKernelGGL((k_rk_stage<S, R, false, false>), gr, bl, 0, s, a, m);
 }
 
 #define TCP_THERMAL_INST(Q)                                                                                  \

@@ -268,6 +268,68 @@ inline Tiling make_tiling(const Geometry &g)
 inline dim3 tiling_grid(const Tiling &t) { return dim3((unsigned)(t.per_xcd * kXCD), 1, 1); }
 inline dim3 tiling_block() { return dim3(kTX, kTY, 1); }
 
+// Tiling of the kernels that march a 64 x 4 tile up a column of kMarchZ
+// planes, staging each plane of their stencil field with a one-cell halo in x
+// and y in LDS (three planes held at a time): each input is read from memory
+// about (66 x 6) / (64 x 4) = 1.55 times and the stencil comes from LDS.
+// Tiles are ordered x fastest, then y, then the column, XCD-aware as above.
+constexpr int kMarchZ = 16;
+constexpr int kHX = kTX + 2, kHY = kTY + 2;
+constexpr int kHalo = kHX * kHY; // 396 cells per staged plane
+
+struct March {
+    int tiles_x, tiles_y, chunks_z;
+    int total, per_xcd;
+};
+
+inline March make_march(const Geometry &g)
+{
+    March m;
+    m.tiles_x = (g.nx + kTX - 1) / kTX;
+    m.tiles_y = (g.ny + kTY - 1) / kTY;
+    m.chunks_z = (g.nz + kMarchZ - 1) / kMarchZ;
+    m.total = m.tiles_x * m.tiles_y * m.chunks_z;
+    m.per_xcd = (m.total + kXCD - 1) / kXCD;
+    return m;
+}
+
+inline dim3 march_grid(const March &m) { return dim3((unsigned)(m.per_xcd * kXCD), 1, 1); }
+
+__host__ __device__ __forceinline__ int wrap(int v, int n)
+{
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+// origin of this work-group's tile and the end of its column; false for a
+// padding work-group (uniform across the work-group: it reaches no barrier)
+__device__ __forceinline__ bool march_tile(const March &m, const Geometry &g, int &x0, int &y0, int &z0, int &z1)
+{
+    const int w = blockIdx.x;
+    const int L = (w % kXCD) * m.per_xcd + w / kXCD;
+    if (L >= m.total) return false;
+    const int r = L / m.tiles_x;
+    x0 = (L % m.tiles_x) * kTX;
+    y0 = (r % m.tiles_y) * kTY;
+    z0 = (r / m.tiles_y) * kMarchZ;
+    z1 = z0 + kMarchZ < g.nz ? z0 + kMarchZ : g.nz;
+    return true;
+}
+
+// cell index of halo entry i of the plane zz staged by the tile at (x0, y0);
+// false for halo rows beyond a wall (never read)
+__device__ __forceinline__ bool halo_cell(const Geometry &g, int x0, int y0, int zz, int i, uint32_t &c)
+{
+    const int gx = wrap(x0 - 1 + i % kHX, g.nx);
+    int gy = y0 - 1 + i / kHX;
+    if (gy < 0 || gy >= g.ny) {
+        if (g.walls) return false;
+        gy = wrap(gy, g.ny);
+    }
+    c = (uint32_t)gx + (uint32_t)gy * (uint32_t)g.nx + (uint32_t)zz * (uint32_t)g.plane;
+    return true;
+}
+
 // Cell of this thread; false for padding work-groups and cells outside the grid.
 // A wavefront is one x-row of a tile (64 threads with the same threadIdx.y), so
 // y and z are wave-uniform; y is read through readfirstlane to tell the compiler.
