@@ -78,8 +78,8 @@ enum { TCP_FP64 = 0, TCP_FP32 = 1, TCP_FP16 = 2 };
  * the phase-field, hydrodynamic and thermal LB kernels, an RK stage, the
  * fused step (all three LB updates of a step in one kernel, see
  * tcp_set_fusion), one update of the thermal adjoint (tcp_thermal_adjoint)
- * and one reverse step of the coupled adjoint (tcp_tape_adjoint: its three
- * kernels together). */
+ * and one reverse step of the coupled adjoint (tcp_tape_adjoint: its one or
+ * two kernels together). */
 enum {
     TCP_K_PHASE = 0,
     TCP_K_HYDRO = 1,
@@ -232,7 +232,7 @@ int tcp_warm_temperature(tcp_domain *d, int64_t max_steps, double tol, int64_t c
  * the three outputs are host arrays or NULL to skip.  One adjoint kernel per
  * LB update or RK stage, last to first, in the storage precision of the
  * domain with FP64 accumulation of the gradients; the workspace (LB: two
- * link-adjoint arrays of the thermal PDF size; RK: thirteen fields; and two FP64
+ * link-adjoint arrays of the thermal PDF size; RK: eight fields; and two FP64
  * fields) is allocated on the first call and kept.  Synchronises. */
 int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, double *dL_dsource,
                         double *dL_dTw_bot, double *dL_dTw_top);
@@ -246,10 +246,13 @@ int tcp_thermal_adjoint(tcp_domain *d, int64_t nsteps, const double *dL_dT, doub
  * of the last segment, and the heat sources and wall temperatures in force.
  * The reverse sweep recomputes the inner states of every other segment from
  * its checkpoint; segment = 1 stores every state and recomputes nothing.
- * Replaces any earlier tape; the device memory (nseg + segment states of the
- * domain's state size plus the reverse sweep's workspace, about 2.2 states)
- * is allocated through the domain's allocator on the first call and again
- * when the sizes change (TCP_ERR_OOM if it does not fit).  Thermal LB only
+ * Replaces any earlier tape; the device memory (nseg + 1 checkpoints and two
+ * rings of segment - 1 states of the domain's state size, so that the reverse
+ * sweep can recompute one segment on a second stream while it undoes the
+ * next, plus the reverse sweep's workspace, about 2.3 states; one ring, and
+ * no overlap, when two do not fit) is allocated through the domain's
+ * allocator on the first call and again when the sizes change (TCP_ERR_OOM
+ * if not even one ring fits).  Thermal LB only
  * (TCP_ERR_UNSUPPORTED for RK).  Asynchronous.  TCP_ERR_ARG for nsteps < 1,
  * TCP_ERR_STATE before tcp_initialize. */
 int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment);
@@ -266,10 +269,12 @@ int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment);
  * source) and dL/dT_w of every column of the bottom and top walls (nx*nz
  * values each, x fastest); each output may be NULL.  Segments are undone
  * last to first, each recomputed from its checkpoint unless its states are
- * at hand, then step by step with one reverse kernel per step (the thermal,
- * hydrodynamic and phase-field updates of a cell in turn: recompute of the
- * cell's update and its vector-Jacobian product, with link and stencil
- * adjoints gathered from the neighbours); arithmetic in the
+ * at hand (with two rings, on a second stream of default priority while the
+ * previous segment is undone), then step by step with one reverse kernel per
+ * step (two in FP32: the thermal and hydrodynamic updates, then the
+ * phase-field update; for each, the recompute of the cell's update and its
+ * vector-Jacobian product, with link and stencil adjoints gathered from the
+ * neighbours); arithmetic in the
  * domain's precision (FP32 for FP16 PDFs), gradient sums in FP64.  The
  * domain's current state is not touched.  Synchronises.  TCP_ERR_STATE
  * without a tape; TCP_ERR_ARG for a missing or non-finite dL_dcentroid. */

@@ -29,7 +29,8 @@
 //      sphi of step n (R2's stencil adjoints plus K1's gradient adjoint).
 // Every gather reads values the neighbours wrote in the previous reverse
 // step (the src buffers), so there are no atomics, the result does not
-// depend on scheduling, and the three phases can run in one kernel.
+// depend on scheduling, and the three phases can run in one kernel (FP64) or
+// in two, R3 and R2 then R1, each needing fewer registers (FP32).
 #include "adjoint_math.hpp"
 #include "kernels.hpp"
 
