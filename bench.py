@@ -399,6 +399,9 @@ def main() -> int:
     ap.add_argument("--oracle-box", type=int, default=64)
     ap.add_argument("--oracle-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true", help="only run the copy kernel")
+    ap.add_argument("--placement", type=int, default=0,
+                    help="only create this many FP32 blocks in turn (each freed before the next) and print "
+                         "the step kernel's time on each (spread between physical placements)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the single-GPU block is the unit it "
@@ -406,6 +409,13 @@ def main() -> int:
         return 2
     if args.copy_calibration:
         copy_calibration()
+        return 0
+    if args.placement > 0:
+        from paper_2401_03041_amd import workloads as W
+        cfg = W.droplet_block(n=args.n, precision="fp32")
+        for k in range(args.placement):
+            res = run_gpu(cfg, 6, 2, "fp32")
+            print(json.dumps({"domain": k, "step_ms": round(res["kernels"]["step"]["avg_ms"], 3)}), flush=True)
         return 0
 
     from paper_2401_03041_amd import tcplb
