@@ -783,8 +783,10 @@ int ensure_tape(tcp_domain *d, int64_t nseg, int64_t seg)
     size_t wtotal = 0;
     for (size_t w : work) wtotal += round256(w);
     // a second ring when there is more than one segment to recompute and it
-    // fits; otherwise one ring and no overlap
+    // fits; otherwise one ring and no overlap (an allocation already made for
+    // one ring of these sizes is kept rather than tried again with two)
     int nrings = nseg > 1 && nring > 0 ? 2 : 1;
+    if (nrings == 2 && tp.mem && tp.mem_bytes == (nckpt + nring) * slot + wtotal) nrings = 1;
     for (; nrings >= 1; --nrings) {
         const size_t total = (nckpt + nrings * nring) * slot + wtotal;
         if (tp.mem && tp.mem_bytes == total) break;
