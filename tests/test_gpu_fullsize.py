@@ -79,3 +79,62 @@ def test_droplet_block_512_sampled_against_oracle(precision, tol):
     g.close()
     del gpu
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("thermal", ["lb", "rk4"])
+def test_paper_block_sampled_against_oracle(thermal):
+    """The paper's per-GPU benchmark shape as bench.py's paper_block runs it:
+    512 x 256 x 256 capture channel (walls in y, moving lid, heater of width 32
+    on the bottom wall, hemisphere of radius 24), D3Q27 phase field and
+    hydrodynamics, FP64, with the fused thermal LB step or the RK4 stages.
+    One LB step couples a cell to its neighbours; one RK4 step to cells four
+    away (four stages, each a 27-point stencil).  After 3 steps, patches
+    spanning the whole channel height (so both walls are exact) and, in x and
+    z, the 7 compared cells plus 3 (LB) or 12 (RK4) on each side, built by the
+    oracle from the same inputs in global coordinates, must match within 1e-11
+    of each field's magnitude."""
+    import torch
+
+    from paper_2401_03041_amd import tcplb
+    nx, ny, nz = 512, 256, 256
+    cfg = dict(W.capture(shape=(nx, ny, nz), precision="fp64"), q_pf=27, thermal=thermal, q_thermal=7,
+               kappa_h=0.2, kappa_l=0.2)
+    g = tcplb.domain_from_workload(cfg)
+    g.step(STEPS)
+    names = ("phi", "ux", "uy", "uz", "p", "T")
+    gpu = {}
+    for k in names:
+        t = torch.empty((nz, ny, nx), dtype=torch.float64, device="cuda")
+        g.get_field(k, out=t)
+        gpu[k] = t
+    torch.cuda.synchronize()
+    scale = {k: float(gpu[k].abs().max()) for k in names}
+    (dx, dy, dz, r), = cfg["droplets"]
+    (q, hx, hy, hz, w, dc), = cfg["heat_sources"]
+    # droplet interface along x and along z, heater centre, periodic corner
+    centres = [(int(dx + r), int(dz)), (int(dx), int(dz + r)), (int(hx), int(hz)), (0, nz - 1)]
+    inner = 3
+    half = inner + (4 if thermal == "rk4" else 1) * STEPS
+    side = 2 * half + 1
+    worst = {k: 0.0 for k in names}
+    for (cx, cz) in centres:
+        ox, oz = cx - half, cz - half
+        o = O.OracleDomain(dict(cfg, shape=(side, ny, side)))
+        o.set_droplets(cfg["droplets"], gdim=(nx, ny, nz), origin=(ox, 0, oz), periodic=(1, 0, 1))
+        o.set_field("T", np.zeros((side, ny, side)))
+        o.set_heat_sources([(q, hx - ox, hy, hz - oz, w, dc)])
+        o.initialize()
+        o.step(STEPS)
+        sl = slice(half - inner, half + inner + 1)
+        iz, ix = (torch.as_tensor(np.arange(c - inner, c + inner + 1) % n, device="cuda")
+                  for c, n in ((cz, nz), (cx, nx)))
+        for k in names:
+            ref = o.get_field(k)[sl, :, sl]
+            got = gpu[k].index_select(0, iz).index_select(2, ix).cpu().numpy()
+            worst[k] = max(worst[k], float(np.max(np.abs(got - ref))) / max(scale[k], 1e-300))
+        o.close()
+    print(thermal, "worst relative errors", worst, "scales", scale, flush=True)
+    for k in names:
+        assert worst[k] < 1e-11, (k, worst[k])
+    g.close()
+    del gpu
