@@ -221,32 +221,36 @@ def test_per_cell_loss_term():
         assert np.max(np.abs(u - v)) <= 1e-12 * max(np.max(np.abs(u)), 1e-300)
 
 
-def test_design_channel_fp32_matches_fp64():
+@pytest.mark.parametrize("prec,c_tol,g_tol", [("fp32", 1e-5, 1e-4), ("fp16", 1e-3, 1e-3)])
+def test_design_channel_matches_fp64(prec, c_tol, g_tol):
     """The 96 x 64 x 64 design channel over 2000 steps (checkpoints every 45
-    steps): FP32 forward and reverse against FP64 on the same GPU."""
+    steps): FP32, or FP16 phase-field and thermal PDFs, forward and reverse
+    against FP64 on the same GPU.  FP32: the centroid within 1e-5 cells, the
+    gradients within the design target 1e-4.  FP16 PDFs: within the FP16
+    storage bar 1e-3, relative to the centroid and to each gradient
+    (measured 4e-5 and 4e-4)."""
     out = {}
-    for prec in ("fp64", "fp32"):
-        cfg = W.capture_design(precision=prec)
-        nx, ny, nz = cfg["shape"]
-        src = [list(s) for s in cfg["heat_sources"]]
+    for p in ("fp64", prec):
+        cfg = W.capture_design(precision=p)
         d = gpu_domain(cfg)
         c0 = d.reduce()[1]
         target = np.array([44.0, c0[1], c0[2]])
         d.step_taped(2000)
         c = d.reduce()[1]
-        out[prec] = (c, d.tape_adjoint(2.0 * (c - target)))
+        out[p] = (c, d.tape_adjoint(2.0 * (c - target)))
         d.close()
     c64, (s64, b64, t64) = out["fp64"]
-    c32, (s32, b32, t32) = out["fp32"]
-    print("centroid", c64, c32, "dsrc", s64, s32, flush=True)
-    assert np.max(np.abs(c32 - c64)) <= 1e-5
+    cp, (sp, bp, tp) = out[prec]
+    print("centroid", c64, cp, "dsrc", s64, sp, flush=True)
+    c_err = np.max(np.abs(cp - c64))
+    assert c_err <= (c_tol if prec == "fp32" else c_tol * np.max(np.abs(c64)))
     # Q, x, y, z of the heater; z is ~1e-10 by the mirror symmetry of the set-up
     # in z, so each is held to the scale of the largest
     scale = np.max(np.abs(s64)) / 100.0
     for j in range(4):
-        assert abs(s32[0, j] - s64[0, j]) <= 1e-4 * max(abs(s64[0, j]), scale), j
-    assert np.max(np.abs(b32 - b64)) <= 1e-4 * np.max(np.abs(b64))
-    assert np.max(np.abs(t32 - t64)) <= 1e-4 * np.max(np.abs(t64))
+        assert abs(sp[0, j] - s64[0, j]) <= g_tol * max(abs(s64[0, j]), scale), j
+    assert np.max(np.abs(bp - b64)) <= g_tol * np.max(np.abs(b64))
+    assert np.max(np.abs(tp - t64)) <= g_tol * np.max(np.abs(t64))
 
 
 def test_torch_function_two_forwards_then_backward():

@@ -81,16 +81,17 @@ def test_droplet_block_512_sampled_against_oracle(precision, tol):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("thermal", ["lb", "rk4"])
+@pytest.mark.parametrize("thermal", ["lb", "rk2", "rk4"])
 def test_paper_block_sampled_against_oracle(thermal):
     """The paper's per-GPU benchmark shape as bench.py's paper_block runs it:
     512 x 256 x 256 capture channel (walls in y, moving lid, heater of width 32
     on the bottom wall, hemisphere of radius 24), D3Q27 phase field and
-    hydrodynamics, FP64, with the fused thermal LB step or the RK4 stages.
-    One LB step couples a cell to its neighbours; one RK4 step to cells four
-    away (four stages, each a 27-point stencil).  After 3 steps, patches
-    spanning the whole channel height (so both walls are exact) and, in x and
-    z, the 7 compared cells plus 3 (LB) or 12 (RK4) on each side, built by the
+    hydrodynamics, FP64, with the fused thermal LB step or the RK2 / RK4
+    stages.  One LB step couples a cell to its neighbours; one RK step to cells
+    as far away as it has stages (each a 27-point stencil).  After 3 steps,
+    patches spanning the whole channel height (so both walls are exact) and,
+    in x and z, the 7 compared cells plus 3 (LB), 6 (RK2) or 12 (RK4) on each
+    side, built by the
     oracle from the same inputs in global coordinates, must match within 1e-11
     of each field's magnitude."""
     import torch
@@ -114,7 +115,7 @@ def test_paper_block_sampled_against_oracle(thermal):
     # droplet interface along x and along z, heater centre, periodic corner
     centres = [(int(dx + r), int(dz)), (int(dx), int(dz + r)), (int(hx), int(hz)), (0, nz - 1)]
     inner = 3
-    half = inner + (4 if thermal == "rk4" else 1) * STEPS
+    half = inner + {"lb": 1, "rk2": 2, "rk4": 4}[thermal] * STEPS
     side = 2 * half + 1
     worst = {k: 0.0 for k in names}
     for (cx, cz) in centres:
