@@ -263,3 +263,29 @@ def test_adjoint_gradient_step_moves_heater_towards_target():
     x = float(src.detach()[0, 1])
     print("heater x", x, "loss", float(loss.detach()))
     assert abs(x - 20.0) < 0.25
+
+
+@pytest.mark.parametrize("thermal", ["lb", "rk4"])
+def test_thermal_adjoint_full_size(thermal):
+    """The 512^3 droplet block in FP32, as bench.py's thermal-adjoint legs run it,
+    with a heater of width 32 at its centre: after 10 updates the adjoint's
+    dL/dQ for random loss weights equals the loss of the GPU's own warm-up at
+    unit amplitude from T = 0 (the map is linear) within the FP32 bar 1e-5."""
+    import torch
+
+    n = 512
+    cfg = dict(W.droplet_block(n=n, precision="fp32"), thermal=thermal,
+               heat_sources=[(1.0, 256.0, 256.0, 256.0, 32.0, 0.0)])
+    m = np.random.default_rng(5).uniform(0.0, 1.0, (n, n, n))
+    g = gpu_domain(cfg)
+    dq, _, _ = g.thermal_adjoint(10, m)
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    f = gpu_domain(cfg, T=np.zeros((n, n, n)))
+    f.warm_temperature(10, 0.0, 11)
+    loss = float(np.sum(m * f.get_field("T")))
+    f.close()
+    print(thermal, "dL/dQ", dq[0, 0], "loss at unit amplitude", loss, flush=True)
+    assert loss > 1e5  # the heater adds (pi w^2 / 2)^(3/2) = 6.4e4 to sum T per update
+    assert abs(dq[0, 0] - loss) <= 1e-5 * abs(loss)
