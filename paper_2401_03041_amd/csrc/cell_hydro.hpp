@@ -29,7 +29,8 @@ namespace tcp {
 // values the thermal pull needs with deviation storage).
 template <typename S, typename R, bool WALL, bool GIVEN = false, int QT = 0>
 __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R (&u)[3],
-                                           const PhiStencil<R> &given = PhiStencil<R>{}, R *tsrc = nullptr)
+                                           const PhiStencil<R> &given = PhiStencil<R>{}, R *tsrc = nullptr,
+                                           const Staged<R> *stagedT = nullptr)
 {
     const S *gs = static_cast<const S *>(a.g_src);
     const PdfLanes<27> pl(nb);
@@ -88,7 +89,8 @@ __device__ __forceinline__ void hydro_cell(const HydroArgs &a, const Nbr &nb, R 
         phi_stencil(pn, sten);
     }
     R tn[27];
-    nb.stencil27(tp, tn);
+    if (stagedT) stagedT->stencil27(tn); // T^n staged in LDS by the fused step
+    else nb.stencil27(tp, tn);
     const R T = tn[0];
     if constexpr (QT > 0) {
 #pragma unroll

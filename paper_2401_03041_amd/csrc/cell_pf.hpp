@@ -23,7 +23,8 @@ namespace tcp {
 // Update of one cell; returns phi^{n+1} and, in sten, phi^n at the cell with
 // its isotropic gradient and Laplacian.
 template <int Q, typename P, typename S, typename R, bool WALL>
-__device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb, PhiStencil<R> &sten)
+__device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb, PhiStencil<R> &sten,
+                                              const Staged<R> *staged = nullptr)
 {
     constexpr bool dev = deviation_storage<P>();
     const P *hs = static_cast<const P *>(a.h_src);
@@ -35,7 +36,8 @@ __device__ __forceinline__ R phase_field_cell(const PfArgs &a, const Nbr &nb, Ph
     const S *po = static_cast<const S *>(a.phi_old);
     __builtin_amdgcn_s_setprio(kPullPriority);
     R pn[27];
-    nb.stencil27(po, pn);
+    if (staged) staged->stencil27(pn); // phi^n staged in LDS by the fused step
+    else nb.stencil27(po, pn);
 #pragma unroll
     for (int k = 0; k < 27; ++k)
         if (WALL && nb.ghost(vel27(k, 1))) pn[k] = nb.phi_ghost(pn[k], vel27(k, 1), a.wet);

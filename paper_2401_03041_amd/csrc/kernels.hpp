@@ -90,6 +90,27 @@ struct PhiStencil {
     R phi, gp[3], lap;
 };
 
+// A field staged in LDS for a work-group's 64 x 4 tile with a one-cell halo in
+// x and y, three planes (z - 1, z, z + 1; kHalo values each): the FP64 fused
+// step stages phi^n and T^n so that their 27-point stencils come from LDS.
+template <typename R>
+struct Staged {
+    const R *pl[3]; // planes z - 1, z, z + 1
+    int o;          // the thread's cell within a plane: (ly + 1) kHX + lx + 1
+    bool below, above;
+    // the 3x3x3 neighbourhood in D3Q27 order, rows beyond a wall replaced by
+    // the own row (as Nbr::stencil27 reads them)
+    __device__ __forceinline__ void stencil27(R (&v)[27]) const
+    {
+#pragma unroll
+        for (int k = 0; k < 27; ++k) {
+            int dy = vel27(k, 1);
+            if ((dy < 0 && below) || (dy > 0 && above)) dy = 0;
+            v[k] = pl[vel27(k, 2) + 1][o + dy * kHX + vel27(k, 0)];
+        }
+    }
+};
+
 // pn: phi^n on the 27-point neighbourhood in D3Q27 order (ghosts applied)
 template <typename R>
 __device__ __forceinline__ void phi_stencil(const R (&pn)[27], PhiStencil<R> &s)

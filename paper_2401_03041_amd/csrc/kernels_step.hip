@@ -32,10 +32,11 @@ __device__ __forceinline__ Nbr opaque(const Nbr &nb)
 }
 
 template <int QH, int QF, typename P, typename S, typename R, bool WALL>
-__device__ __forceinline__ void step_cell(const StepArgs &a, const Nbr &nb, int x, int y, int z)
+__device__ __forceinline__ void step_cell(const StepArgs &a, const Nbr &nb, int x, int y, int z,
+                                          const Staged<R> *sphi = nullptr, const Staged<R> *sT = nullptr)
 {
     PhiStencil<R> ps;
-    const R phi_new = phase_field_cell<QH, P, S, R, WALL>(a.pf, opaque(nb), ps);
+    const R phi_new = phase_field_cell<QH, P, S, R, WALL>(a.pf, opaque(nb), ps, sphi);
     // keep the phases apart: hoisting one phase's loads into the previous one
     // holds both phases' PDFs in registers at once and costs occupancy
     __builtin_amdgcn_sched_barrier(0);
@@ -44,7 +45,7 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, const Nbr &nb, int 
     // hydrodynamic update has it from its T^n stencil
     constexpr bool dev = deviation_storage<P>();
     R tsrc[QF];
-    hydro_cell<S, R, WALL, true, dev ? QF : 0>(a.hy, opaque(nb), u, ps, tsrc);
+    hydro_cell<S, R, WALL, true, dev ? QF : 0>(a.hy, opaque(nb), u, ps, tsrc, sT);
     __builtin_amdgcn_sched_barrier(0);
     thermal_cell<QF, P, S, R, WALL, dev>(a.th, opaque(nb), x, y, z, phi_new, u, tsrc);
 }
@@ -55,13 +56,50 @@ template <int QH, int QF, typename P, typename S, typename R>
 __global__ void __launch_bounds__(kTX *kTY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 3 : 1)))
 k_step(const StepArgs a, const Tiling t)
 {
-    int x, y, z;
-    if (!cell_of_thread(t, a.pf.geo, x, y, z)) return;
-    const Nbr nb(a.pf.geo, x, y, z);
-    if (nb.below || nb.above)
-        step_cell<QH, QF, P, S, R, true>(a, nb, x, y, z);
-    else
-        step_cell<QH, QF, P, S, R, false>(a, nb, x, y, z);
+    if constexpr (sizeof(R) == 8) {
+        // FP64: the work-group first stages phi^n and T^n of its tile, a
+        // one-cell halo in x and y and the planes z - 1, z, z + 1 in LDS, so that
+        // the 27-point stencils of K1 and K2 read LDS instead of memory
+        __shared__ R lphi[3][kHalo], lT[3][kHalo];
+        const Geometry &g = a.pf.geo;
+        int x0, y0, z;
+        if (!tile_of_block(t, g, x0, y0, z)) return;
+        const int lx = threadIdx.x, ly = __builtin_amdgcn_readfirstlane((int)threadIdx.y);
+        {
+            const S *po = static_cast<const S *>(a.pf.phi_old);
+            const S *to = static_cast<const S *>(a.hy.T);
+            const int tid = lx + kTX * ly;
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const int zz = wrap(z - 1 + p, g.nz);
+                for (int i = tid; i < kHalo; i += kTX * kTY) {
+                    uint32_t c;
+                    const bool in = halo_cell(g, x0, y0, zz, i, c);
+                    lphi[p][i] = in ? ld<R>(elem(po, c)) : R(0);
+                    lT[p][i] = in ? ld<R>(elem(to, c)) : R(0);
+                }
+            }
+        }
+        __syncthreads();
+        const int x = x0 + lx, y = y0 + ly;
+        if (x >= g.nx || y >= g.ny) return;
+        const Nbr nb(g, x, y, z);
+        const int o = (ly + 1) * kHX + lx + 1;
+        const Staged<R> sphi{{lphi[0], lphi[1], lphi[2]}, o, nb.below, nb.above};
+        const Staged<R> sT{{lT[0], lT[1], lT[2]}, o, nb.below, nb.above};
+        if (nb.below || nb.above)
+            step_cell<QH, QF, P, S, R, true>(a, nb, x, y, z, &sphi, &sT);
+        else
+            step_cell<QH, QF, P, S, R, false>(a, nb, x, y, z, &sphi, &sT);
+    } else {
+        int x, y, z;
+        if (!cell_of_thread(t, a.pf.geo, x, y, z)) return;
+        const Nbr nb(a.pf.geo, x, y, z);
+        if (nb.below || nb.above)
+            step_cell<QH, QF, P, S, R, true>(a, nb, x, y, z);
+        else
+            step_cell<QH, QF, P, S, R, false>(a, nb, x, y, z);
+    }
 }
 
 template <int QH, int QF, typename P, typename S, typename R>

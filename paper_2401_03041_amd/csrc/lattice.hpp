@@ -330,6 +330,23 @@ __device__ __forceinline__ bool halo_cell(const Geometry &g, int x0, int y0, int
     return true;
 }
 
+// Tile of this work-group in the mapping of cell_of_thread: origin (x0, y0)
+// and plane z; false for a padding work-group or a plane beyond the grid
+// (both uniform across the work-group).
+__device__ __forceinline__ bool tile_of_block(const Tiling &t, const Geometry &g, int &x0, int &y0, int &z)
+{
+    const int w = blockIdx.x;
+    const int L = (w % kXCD) * t.per_xcd + w / kXCD;
+    if (L >= t.total) return false;
+    const int zz = L % kTZ;
+    int r = L / kTZ;
+    x0 = (r % t.tiles_x) * kTX;
+    r /= t.tiles_x;
+    y0 = (r % t.tiles_y) * kTY;
+    z = (r / t.tiles_y) * kTZ + zz;
+    return z < g.nz;
+}
+
 // Cell of this thread; false for padding work-groups and cells outside the grid.
 // A wavefront is one x-row of a tile (64 threads with the same threadIdx.y), so
 // y and z are wave-uniform; y is read through readfirstlane to tell the compiler.
