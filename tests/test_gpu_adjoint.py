@@ -110,11 +110,13 @@ def test_thermal_adjoint_matches_oracle_gradient(precision, q, thermal):
 
 
 @pytest.mark.parametrize("thermal,shape,periodic", [("lb", (12, 10, 6), True), ("rk4", (12, 10, 6), True),
-                                                    ("lb", (8, 2, 4), False), ("rk2", (8, 2, 4), False)])
+                                                    ("lb", (8, 2, 4), False), ("rk2", (8, 2, 4), False),
+                                                    ("rk4", (9, 7, 1), False)])
 def test_thermal_adjoint_periodic_and_two_rows(thermal, shape, periodic):
-    """Periodic y (no wall gradients: exactly zero) and a two-row channel, the
-    smallest with walls (every cell next to a wall), FP64, against the oracle's
-    unit-input gradients."""
+    """Periodic y (no wall gradients: exactly zero), a two-row channel, the
+    smallest with walls (every cell next to a wall), and a channel one plane
+    thick (z wraps onto itself), FP64, against the oracle's unit-input
+    gradients."""
     steps = 20
     cfg, phi, u, m = _case(7, "fp64", thermal, *shape, periodic_y=periodic)
     g = gpu_domain(cfg, phi=phi, u=u)

@@ -92,16 +92,19 @@ def test_post_collision_pdfs(q_pf, q_th, precision):
         assert err < tol, (which, err)
 
 
-def test_degenerate_shapes_fp64():
-    """Single-cell-thick boxes (x and z wrap onto themselves) and a two-row channel.
-    Components that vanish by symmetry are compared against the 1e-6 velocity scale
-    of the forcing instead of their own (round-off sized) maximum."""
+@pytest.mark.parametrize("thermal", ["lb", "rk2", "rk4"])
+def test_degenerate_shapes_fp64(thermal):
+    """Single-cell-thick boxes (x and z wrap onto themselves) and a two-row channel,
+    with the thermal LB or the RK stages (whose tiles then hold one or two valid
+    rows and whose plane columns wrap onto one plane).  Components that vanish by
+    symmetry are compared against the 1e-6 velocity scale of the forcing instead
+    of their own (round-off sized) maximum."""
     for shape, walls in (((1, 24, 1), True), ((33, 1, 1), False), ((1, 2, 1), True), ((5, 1, 3), False)):
         ny = shape[1]
         y = np.arange(ny, dtype=np.float64)
         phi = (0.5 + 0.5 * np.tanh(2 * (y - ny / 2 + 0.5) / 3.0))[None, :, None] * np.ones(shape[::-1])
         cfg = W.make(shape=shape, periodic_y=not walls, rho_l=0.5, sigma_ref=1e-3, sigma_t=1e-4, xi=3.0,
-                     u_wall_top=(0.01, 0, 0), g=(1e-6, -1e-6, 0), t_wall_bot=1.0,
+                     u_wall_top=(0.01, 0, 0), g=(1e-6, -1e-6, 0), t_wall_bot=1.0, thermal=thermal,
                      t_init={"kind": "uniform", "value": 0.3})
         g, o = _run_pair(cfg, 25, phi=phi)
         errs = compare(g, o, floor=1e-6)
