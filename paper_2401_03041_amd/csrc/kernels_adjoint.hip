@@ -239,32 +239,9 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_coeff(const RkAdjointArgs a
 // acc (which starts from lambda' in the last stage) and collects the source
 // and wall gradients of the stage.
 
-// packed sources of plane zz (already wrapped) into LDS slot `slot`; halo rows
-// beyond a wall are never gathered from and hold zeros
-template <typename S, typename R>
-__device__ __forceinline__ void rk_adj_fill(const RkAdjointArgs &a, R (*lds)[4][kHalo], int slot, int x0, int y0,
-                                            int zz, int tid)
-{
-    const Geometry &g = a.geo;
-    const uint32_t N = (uint32_t)g.N;
-    const S *lam = static_cast<const S *>(a.lam);
-    const S *thi = static_cast<const S *>(a.theta_in);
-    const S *co = static_cast<const S *>(a.coeff);
-    for (int i = tid; i < kHalo; i += kTX * kTY) {
-        R b[4] = {R(0), R(0), R(0), R(0)};
-        uint32_t c;
-        if (halo_cell(g, x0, y0, zz, i, c)) {
-            R k = R(a.w_s) * ld<R>(elem(lam, c));
-            if (thi) k += R(a.a_s) * ld<R>(elem(thi, c));
-#pragma unroll
-            for (int j = 0; j < 3; ++j) b[j] = R(3) * k * ld<R>(elem(co + j * N, c));
-            b[3] = R(6) * k * ld<R>(elem(co + 3 * N, c));
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) lds[slot][j][i] = b[j];
-    }
-}
-
+// The loads run one plane ahead, as in the forward stage: while plane z is
+// gathered, the inputs of plane z + 2's packed sources (for the LDS) and the
+// own-cell values of plane z + 1 are already in flight into registers.
 template <typename S, typename R>
 __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_march(const RkAdjointArgs a, const March m)
 {
@@ -279,15 +256,65 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_march(const RkAdjointArgs a
     const bool below = g.walls && y == 0, above = g.walls && y == g.ny - 1;
     const S *lam = static_cast<const S *>(a.lam);
     const S *thi = static_cast<const S *>(a.theta_in);
+    const S *co = static_cast<const S *>(a.coeff);
+    const uint32_t N = (uint32_t)g.N, plane = (uint32_t)g.plane;
+    const uint32_t c0 = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx; // own cell within a plane
+    const HaloSlots hs(g, x0, y0, tid);
 
-    rk_adj_fill<S, R>(a, lds, 0, x0, y0, wrap(z0 - 1, g.nz), tid);
-    rk_adj_fill<S, R>(a, lds, 1, x0, y0, z0, tid);
+    // inputs of the packed sources of the staged entries: lambda', theta_in, a, kappa
+    R pl[kHaloPer], pt[kHaloPer], pc[kHaloPer][4];
+    auto load = [&](int zz) {
+#pragma unroll
+        for (int j = 0; j < kHaloPer; ++j) {
+            const uint32_t c = hs.off[j] + (uint32_t)zz * plane;
+            pl[j] = hs.in[j] ? ld<R>(elem(lam, c)) : R(0);
+            pt[j] = hs.in[j] && thi ? ld<R>(elem(thi, c)) : R(0);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) pc[j][q] = hs.in[j] ? ld<R>(elem(co + q * N, c)) : R(0);
+        }
+    };
+    // packed sources kappa = w_s lambda' + a_s theta_in, B = 3 kappa a,
+    // D = 6 kappa kappa(phi); entries in rows beyond a wall are never gathered
+    // from and hold zeros
+    auto put = [&](int slot) {
+#pragma unroll
+        for (int j = 0; j < kHaloPer; ++j) {
+            if (!hs.own[j]) continue;
+            R k = R(a.w_s) * pl[j];
+            if (thi) k += R(a.a_s) * pt[j];
+            const int i = tid + j * kTX * kTY;
+#pragma unroll
+            for (int q = 0; q < 3; ++q) lds[slot][q][i] = R(3) * k * pc[j][q];
+            lds[slot][3][i] = R(6) * k * pc[j][3];
+        }
+    };
+    // own-cell values: lambda', theta_in, acc
+    struct Own {
+        R l, t, acc;
+    } cur{}, ahead{};
+    auto own = [&](int zz, Own &o) {
+        const uint32_t c = c0 + (uint32_t)zz * plane;
+        o.l = ld<R>(elem(lam, c));
+        o.t = thi ? ld<R>(elem(thi, c)) : R(0);
+        o.acc = a.first ? R(0) : ld<R>(elem(static_cast<const S *>(a.acc), c));
+    };
+
+    load(wrap(z0 - 1, g.nz));
+    put(0);
+    load(z0);
+    put(1);
+    load(wrap(z0 + 1, g.nz));
+    if (live) own(z0, cur);
     for (int z = z0; z < z1; ++z) {
         const int k = z - z0;
         // slots of planes z - 1, z, z + 1
         const int sl[3] = {k % 3, (k + 1) % 3, (k + 2) % 3};
-        rk_adj_fill<S, R>(a, lds, sl[2], x0, y0, wrap(z + 1, g.nz), tid);
+        put(sl[2]); // plane z + 1, loaded one plane ago
         __syncthreads();
+        if (z + 1 < z1) {
+            load(wrap(z + 2, g.nz));
+            if (live) own(z + 1, ahead);
+        }
         if (live) {
             // LDS element of the cell at offset (dx, dy, dz), component j
             auto at = [&](int j, int dx, int dy, int dz) -> R {
@@ -318,13 +345,11 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_march(const RkAdjointArgs a
                 }
             }
             out -= refl[0] + refl[1];
-            const uint32_t c = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * (uint32_t)g.plane;
+            const uint32_t c = c0 + (uint32_t)z * plane;
             st(elem(static_cast<S *>(a.theta_out), c), out);
-            S *acc = static_cast<S *>(a.acc);
-            const R l = ld<R>(elem(lam, c));
-            st(elem(acc, c), (a.first ? l : ld<R>(elem(acc, c))) + out);
-            R kc = R(a.w_s) * l;
-            if (thi) kc += R(a.a_s) * ld<R>(elem(thi, c));
+            st(elem(static_cast<S *>(a.acc), c), (a.first ? cur.l : cur.acc) + out);
+            R kc = R(a.w_s) * cur.l;
+            if (thi) kc += R(a.a_s) * cur.t;
             a.grad_q[c] += static_cast<double>(kc);
             if (below || above) {
                 const uint32_t col = (uint32_t)x + (uint32_t)z * (uint32_t)g.nx;
@@ -332,7 +357,8 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_adj_march(const RkAdjointArgs a
                 if (above) a.grad_twt[col] += 2.0 * static_cast<double>(refl[1]);
             }
         }
-        __syncthreads(); // the next plane's fill overwrites the slot of plane z - 1
+        cur = ahead;
+        __syncthreads(); // the next plane's put overwrites the slot of plane z - 1
     }
 }
 

@@ -89,28 +89,41 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_coef(const RkArgs a, const Tili
         rk_coef_cell<S, R, false>(a, nb, x, y, z);
 }
 
-// The stage at cell c from the stencil sums of its argument theta: gt (the
-// isotropic gradient without its factor 3) and lap (the Laplacian).
+// What the stage reads at its own cell besides the stencil: a (or -u),
+// kappa, q, T^n and the accumulator.
+template <typename R>
+struct RkOwn {
+    R av[3], kap, q, T, acc;
+};
+
 template <typename S, typename R, bool GK, bool HQ>
-__device__ __forceinline__ void rk_tail(const RkArgs &a, uint32_t c, const R (&gt)[3], R lap)
+__device__ __forceinline__ void rk_own(const RkArgs &a, uint32_t c, RkOwn<R> &o)
 {
     const S *co = static_cast<const S *>(a.coef);
     const int64_t N = a.geo.N;
-    R av[3], kap;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
-        av[k] = GK ? ld<R>(elem(co + k * N, c)) : -ld<R>(elem(static_cast<const S *>(a.u[k]), c));
-    kap = GK ? ld<R>(elem(co + 3 * N, c)) : R(a.kappa_l);
-    R k = R(3) * (av[0] * gt[0] + av[1] * gt[1] + av[2] * gt[2]) + kap * lap;
-    if (HQ) k += ld<R>(elem(co + 4 * N, c));
+        o.av[k] = GK ? ld<R>(elem(co + k * N, c)) : -ld<R>(elem(static_cast<const S *>(a.u[k]), c));
+    o.kap = GK ? ld<R>(elem(co + 3 * N, c)) : R(a.kappa_l);
+    o.q = HQ ? ld<R>(elem(co + 4 * N, c)) : R(0);
+    o.T = ld<R>(elem(static_cast<const S *>(a.T), c));
+    o.acc = a.first ? R(0) : ld<R>(elem(static_cast<const S *>(a.acc), c));
+}
+
+// The stage at cell c from the stencil sums of its argument theta: gt (the
+// isotropic gradient without its factor 3) and lap (the Laplacian).
+template <typename S, typename R, bool HQ>
+__device__ __forceinline__ void rk_tail(const RkArgs &a, uint32_t c, const RkOwn<R> &o, const R (&gt)[3], R lap)
+{
+    R k = R(3) * (o.av[0] * gt[0] + o.av[1] * gt[1] + o.av[2] * gt[2]) + o.kap * lap;
+    if (HQ) k += o.q;
     S *ap = static_cast<S *>(a.acc);
-    const R T = ld<R>(elem(static_cast<const S *>(a.T), c));
-    const R acc = (a.first ? R(0) : ld<R>(elem(ap, c))) + R(a.w_acc) * k;
+    const R acc = o.acc + R(a.w_acc) * k;
     if (a.last) {
-        st(elem(static_cast<S *>(a.T_new), c), T + acc);
+        st(elem(static_cast<S *>(a.T_new), c), o.T + acc);
     } else {
         if (ap) st(elem(ap, c), acc);
-        st(elem(static_cast<S *>(a.theta_out), c), T + R(a.a_next) * k);
+        st(elem(static_cast<S *>(a.theta_out), c), o.T + R(a.a_next) * k);
     }
 }
 
@@ -118,8 +131,10 @@ __device__ __forceinline__ void rk_tail(const RkArgs &a, uint32_t c, const R (&g
 // equation): the argument theta is staged plane by plane in LDS for a 64 x 4
 // tile and its halo while the work-group marches up kMarchZ planes (three
 // planes held at a time), so its 27-point stencil costs about 1.55 loads per
-// cell instead of 27.  A neighbour across a wall is the ghost 2 T_w - theta
-// of the mirror cell in the own row.
+// cell instead of 27.  The loads run one plane ahead: while plane z is
+// computed, plane z + 2 of theta (for the LDS) and the own-cell values of
+// plane z + 1 are already in flight into registers.  A neighbour across a
+// wall is the ghost 2 T_w - theta of the mirror cell in the own row.
 template <typename S, typename R, bool GK, bool HQ>
 __global__ void __launch_bounds__(kTX *kTY) k_rk_stage(const RkArgs a, const March m)
 {
@@ -133,19 +148,36 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_stage(const RkArgs a, const Mar
     const bool live = x < g.nx && y < g.ny;
     const bool below = g.walls && y == 0, above = g.walls && y == g.ny - 1;
     const S *th = static_cast<const S *>(a.theta_in);
-    auto fill = [&](int slot, int zz) {
-        for (int i = tid; i < kHalo; i += kTX * kTY) {
-            uint32_t c;
-            lds[slot][i] = halo_cell(g, x0, y0, zz, i, c) ? ld<R>(elem(th, c)) : R(0);
-        }
+    const HaloSlots hs(g, x0, y0, tid);
+    const uint32_t plane = (uint32_t)g.plane;
+    const uint32_t c0 = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx; // own cell within a plane
+    R nxt[kHaloPer];
+    auto load = [&](int zz) {
+#pragma unroll
+        for (int j = 0; j < kHaloPer; ++j)
+            nxt[j] = hs.in[j] ? ld<R>(elem(th, hs.off[j] + (uint32_t)zz * plane)) : R(0);
     };
-    fill(0, wrap(z0 - 1, g.nz));
-    fill(1, z0);
+    auto put = [&](int slot) {
+#pragma unroll
+        for (int j = 0; j < kHaloPer; ++j)
+            if (hs.own[j]) lds[slot][tid + j * kTX * kTY] = nxt[j];
+    };
+    load(wrap(z0 - 1, g.nz));
+    put(0);
+    load(z0);
+    put(1);
+    load(wrap(z0 + 1, g.nz));
+    RkOwn<R> cur{}, ahead{};
+    if (live) rk_own<S, R, GK, HQ>(a, c0 + (uint32_t)z0 * plane, cur);
     for (int z = z0; z < z1; ++z) {
         const int k = z - z0;
         const int sl[3] = {k % 3, (k + 1) % 3, (k + 2) % 3}; // planes z - 1, z, z + 1
-        fill(sl[2], wrap(z + 1, g.nz));
+        put(sl[2]);                                          // plane z + 1, loaded one plane ago
         __syncthreads();
+        if (z + 1 < z1) {
+            load(wrap(z + 2, g.nz));
+            if (live) rk_own<S, R, GK, HQ>(a, c0 + (uint32_t)(z + 1) * plane, ahead);
+        }
         if (live) {
             auto at = [&](int dx, int dy, int dz) -> R { return lds[sl[dz + 1]][(ly + 1 + dy) * kHX + (lx + 1 + dx)]; };
             const R tc = at(0, 0, 0);
@@ -168,10 +200,10 @@ __global__ void __launch_bounds__(kTX *kTY) k_rk_stage(const RkArgs a, const Mar
                 lap += w * tv;
             }
             lap = R(6) * (lap - R(1.0 - weight<27>(0)) * tc);
-            const uint32_t c = (uint32_t)x + (uint32_t)y * (uint32_t)g.nx + (uint32_t)z * (uint32_t)g.plane;
-            rk_tail<S, R, GK, HQ>(a, c, gt, lap);
+            rk_tail<S, R, HQ>(a, c0 + (uint32_t)z * plane, cur, gt, lap);
         }
-        __syncthreads(); // the next plane's fill overwrites the slot of plane z - 1
+        cur = ahead;
+        __syncthreads(); // the next plane's put overwrites the slot of plane z - 1
     }
 }
 

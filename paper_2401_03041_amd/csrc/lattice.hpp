@@ -330,6 +330,27 @@ __device__ __forceinline__ bool halo_cell(const Geometry &g, int x0, int y0, int
     return true;
 }
 
+// The halo entries a thread stages in the marching kernels (tid and
+// tid + 256: kHalo = 396 entries over 256 threads), as offsets within a plane,
+// worked out once per work-group: `own` marks an entry of the halo, `in` one
+// with a cell to load (not in a row beyond a wall).
+constexpr int kHaloPer = (kHalo + kTX * kTY - 1) / (kTX * kTY);
+struct HaloSlots {
+    uint32_t off[kHaloPer];
+    bool own[kHaloPer], in[kHaloPer];
+    __device__ __forceinline__ HaloSlots(const Geometry &g, int x0, int y0, int tid)
+    {
+#pragma unroll
+        for (int j = 0; j < kHaloPer; ++j) {
+            const int i = tid + j * kTX * kTY;
+            uint32_t c = 0;
+            own[j] = i < kHalo;
+            in[j] = own[j] && halo_cell(g, x0, y0, 0, i, c);
+            off[j] = c;
+        }
+    }
+};
+
 // Tile of this work-group in the mapping of cell_of_thread: origin (x0, y0)
 // and plane z; false for a padding work-group or a plane beyond the grid
 // (both uniform across the work-group).
