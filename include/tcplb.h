@@ -168,6 +168,15 @@ int tcp_destroy(tcp_domain *d);
  * host array) or dev (FP64 device array) is non-NULL; both hold nx*ny*nz
  * values.  The library keeps no reference to the caller's array. */
 int tcp_set_field(tcp_domain *d, int which, const double *host, const void *dev);
+/* Passage: Sec. 4.1 (fields initialised before the first step), as for
+ * tcp_set_field, from FP32.
+ * Copy one field (TCP_PHI, TCP_UX..TCP_UZ, TCP_T) from dev, an FP32 device
+ * array of nx*ny*nz values in x-fastest order, into the domain, asynchronously
+ * on the domain's stream; each value is converted to the storage type (exact
+ * in FP64 and FP32 storage).  The caller keeps ownership of dev and must keep
+ * it alive until the stream reaches the copy.  TCP_ERR_ARG for a NULL dev or a
+ * field that cannot be set. */
+int tcp_set_field_f32(tcp_domain *d, int which, const float *dev);
 
 /* Passage: Sec. 3.1 (tanh interface profile), Sec. 3.2-3.3 (droplet set-ups).
  * phi := max over droplets of 1/2 + 1/2 tanh(2 (r_k - dist_k) / xi)
@@ -286,6 +295,13 @@ int tcp_tape_adjoint(tcp_domain *d, const double dL_dcentroid[3], const double *
  * Read back one field as FP64 into host (synchronises) or dev (FP64 device
  * array of nx*ny*nz values, asynchronous); exactly one is non-NULL. */
 int tcp_get_field(tcp_domain *d, int which, double *host, void *dev);
+/* Passage: Sec. 2.2 (phi, u, p*, p, rho(phi)), Eq. lb_thermal (T), as for
+ * tcp_get_field, into FP32.
+ * Read back one field into dev, an FP32 device array of nx*ny*nz values in
+ * x-fastest order, asynchronously on the domain's stream.  The value is formed
+ * in FP64 exactly as tcp_get_field forms it and rounded once to FP32.  The
+ * caller owns dev.  TCP_ERR_ARG for a NULL dev or an unknown field. */
+int tcp_get_field_f32(tcp_domain *d, int which, float *dev);
 
 /* For callers that cannot allocate device memory: serving loops and
  * harnesses that forbid hipMalloc.  Same result as tcp_get_field with a host

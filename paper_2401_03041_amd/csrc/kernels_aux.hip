@@ -3,9 +3,11 @@
 //  - droplets: phi = max_k 1/2 + 1/2 tanh(2 (r_k - d_k)/xi), the tanh interface
 //    of Sec. 3.1, minimum-image distances along periodic axes (FP64).
 //  - init: every PDF at the equilibrium of the current fields with p* = 0.
-//  - read: storage -> FP64 fields, p = p* rho(phi) c_s^2 with p* = sum_i g_i.
+//  - read: storage -> FP64 (or FP32) fields, p = p* rho(phi) c_s^2 with
+//    p* = sum_i g_i.
 //  - reduce: FP64 sums of phi and phi x in a fixed order (deterministic).
 #include "kernels.hpp"
+#include "kernels_io.hpp"
 
 namespace tcp {
 
@@ -43,6 +45,13 @@ __global__ void __launch_bounds__(kThreads) k_droplets(const Geometry g, const D
 
 template <typename S>
 __global__ void __launch_bounds__(kThreads) k_from_f64(const double *src, S *dst, int64_t n)
+{
+    const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    if (c < n) dst[c] = static_cast<S>(src[c]);
+}
+
+template <typename S>
+__global__ void __launch_bounds__(kThreads) k_from_f32(const float *src, S *dst, int64_t n)
 {
     const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     if (c < n) dst[c] = static_cast<S>(src[c]);
@@ -97,8 +106,8 @@ __global__ void __launch_bounds__(kThreads) k_init(const InitArgs a)
     static_cast<S *>(a.phi_other)[c] = static_cast<S>(phi);
 }
 
-template <typename S>
-__global__ void __launch_bounds__(kThreads) k_read(const ReadArgs a)
+template <typename S, typename O>
+__global__ void __launch_bounds__(kThreads) k_read(const ReadArgs a, O *out)
 {
     const int64_t c = (int64_t)blockIdx.x * kThreads + threadIdx.x;
     const Geometry &G = a.geo;
@@ -119,7 +128,7 @@ __global__ void __launch_bounds__(kThreads) k_read(const ReadArgs a)
         const double rho = a.rho_l + phic * a.drho;
         v = a.which == 5 ? ps * rho / 3.0 : (a.which == 6 ? ps : rho);
     }
-    a.out[c] = v;
+    out[c] = static_cast<O>(v);
 }
 
 // blocked PDF layout -> component-major FP64 out[i*N + c]
@@ -256,6 +265,12 @@ void launch_from_f64(const double *src, void *dst, int64_t n, hipStream_t s)
     hipLaunchKernelGGL((k_from_f64<S>), dim3(blocks_for(n)), dim3(kThreads), 0, s, src, static_cast<S *>(dst), n);
 }
 
+template <typename S>
+void launch_from_f32(const float *src, void *dst, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_from_f32<S>), dim3(blocks_for(n)), dim3(kThreads), 0, s, src, static_cast<S *>(dst), n);
+}
+
 template <typename S, typename P>
 void launch_init(const InitArgs &a, hipStream_t s)
 {
@@ -265,7 +280,13 @@ void launch_init(const InitArgs &a, hipStream_t s)
 template <typename S>
 void launch_read(const ReadArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_read<S>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a);
+    hipLaunchKernelGGL((k_read<S, double>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a, a.out);
+}
+
+template <typename S>
+void launch_read_f32(const ReadArgs &a, float *out, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_read<S, float>), dim3(blocks_for(a.geo.N)), dim3(kThreads), 0, s, a, out);
 }
 
 template <typename P, typename F>
@@ -333,8 +354,10 @@ void launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
 #define TCP_AUX_INST(S)                                                                                      \
     template void launch_droplets<S>(const Geometry &, const Droplets &, void *, hipStream_t);              \
     template void launch_from_f64<S>(const double *, void *, int64_t, hipStream_t);                         \
+    template void launch_from_f32<S>(const float *, void *, int64_t, hipStream_t);                          \
     template void launch_init<S, S>(const InitArgs &, hipStream_t);                                         \
     template void launch_read<S>(const ReadArgs &, hipStream_t);                                            \
+    template void launch_read_f32<S>(const ReadArgs &, float *, hipStream_t);                               \
     template void launch_read_pdfs<S, S>(const void *, int, const Geometry &, double, const void *, double *, hipStream_t); \
     template void launch_reduce<S>(const Geometry &, const void *, double *, double *, hipStream_t);          \
     template void launch_maxdiff<S>(int64_t, const void *, const void *, double *, double *, hipStream_t);

@@ -13,6 +13,7 @@
 
 #include "../../include/tcplb.h"
 #include "kernels.hpp"
+#include "kernels_io.hpp"
 
 using namespace tcp;
 
@@ -675,8 +676,8 @@ int scratch_address(tcp_domain *d, int dev, void **out)
     return TCP_OK;
 }
 
-// read field `which` of the current state into dev_out (FP64, N values)
-int read_field(tcp_domain *d, int which, double *dev_out)
+// read-kernel arguments for field `which` of the current state
+ReadArgs read_args(const tcp_domain *d, int which)
 {
     ReadArgs a{};
     a.geo = d->geo;
@@ -687,10 +688,28 @@ int read_field(tcp_domain *d, int which, double *dev_out)
     for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
     a.rho_l = d->P.rho_l;
     a.drho = d->P.rho_h - d->P.rho_l;
+    return a;
+}
+
+// read field `which` of the current state into dev_out (FP64, N values)
+int read_field(tcp_domain *d, int which, double *dev_out)
+{
+    ReadArgs a = read_args(d, which);
     a.out = dev_out;
     if (d->sb == 8) launch_read<double>(a, d->stream);
     else launch_read<float>(a, d->stream);
     return check_launch(d);
+}
+
+// storage of a field the caller may set (phi^n, u, T^n), or nullptr
+void *settable_field(tcp_domain *d, int which)
+{
+    switch (which) {
+    case TCP_PHI: return d->phi[d->cur];
+    case TCP_UX: case TCP_UY: case TCP_UZ: return d->u[which - TCP_UX];
+    case TCP_T: return d->T[d->cur];
+    default: return nullptr;
+    }
 }
 
 } // namespace
@@ -1200,13 +1219,8 @@ int tcp_set_field(tcp_domain *d, int which, const double *host, const void *dev)
 {
     if (!d) return TCP_ERR_ARG;
     if ((host == nullptr) == (dev == nullptr)) return fail(d, TCP_ERR_ARG, "give exactly one of host or dev");
-    void *dst = nullptr;
-    switch (which) {
-    case TCP_PHI: dst = d->phi[d->cur]; break;
-    case TCP_UX: case TCP_UY: case TCP_UZ: dst = d->u[which - TCP_UX]; break;
-    case TCP_T: dst = d->T[d->cur]; break;
-    default: return fail(d, TCP_ERR_ARG, "field cannot be set");
-    }
+    void *dst = settable_field(d, which);
+    if (!dst) return fail(d, TCP_ERR_ARG, "field cannot be set");
     return guarded(d, [&]() -> int {
         const int64_t N = d->geo.N;
         const double *src = static_cast<const double *>(dev);
@@ -1218,6 +1232,20 @@ int tcp_set_field(tcp_domain *d, int which, const double *host, const void *dev)
         }
         if (d->sb == 8) launch_from_f64<double>(src, dst, N, d->stream);
         else launch_from_f64<float>(src, dst, N, d->stream);
+        d->initialized = false;
+        return check_launch(d);
+    });
+}
+
+int tcp_set_field_f32(tcp_domain *d, int which, const float *dev)
+{
+    if (!d) return TCP_ERR_ARG;
+    if (!dev) return fail(d, TCP_ERR_ARG, "a device source array is required");
+    void *dst = settable_field(d, which);
+    if (!dst) return fail(d, TCP_ERR_ARG, "field cannot be set");
+    return guarded(d, [&]() -> int {
+        if (d->sb == 8) launch_from_f32<double>(dev, dst, d->geo.N, d->stream);
+        else launch_from_f32<float>(dev, dst, d->geo.N, d->stream);
         d->initialized = false;
         return check_launch(d);
     });
@@ -1509,15 +1537,7 @@ int tcp_get_field(tcp_domain *d, int which, double *host, void *dev)
         const int64_t N = d->geo.N;
         Scratch tmp(d, host ? (size_t)N * sizeof(double) : 0);
         if (host && !tmp.p) return fail(d, TCP_ERR_OOM, "staging allocation failed");
-        ReadArgs a{};
-        a.geo = d->geo;
-        a.which = which; // TCP_PHI..TCP_RHO use the read-kernel codes 0..7
-        a.phi = d->phi[d->cur];
-        a.T = d->T[d->cur];
-        a.g = d->g[d->cur];
-        for (int k = 0; k < 3; ++k) a.u[k] = d->u[k];
-        a.rho_l = d->P.rho_l;
-        a.drho = d->P.rho_h - d->P.rho_l;
+        ReadArgs a = read_args(d, which);
         a.out = host ? static_cast<double *>(tmp.p) : static_cast<double *>(dev);
         if (d->sb == 8) launch_read<double>(a, d->stream);
         else launch_read<float>(a, d->stream);
@@ -1528,6 +1548,19 @@ int tcp_get_field(tcp_domain *d, int which, double *host, void *dev)
             TCP_HIP(d, hipStreamSynchronize(d->stream));
         }
         return TCP_OK;
+    });
+}
+
+int tcp_get_field_f32(tcp_domain *d, int which, float *dev)
+{
+    if (!d) return TCP_ERR_ARG;
+    if (!dev) return fail(d, TCP_ERR_ARG, "a device destination array is required");
+    if (which < TCP_PHI || which > TCP_RHO) return fail(d, TCP_ERR_ARG, "unknown field");
+    return guarded(d, [&]() -> int {
+        const ReadArgs a = read_args(d, which);
+        if (d->sb == 8) launch_read_f32<double>(a, dev, d->stream);
+        else launch_read_f32<float>(a, dev, d->stream);
+        return check_launch(d);
     });
 }
 

@@ -24,9 +24,10 @@ KERNELS = ("phase", "hydro", "thermal", "rk", "step", "adjoint", "coupled_adjoin
 
 # names of every entry point the header declares
 EXPORTS = (
-    "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_droplets",
+    "tcp_params_default", "tcp_create", "tcp_destroy", "tcp_set_field", "tcp_set_field_f32", "tcp_set_droplets",
     "tcp_set_heat_sources", "tcp_set_wall_temperature", "tcp_initialize", "tcp_step", "tcp_step_taped", "tcp_tape_adjoint",
-    "tcp_warm_temperature", "tcp_thermal_adjoint", "tcp_get_field", "tcp_get_field_noalloc",
+    "tcp_warm_temperature", "tcp_thermal_adjoint", "tcp_get_field", "tcp_get_field_f32",
+    "tcp_get_field_noalloc",
     "tcp_get_pdfs", "tcp_reduce", "tcp_state_bytes", "tcp_save_state", "tcp_load_state", "tcp_synchronize",
     "tcp_set_profiling", "tcp_set_fusion", "tcp_set_graphs", "tcp_kernel_times", "tcp_algorithmic_bytes", "tcp_bandwidth_probe", "tcp_pdf_copy_probe",
     "tcp_error_string",
@@ -101,6 +102,7 @@ def load() -> C.CDLL:
         "tcp_warm_temperature": [vp, i64, C.c_double, i64, C.POINTER(i64), dp],
         "tcp_thermal_adjoint": [vp, i64, dp, dp, dp, dp],
         "tcp_get_field": [vp, C.c_int, dp, vp],
+        "tcp_get_field_f32": [vp, C.c_int, vp],
         "tcp_get_field_noalloc": [vp, C.c_int, dp],
         "tcp_get_pdfs": [vp, C.c_int, dp],
         "tcp_reduce": [vp, dp, dp],
@@ -235,11 +237,30 @@ class Domain:
             pass
 
     # -- problem set-up --------------------------------------------------------------
+    def _device_array(self, t, what: str):
+        """Check that a CUDA tensor holds exactly one field (nx*ny*nz values,
+        contiguous) before its address crosses the boundary."""
+        import torch
+        if t.dtype not in (torch.float32, torch.float64):
+            raise TypeError(f"{what}: device arrays are float32 or float64, not {t.dtype}")
+        if t.numel() != self.nx * self.ny * self.nz or not t.is_contiguous():
+            raise ValueError(f"{what}: a contiguous device array of {self.nx * self.ny * self.nz} values is required")
+        return t
+
     def set_field(self, name: str, value) -> None:
+        """Set phi, ux, uy, uz or T from a host array (FP64), or from a CUDA
+        tensor: float32 through the FP32 entry point, anything else as FP64."""
         which = FIELDS[name]
         if hasattr(value, "is_cuda") and value.is_cuda:
-            t = value.contiguous().to(dtype=__import__("torch").float64)
-            self._check(self._lib.tcp_set_field(self._h, which, None, C.c_void_p(t.data_ptr())), "set_field")
+            import torch
+            t = value.contiguous()
+            if t.dtype != torch.float32:
+                t = t.to(dtype=torch.float64)
+            self._device_array(t, "set_field")
+            if t.dtype == torch.float32:
+                self._check(self._lib.tcp_set_field_f32(self._h, which, C.c_void_p(t.data_ptr())), "set_field")
+            else:
+                self._check(self._lib.tcp_set_field(self._h, which, None, C.c_void_p(t.data_ptr())), "set_field")
             self._lib.tcp_synchronize(self._h)
             return
         a = np.ascontiguousarray(np.broadcast_to(np.asarray(value, dtype=np.float64), self.shape3))
@@ -310,10 +331,18 @@ class Domain:
 
     # -- read-back ---------------------------------------------------------------------
     def get_field(self, name: str, out=None):
-        """FP64 field, shape (nz, ny, nx): numpy array, or into a CUDA float64 tensor `out`."""
+        """Field, shape (nz, ny, nx): FP64 numpy array, or into `out`, a CUDA
+        float64 or float32 tensor of nx*ny*nz values (asynchronous)."""
         which = FIELDS[name]
         if out is not None:
-            self._check(self._lib.tcp_get_field(self._h, which, None, C.c_void_p(out.data_ptr())), "get_field")
+            import torch
+            if not out.is_cuda:
+                raise ValueError("get_field: out must be a CUDA tensor")
+            self._device_array(out, "get_field")
+            if out.dtype == torch.float32:
+                self._check(self._lib.tcp_get_field_f32(self._h, which, C.c_void_p(out.data_ptr())), "get_field")
+            else:
+                self._check(self._lib.tcp_get_field(self._h, which, None, C.c_void_p(out.data_ptr())), "get_field")
             return out
         a = np.empty(self.shape3, dtype=np.float64)
         self._check(self._lib.tcp_get_field(self._h, which, _dptr(a), None), "get_field")

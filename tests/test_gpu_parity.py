@@ -357,3 +357,31 @@ def test_device_pointer_round_trip():
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), T0)
     assert np.array_equal(g.get_field("T"), T0)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_fp32_device_arrays(precision):
+    """FP32 device arrays at the boundary: a field set from FP32 holds exactly
+    the FP32 values (exact in FP64 and FP32 storage), and every field read into
+    FP32 is the FP64 read-back rounded once, bit for bit; a tensor of the wrong
+    size or type is refused before its address reaches the library."""
+    import torch
+    cfg = W.make(shape=(16, 9, 5), rho_l=0.5, droplets=[(7.0, 4.0, 2.0, 3.0)], precision=precision)
+    T0 = np.random.default_rng(1).uniform(0, 1, (5, 9, 16)).astype(np.float32)
+    g = gpu_domain(cfg)
+    g.set_field("T", torch.tensor(T0, device="cuda"))
+    assert np.array_equal(g.get_field("T"), T0.astype(np.float64))
+    g.initialize()
+    g.step(3)
+    for name in ("phi", "ux", "uy", "uz", "T", "p", "pstar", "rho"):
+        out = torch.full((5, 9, 16), float("nan"), dtype=torch.float32, device="cuda")
+        g.get_field(name, out=out)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), g.get_field(name).astype(np.float32)), name
+    with pytest.raises(ValueError):
+        g.get_field("T", out=torch.empty((5, 9, 15), dtype=torch.float32, device="cuda"))
+    with pytest.raises(TypeError):
+        g.get_field("T", out=torch.empty((5, 9, 16), dtype=torch.float16, device="cuda"))
+    with pytest.raises(ValueError):
+        g.set_field("T", torch.zeros((5, 9, 15), dtype=torch.float32, device="cuda"))
+    g.close()
