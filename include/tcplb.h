@@ -285,7 +285,10 @@ int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment);
  * vector-Jacobian product, with link and stencil adjoints gathered from the
  * neighbours); arithmetic in the
  * domain's precision (FP32 for FP16 PDFs), gradient sums in FP64.  The
- * domain's current state is not touched.  Synchronises.  TCP_ERR_STATE
+ * recomputation uses the heat sources and wall temperatures of the taped
+ * run, even if tcp_set_heat_sources or tcp_set_wall_temperature changed the
+ * domain's since.  The domain's current state, sources and wall
+ * temperatures are not touched.  Synchronises.  TCP_ERR_STATE
  * without a tape; TCP_ERR_ARG for a missing or non-finite dL_dcentroid. */
 int tcp_tape_adjoint(tcp_domain *d, const double dL_dcentroid[3], const double *dL_dphi, double *dL_dsource,
                      double *dL_dTw_bot, double *dL_dTw_top);

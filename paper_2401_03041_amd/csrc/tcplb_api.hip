@@ -35,6 +35,7 @@ struct tcp_domain {
     void *h[2]{}, *g[2]{}, *f[2]{}, *phi[2]{}, *u[3]{}, *T[2]{}; // [cur]: time level n
     void *rk[3]{}; // theta_a, theta_b, acc
     void *rkc = nullptr; // RK right-hand side coefficients: a_x, a_y, a_z, kappa, q
+    bool rkq_ready = false; // q in rkc holds the current heat sources
     double *twb = nullptr, *twt = nullptr;
     double *partial = nullptr, *out4 = nullptr;
     HeatSources src{};
@@ -314,6 +315,11 @@ void thermal_step(tcp_domain *d)
     a.coef = d->rkc;
     a.gk = P.kappa_h != P.kappa_l;
     a.hq = d->src.n > 0;
+    // a and kappa change every step with a conductivity ratio; q depends on
+    // the sources alone, so without one the pass runs once after each change
+    // of the sources (in a captured graph: in its first step)
+    const bool coef = a.gk || (a.hq && !d->rkq_ready);
+    if (coef) d->rkq_ready = true;
     if (P.thermal == TCP_THERMAL_RK2) {
         // theta = T + k1/2; T_new = T + R(theta)
         a.theta_in = d->T[d->cur];
@@ -326,7 +332,7 @@ void thermal_step(tcp_domain *d)
         {
             // the per-step coefficient pass is timed with the first stage
             KernelTimer t(d, TCP_K_RK);
-            launch_rk_coef<S, S>(a, d->stream);
+            if (coef) launch_rk_coef<S, S>(a, d->stream);
             launch_rk<S, S>(a, d->stream);
         }
         a.theta_in = d->rk[0];
@@ -351,7 +357,7 @@ void thermal_step(tcp_domain *d)
         a.w_acc = wacc[s];
         a.a_next = anext[s];
         KernelTimer t(d, TCP_K_RK);
-        if (s == 0) launch_rk_coef<S, S>(a, d->stream);
+        if (s == 0 && coef) launch_rk_coef<S, S>(a, d->stream);
         launch_rk<S, S>(a, d->stream);
     }
 }
@@ -456,6 +462,8 @@ int build_graph(tcp_domain *d)
     TCP_HIP(d, hipStreamBeginCapture(d->cap_stream, hipStreamCaptureModeThreadLocal));
     const hipStream_t user = d->stream;
     const int cur = d->cur;
+    // what the recorded steps take as done only happens when the graph runs
+    const bool rkq_ready = d->rkq_ready;
     d->stream = d->cap_stream;
     run_steps(d, kGraphSteps); // an even number of buffer swaps: cur is unchanged
     d->stream = user;
@@ -464,13 +472,18 @@ int build_graph(tcp_domain *d)
     const hipError_t e_end = hipStreamEndCapture(d->cap_stream, &graph);
     if (e_launch != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
+        d->rkq_ready = rkq_ready;
         return hip_fail(d, "kernel launch during graph capture", e_launch);
     }
-    if (e_end != hipSuccess) return hip_fail(d, "hipStreamEndCapture", e_end);
+    if (e_end != hipSuccess) {
+        d->rkq_ready = rkq_ready;
+        return hip_fail(d, "hipStreamEndCapture", e_end);
+    }
     const hipError_t e_inst = hipGraphInstantiate(&d->gexec[cur], graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     if (e_inst != hipSuccess) {
         d->gexec[cur] = nullptr;
+        d->rkq_ready = rkq_ready;
         return hip_fail(d, "hipGraphInstantiate", e_inst);
     }
     return TCP_OK;
@@ -985,6 +998,27 @@ int run_taped(tcp_domain *d)
     return check_launch(d);
 }
 
+// The recomputation of taped steps runs with the heat sources and wall
+// temperatures of the taped run, whatever the domain holds by then; the
+// domain's own are restored at the end of the scope.
+struct TapedInputs {
+    tcp_domain *d;
+    HeatSources src;
+    double *twb, *twt;
+    explicit TapedInputs(tcp_domain *dd) : d(dd), src(dd->src), twb(dd->twb), twt(dd->twt)
+    {
+        d->src = d->tape.src;
+        d->twb = d->tape.twb;
+        d->twt = d->tape.twt;
+    }
+    ~TapedInputs()
+    {
+        d->src = src;
+        d->twb = twb;
+        d->twt = twt;
+    }
+};
+
 // Reverse sweep over the taped steps, last segment first: recompute the inner
 // states of a segment from its checkpoint (unless a ring holds them already),
 // then undo its steps last to first.  With two rings the recomputation of
@@ -1298,6 +1332,7 @@ int tcp_set_heat_sources(tcp_domain *d, const tcp_heat_source *s, int n)
         hs.dcut2[k] = s[k].d_cut > 0.0 ? s[k].d_cut * s[k].d_cut : 0.0;
     }
     d->src = hs;
+    d->rkq_ready = false; // the RK heat-source field is evaluated again
     drop_graphs(d); // captured launches hold the previous sources by value
     return TCP_OK;
 }
@@ -1399,10 +1434,13 @@ int tcp_tape_adjoint(tcp_domain *d, const double dL_dcentroid[3], const double *
             TCP_HIP(d, hipMemcpyAsync(tp.dphi, dL_dphi, N * sizeof(double), hipMemcpyHostToDevice, d->stream));
         const double *dphi = dL_dphi ? tp.dphi : nullptr;
         int rc;
-        switch (d->P.precision) {
-        case TCP_FP64: rc = run_tape_adjoint<double, double>(d, dL_dcentroid, dphi); break;
-        case TCP_FP32: rc = run_tape_adjoint<float, float>(d, dL_dcentroid, dphi); break;
-        default: rc = run_tape_adjoint<float, _Float16>(d, dL_dcentroid, dphi); break;
+        {
+            TapedInputs taped(d);
+            switch (d->P.precision) {
+            case TCP_FP64: rc = run_tape_adjoint<double, double>(d, dL_dcentroid, dphi); break;
+            case TCP_FP32: rc = run_tape_adjoint<float, float>(d, dL_dcentroid, dphi); break;
+            default: rc = run_tape_adjoint<float, _Float16>(d, dL_dcentroid, dphi); break;
+            }
         }
         if (rc != TCP_OK) return rc;
         const int ns = tp.src.n;
@@ -1746,13 +1784,14 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
         // whole step of RK stages: each stage reads theta, a (or u), T and the
         // accumulator, kappa with a conductivity ratio and q with heat sources,
         // and writes the next argument / accumulator (stage 1 reads T once as
-        // theta and T); the per-step coefficient pass reads phi and u and writes
-        // a, kappa (conductivity ratio) and writes q (heat sources)
+        // theta and T); with a conductivity ratio a coefficient pass per step
+        // reads phi and u and writes a and kappa (and q with heat sources);
+        // without one, q is written once per change of the sources, not per step
         const double gk = d->P.kappa_h != d->P.kappa_l ? 1.0 : 0.0, hq = d->src.n > 0 ? 1.0 : 0.0;
         if (d->P.thermal == TCP_THERMAL_RK2)
-            b[TCP_K_RK] = (11.0 + 2.0 * (gk + hq) + 8.0 * gk + hq) * sb;
+            b[TCP_K_RK] = (11.0 + 2.0 * (gk + hq) + 8.0 * gk + gk * hq) * sb;
         else if (d->P.thermal == TCP_THERMAL_RK4)
-            b[TCP_K_RK] = (29.0 + 4.0 * (gk + hq) + 8.0 * gk + hq) * sb;
+            b[TCP_K_RK] = (29.0 + 4.0 * (gk + hq) + 8.0 * gk + gk * hq) * sb;
         else
             b[TCP_K_RK] = 0.0;
     }

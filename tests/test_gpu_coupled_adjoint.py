@@ -190,6 +190,34 @@ def test_checkpoint_segments_give_identical_gradients():
             assert np.array_equal(a, b), seg
 
 
+def test_adjoint_uses_the_taped_inputs():
+    """Heat sources and wall temperatures changed between the taped run and
+    its adjoint do not enter the recomputation: the gradients are those of the
+    taped run, bit for bit, and the domain keeps the inputs it was given last."""
+    cfg, twb, twt, _ = _small("mixed")
+    src = [list(s) for s in cfg["heat_sources"]]
+    target = _target(cfg)
+    ref = _adjoint(cfg, src, twb, twt, 30, target, segment=6)
+    d, c = _centroid_gpu(cfg, src, twb, twt, 30, taped=True, segment=6)
+    other = [[2.0 * s[0], s[1] + 3.0] + list(s[2:]) for s in src]
+    d.set_heat_sources(other)
+    d.set_wall_temperature(0, twb + 0.5)
+    d.set_wall_temperature(1, twt - 0.25)
+    g = d.tape_adjoint(2.0 * (c - target))
+    for a, b in zip(ref, g):
+        assert np.array_equal(a, b)
+    # the domain runs on with the inputs set last
+    e, _ = _centroid_gpu(cfg, src, twb, twt, 30)
+    e.set_heat_sources(other)
+    e.set_wall_temperature(0, twb + 0.5)
+    e.set_wall_temperature(1, twt - 0.25)
+    d.step(4)
+    e.step(4)
+    assert np.array_equal(d.get_field("T"), e.get_field("T"))
+    d.close()
+    e.close()
+
+
 def test_taped_run_is_the_plain_run():
     """tcp_step_taped advances the state exactly as tcp_step does."""
     cfg, twb, twt, _ = _small("mixed")
