@@ -76,8 +76,8 @@ enum { TCP_FP64 = 0, TCP_FP32 = 1, TCP_FP16 = 2 };
 
 /* Kernel kinds reported by tcp_kernel_times and tcp_algorithmic_bytes:
  * the phase-field, hydrodynamic and thermal LB kernels, an RK stage, the
- * fused step (all three LB updates of a step in one kernel, see
- * tcp_set_fusion), one update of the thermal adjoint (tcp_thermal_adjoint)
+ * fused step (all three LB updates of a step in one kernel, or the phase-field
+ * and hydrodynamic updates with the RK schemes, see tcp_set_fusion), one update of the thermal adjoint (tcp_thermal_adjoint)
  * and one reverse step of the coupled adjoint (tcp_tape_adjoint: its one or
  * two kernels together). */
 enum {
@@ -354,8 +354,11 @@ int tcp_kernel_times(tcp_domain *d, double *ms, int64_t *launches);
  * which each thread updates its cell's phase field, hydrodynamics and
  * temperature in turn (no thread reads what another writes within a step, so
  * this is the same update as the three kernels of Algorithm 1, with fewer
- * field reads).  enabled = 0 launches the three kernels instead (default 1).
- * The RK schemes always run the separate kernels. */
+ * field reads).  With the RK schemes (Algorithm 2) the phase-field and
+ * hydrodynamic updates run as one kernel the same way and the RK stages
+ * follow.  enabled = 0 launches the kernels of their own instead (default 1):
+ * the same update, up to the compiler rounding single operations differently
+ * in the two code paths. */
 int tcp_set_fusion(tcp_domain *d, int enabled);
 
 /* Passage: none (launch scheduling of Algorithm 1 / 2 steps).

@@ -1,6 +1,8 @@
 // kernels_step.hip -- one coupled time step with the thermal LB as a single
 // kernel: K1 (phase field), K2 (hydrodynamics) and K3 (thermal LB) of one cell
-// run back to back in one thread, in the order of Algorithm 1.
+// run back to back in one thread, in the order of Algorithm 1.  With the RK
+// schemes (Algorithm 2) the same kernel runs K1 and K2 only (QF = 0) and the
+// RK stages follow it.
 //
 // This is the same update as the three kernels of their own, arithmetic
 // included.  It is legal because, with the time levels used here, no thread
@@ -43,11 +45,15 @@ __device__ __forceinline__ void step_cell(const StepArgs &a, const Nbr &nb, int 
     R u[3];
     // with deviation storage the thermal pull needs T^n at x - e_i: the
     // hydrodynamic update has it from its T^n stencil
-    constexpr bool dev = deviation_storage<P>();
-    R tsrc[QF];
+    constexpr bool dev = QF > 0 && deviation_storage<P>();
+    R tsrc[QF > 0 ? QF : 1];
     hydro_cell<S, R, WALL, true, dev ? QF : 0>(a.hy, opaque(nb), u, ps, tsrc, sT);
-    __builtin_amdgcn_sched_barrier(0);
-    thermal_cell<QF, P, S, R, WALL, dev>(a.th, opaque(nb), x, y, z, phi_new, u, tsrc);
+    if constexpr (QF > 0) {
+        __builtin_amdgcn_sched_barrier(0);
+        thermal_cell<QF, P, S, R, WALL, dev>(a.th, opaque(nb), x, y, z, phi_new, u, tsrc);
+    } else {
+        (void)phi_new;
+    }
 }
 
 // FP64 needs 174 registers per lane; capping it at 168 lets three wavefronts
@@ -121,6 +127,8 @@ TCP_STEP_INST(27, 7)
 TCP_STEP_INST(27, 15)
 TCP_STEP_INST(27, 19)
 TCP_STEP_INST(27, 27)
+TCP_STEP_INST(15, 0)
+TCP_STEP_INST(27, 0)
 #undef TCP_STEP_INST
 
 } // namespace tcp

@@ -383,6 +383,16 @@ void fused_step(tcp_domain *d)
     else fused_step_q<27, S, Pdf>(d, a);
 }
 
+// K1 + K2 in one kernel (RK schemes: the stages follow)
+template <typename S, typename Pdf>
+void fused_pf_hydro(tcp_domain *d)
+{
+    const StepArgs a{pf_args(d), hydro_args(d), ThermalArgs{}};
+    KernelTimer t(d, TCP_K_STEP);
+    if (d->P.q_pf == 15) launch_step<15, 0, Pdf, S, S>(a, d->stream);
+    else launch_step<27, 0, Pdf, S, S>(a, d->stream);
+}
+
 // S: hydrodynamic PDFs and fields (also the arithmetic type); Pdf: phase-field
 // and thermal PDFs
 template <typename S, typename Pdf>
@@ -390,6 +400,9 @@ void one_step(tcp_domain *d)
 {
     if (d->fuse && d->P.thermal == TCP_THERMAL_LB) {
         fused_step<S, Pdf>(d);
+    } else if (d->fuse) {
+        fused_pf_hydro<S, Pdf>(d);
+        thermal_step<S, Pdf>(d);
     } else {
         phase_step<S, Pdf>(d);
         hydro_step<S>(d);
@@ -1795,10 +1808,12 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
         else
             b[TCP_K_RK] = 0.0;
     }
-    // fused step: all PDFs in/out; phi^n, T^n, u^n in; phi^{n+1}, u^{n+1}, T^{n+1} out
+    // fused step: all PDFs in/out; phi^n, T^n, u^n in; phi^{n+1}, u^{n+1}, T^{n+1}
+    // out (RK schemes: K1 and K2 only, the phase-field and hydrodynamic PDFs,
+    // no T^{n+1})
     b[TCP_K_STEP] = d->P.thermal == TCP_THERMAL_LB
                         ? 2.0 * (d->P.q_pf + d->P.q_thermal) * pb + 54.0 * sb + 10.0 * sb
-                        : 0.0;
+                        : 2.0 * d->P.q_pf * pb + 54.0 * sb + 9.0 * sb;
     // per launch.  LB update: link adjoints in/out, u and phi in, the FP64
     // source adjoint read and written.  RK stage (one pass): lambda', the next
     // stage's field, the four coefficients and acc read, acc and the stage

@@ -188,17 +188,56 @@ def test_graph_replay_matches_eager(precision, thermal):
         assert np.array_equal(a[k], b[k]), ("new sources", k)
 
 
-@pytest.mark.parametrize("precision,q_pf,q_th", [("fp64", 15, 7), ("fp32", 27, 19), ("fp16", 15, 15),
-                                                 ("fp64", 27, 27)])
-def test_fused_step_matches_three_kernels(precision, q_pf, q_th):
-    """With the thermal LB a step runs as one fused kernel; it must agree with the
-    three kernels of their own (same arithmetic, no intra-step dependence
-    between threads; the compiler may round single operations differently in
-    the two kernels, which was measured at one unit in the last place after a
-    step), walls, moving lid and heater included."""
+@pytest.mark.parametrize("thermal,graphs", [("rk2", 0), ("rk4", 0), ("rk4", 2)])
+def test_rk_heat_sources_changed_mid_run(thermal, graphs):
+    """The RK schemes keep the heat-source field from one step to the next;
+    new sources take effect at the next step: a run that changes them half way
+    equals, bitwise, a fresh domain started from the half-way state with the
+    new sources (eager launches, and step graphs captured before and after
+    the change)."""
+    cfg = W.make(shape=(40, 18, 12), periodic_y=False, precision="fp64", thermal=thermal,
+                 rho_h=1.0, rho_l=0.25, nu_h=0.12, nu_l=0.05, xi=4.0, sigma_ref=2e-3, sigma_t=-2e-4,
+                 t_ref=0.5, kappa_h=0.1, kappa_l=0.1, t_wall_top=1.0,
+                 droplets=[(17.3, 8.6, 5.2, 4.5)], heat_sources=[(0.05, 25.0, -0.5, 6.0, 4.0, 0.0)],
+                 t_init={"kind": "conduction"})
+    new = [(0.08, 10.0, -0.5, 3.0, 5.0, 0.0), (0.03, 30.0, 9.0, 9.0, 3.0, 0.0)]
+    a = gpu_domain(cfg)
+    a.set_graphs(graphs)
+    a.step(16)
+    half = a.save_state()
+    a.set_heat_sources(new)
+    a.step(16)
+    b = gpu_domain(cfg)
+    b.set_graphs(graphs)
+    b.load_state(half)
+    b.set_heat_sources(new)
+    b.step(16)
+    for k in FIELDS:
+        assert np.array_equal(a.get_field(k), b.get_field(k)), k
+    # and the old sources are really gone: the run differs from one that kept them
+    c = gpu_domain(cfg)
+    c.set_graphs(graphs)
+    c.step(32)
+    assert not np.array_equal(a.get_field("T"), c.get_field("T"))
+    for d in (a, b, c):
+        d.close()
+
+
+@pytest.mark.parametrize("precision,q_pf,q_th,thermal", [("fp64", 15, 7, "lb"), ("fp32", 27, 19, "lb"),
+                                                         ("fp16", 15, 15, "lb"), ("fp64", 27, 27, "lb"),
+                                                         ("fp64", 27, 7, "rk2"), ("fp32", 15, 7, "rk4")])
+def test_fused_step_matches_three_kernels(precision, q_pf, q_th, thermal):
+    """With the thermal LB a step runs as one fused kernel, with the RK schemes
+    the phase-field and hydrodynamic updates do; it must agree with the
+    kernels of their own (same arithmetic, no intra-step dependence between
+    threads; the compiler may round single operations differently in the two
+    kernels, which was measured at one unit in the last place after a step),
+    walls, moving lid and heater included."""
+    kap = (0.25, 0.15) if thermal == "lb" else (0.12, 0.08)
     cfg = W.make(shape=(70, 22, 14), periodic_y=False, precision=precision, q_pf=q_pf, q_thermal=q_th,
+                 thermal=thermal,
                  rho_h=1.0, rho_l=0.2, nu_h=0.15, nu_l=0.05, mobility=0.04, xi=4.0, sigma_ref=3e-3,
-                 sigma_t=-4e-4, t_ref=0.5, kappa_h=0.25, kappa_l=0.15, u_wall_top=(0.01, 0.0, 0.003),
+                 sigma_t=-4e-4, t_ref=0.5, kappa_h=kap[0], kappa_l=kap[1], u_wall_top=(0.01, 0.0, 0.003),
                  t_wall_bot=0.2, t_wall_top=1.0, droplets=[(30.3, 6.7, 4.1, 4.5), (52.4, 15.2, 9.6, 3.5)],
                  heat_sources=[(0.02, 40.0, -0.5, 4.5, 6.0, 0.0)], t_init={"kind": "conduction"})
     fused, split = gpu_domain(cfg), gpu_domain(cfg)
@@ -208,9 +247,9 @@ def test_fused_step_matches_three_kernels(precision, q_pf, q_th):
         fused.step(n)
         split.step(n)
         errs = compare(fused, split, floor=1e-6)  # p starts at zero: compare against the 1e-6 scale
-        print(precision, q_pf, q_th, n, errs)
+        print(precision, q_pf, q_th, thermal, n, errs)
         _report(errs, tol)
-    for which in ("h", "g", "f"):
+    for which in ("h", "g", "f") if thermal == "lb" else ("h", "g"):
         a, b = fused.get_pdfs(which), split.get_pdfs(which)
         assert np.max(np.abs(a - b)) <= tol * np.max(np.abs(b)), which
 
