@@ -92,6 +92,7 @@ def load() -> C.CDLL:
         "tcp_create": [C.POINTER(Params), C.POINTER(Allocator), vp, C.POINTER(vp)],
         "tcp_destroy": [vp],
         "tcp_set_field": [vp, C.c_int, dp, vp],
+        "tcp_set_field_f32": [vp, C.c_int, vp],
         "tcp_set_droplets": [vp, C.POINTER(Droplet), C.c_int],
         "tcp_set_heat_sources": [vp, C.POINTER(HeatSource), C.c_int],
         "tcp_set_wall_temperature": [vp, C.c_int, dp],

@@ -25,6 +25,8 @@ def test_library_exports_every_declared_symbol():
     assert len(names) >= 20
     for n in names:
         assert hasattr(lib, n), n
+        # the binding declares every entry point's argument types
+        assert getattr(lib, n).argtypes is not None, n
     assert sorted(tcplb.EXPORTS) == names
 
 
@@ -116,6 +118,20 @@ def test_warm_temperature_rejects_bad_arguments_without_a_domain():
     lib = tcplb.load()
     n, ch = C.c_int64(), C.c_double()
     assert lib.tcp_warm_temperature(None, 10, 0.0, 1, C.byref(n), C.byref(ch)) == -1  # TCP_ERR_ARG
+
+
+def test_field_calls_reject_a_null_domain():
+    """The field entry points, FP64 and FP32, refuse a null domain (TCP_ERR_ARG)
+    before anything touches the device."""
+    from paper_2401_03041_amd import tcplb
+    lib = tcplb.load()
+    buf = (C.c_double * 4)()
+    fbuf = (C.c_float * 4)()
+    assert lib.tcp_set_field(None, 0, buf, None) == -1
+    assert lib.tcp_get_field(None, 0, buf, None) == -1
+    assert lib.tcp_set_field_f32(None, 0, C.cast(fbuf, C.c_void_p)) == -1
+    assert lib.tcp_get_field_f32(None, 0, C.cast(fbuf, C.c_void_p)) == -1
+    assert lib.tcp_get_field_noalloc(None, 0, buf) == -1
 
 
 def _declaration_comments():
