@@ -78,8 +78,8 @@ enum { TCP_FP64 = 0, TCP_FP32 = 1, TCP_FP16 = 2 };
  * the phase-field, hydrodynamic and thermal LB kernels, an RK stage, the
  * fused step (all three LB updates of a step in one kernel, or the phase-field
  * and hydrodynamic updates with the RK schemes, see tcp_set_fusion), one update of the thermal adjoint (tcp_thermal_adjoint)
- * and one reverse step of the coupled adjoint (tcp_tape_adjoint: its one or
- * two kernels together). */
+ * and one reverse step of the coupled adjoint (tcp_tape_adjoint: its two
+ * kernels together). */
 enum {
     TCP_K_PHASE = 0,
     TCP_K_HYDRO = 1,
@@ -279,9 +279,9 @@ int tcp_step_taped(tcp_domain *d, int64_t nsteps, int64_t segment);
  * values each, x fastest); each output may be NULL.  Segments are undone
  * last to first, each recomputed from its checkpoint unless its states are
  * at hand (with two rings, on a second stream of default priority while the
- * previous segment is undone), then step by step with one reverse kernel per
- * step (two in FP32: the thermal and hydrodynamic updates, then the
- * phase-field update; for each, the recompute of the cell's update and its
+ * previous segment is undone), then step by step with two reverse kernels
+ * per step (the thermal and hydrodynamic updates, then the phase-field
+ * update; for each, the recompute of the cell's update and its
  * vector-Jacobian product, with link and stencil adjoints gathered from the
  * neighbours); arithmetic in the
  * domain's precision (FP32 for FP16 PDFs), gradient sums in FP64.  The

@@ -29,8 +29,8 @@
 //      sphi of step n (R2's stencil adjoints plus K1's gradient adjoint).
 // Every gather reads values the neighbours wrote in the previous reverse
 // step (the src buffers), so there are no atomics, the result does not
-// depend on scheduling, and the three phases can run in one kernel (FP64) or
-// in two, R3 and R2 then R1, each needing fewer registers (FP32).
+// depend on scheduling, and the three phases could run in one kernel; they
+// run in two, R3 and R2 then R1, each needing fewer registers.
 #include "adjoint_math.hpp"
 #include "kernels.hpp"
 
@@ -259,11 +259,12 @@ __device__ __forceinline__ void adj_hydro_cell(const CoupledAdjointArgs &a, cons
 }
 
 // ---------------------------------------------------------------------------
-// R1: phase field.  aphi3: K3's adjoint of phi^{n+1}; sp: K2's adjoints of
-// the phi^n stencil reads, completed here with K1's gradient adjoint and stored.
+// R1: phase field.  aphi3: K3's adjoint of phi^{n+1}; K2's adjoints of the
+// phi^n stencil reads, stored at the cell by the first half of the reverse
+// step, are completed here with K1's gradient adjoint.
 // ---------------------------------------------------------------------------
-template <int Q, typename P, typename S, typename R, bool WALL, bool SPLIT>
-__device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const Nbr &nb, R aphi3, const R (&sp)[5])
+template <int Q, typename P, typename S, typename R, bool WALL>
+__device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const Nbr &nb, R aphi3)
 {
     constexpr bool dev = deviation_storage<P>();
     const Geometry &g = a.geo;
@@ -353,54 +354,43 @@ __device__ __forceinline__ void adj_pf_cell(const CoupledAdjointArgs &a, const N
     S *lu1 = static_cast<S *>(a.lu1);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        // split: the hydrodynamic half has stored its part of the stencil adjoint
-        const R spk = SPLIT ? ld<R>(elem(sd + k * N, nb.c)) : sp[k];
-        st(elem(sd + k * N, nb.c), spk + aG[k]);
+        // the hydrodynamic half has stored its part of the stencil adjoint
+        st(elem(sd + k * N, nb.c), ld<R>(elem(sd + k * N, nb.c)) + aG[k]);
         st(elem(lu1 + k * N, nb.c), au[k]);
-    }
-    if (!SPLIT) {
-        st(elem(sd + 3 * N, nb.c), sp[3]);
-        st(elem(sd + 4 * N, nb.c), sp[4]);
     }
 }
 
-// One reverse step, the three reverse updates of a cell in one thread (K3, K2,
-// K1 in turn): every value a thread reads from another cell comes from the
-// previous reverse step's buffers, and the adjoints passed between the phases
-// (of u^{n+1}, phi^{n+1} and the phi^n stencil) stay in registers (PART 0).
-// Split in two launches (PART 1: K3 and K2, PART 2: K1) the halves need fewer
-// registers each; the first stores its part of the phi^n stencil adjoint
-// (sp) where the step's own result goes, and the phi^{n+1} adjoint of K3 in
-// a scratch field, both read back at the same cell by the second.
+// One reverse step undoes the three updates of a cell in reverse order in two
+// launches: PART 1 K3 and K2, PART 2 K1.  Every value a thread reads from
+// another cell comes from the previous reverse step's buffers.  The first
+// half stores its part of the phi^n stencil adjoint where the step's own
+// result goes, and K3's adjoint of phi^{n+1} in a scratch field; the second
+// reads both back at the same cell.  Each half needs fewer registers than the
+// whole update in one thread: in FP32 164 and 125 (three and four wavefronts
+// per SIMD where the whole update, 188, runs two), in FP64 two wavefronts per
+// SIMD with a few spills where the whole update runs one.
 template <int QH, int QF, typename P, typename S, typename R, bool WALL, int PART>
 __device__ __forceinline__ void adj_step_cell(const CoupledAdjointArgs &a, const Nbr &nb)
 {
-    R au3[3], aphi3;
-    R sp[5];
-    const int64_t N = a.geo.N;
-    if (PART != 2) {
+    if constexpr (PART == 1) {
+        R au3[3], aphi3, sp[5];
         adj_thermal_cell<QF, P, S, R, WALL>(a, opaque(nb), au3, aphi3);
         __builtin_amdgcn_sched_barrier(0);
         adj_hydro_cell<S, R, WALL>(a, opaque(nb), au3, sp);
-    }
-    if (PART == 1) {
+        const int64_t N = a.geo.N;
         S *sd = static_cast<S *>(a.sphi_dst);
 #pragma unroll
         for (int k = 0; k < 5; ++k) st(elem(sd + k * N, nb.c), sp[k]);
         st(elem(static_cast<S *>(a.xphi), nb.c), aphi3);
-        return;
+    } else {
+        const R aphi3 = ld<R>(elem(static_cast<const S *>(a.xphi), nb.c));
+        adj_pf_cell<QH, P, S, R, WALL>(a, opaque(nb), aphi3);
     }
-    if (PART == 2) {
-        aphi3 = ld<R>(elem(static_cast<const S *>(a.xphi), nb.c));
-#pragma unroll
-        for (int k = 0; k < 5; ++k) sp[k] = R(0); // unused: read back from sphi_dst
-    }
-    __builtin_amdgcn_sched_barrier(0);
-    adj_pf_cell<QH, P, S, R, WALL, PART == 2>(a, opaque(nb), aphi3, sp);
 }
 
 template <int QH, int QF, typename P, typename S, typename R, int PART>
-__global__ void __launch_bounds__(kTX *kTY) k_adj_step(const CoupledAdjointArgs a, const Tiling t)
+__global__ void __launch_bounds__(kTX *kTY) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 8 ? 2 : 1)))
+k_adj_step(const CoupledAdjointArgs a, const Tiling t)
 {
     int x, y, z;
     if (!cell_of_thread(t, a.geo, x, y, z)) return;
@@ -466,14 +456,8 @@ template <int QH, int QF, typename P, typename S, typename R>
 void launch_coupled_adjoint_step(const CoupledAdjointArgs &a, hipStream_t s)
 {
     const Tiling t = make_tiling(a.geo);
-    if constexpr (sizeof(R) == 4) {
-        // FP32 arithmetic: two launches of about 170 and 130 registers run three
-        // wavefronts per SIMD where the whole update (188) runs two
-        hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R, 1>), tiling_grid(t), tiling_block(), 0, s, a, t);
-        hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R, 2>), tiling_grid(t), tiling_block(), 0, s, a, t);
-    } else {
-        hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R, 0>), tiling_grid(t), tiling_block(), 0, s, a, t);
-    }
+    hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R, 1>), tiling_grid(t), tiling_block(), 0, s, a, t);
+    hipLaunchKernelGGL((k_adj_step<QH, QF, P, S, R, 2>), tiling_grid(t), tiling_block(), 0, s, a, t);
 }
 
 template <typename S>

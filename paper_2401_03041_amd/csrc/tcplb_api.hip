@@ -1819,8 +1819,10 @@ int tcp_algorithmic_bytes(const tcp_domain *d, double *b)
     // stage's field, the four coefficients and acc read, acc and the stage
     // field written, the FP64 source adjoint read and written.
     b[TCP_K_ADJOINT] = d->P.thermal == TCP_THERMAL_LB ? 2.0 * d->P.q_thermal * sb + 4.0 * sb + 16.0 : 9.0 * sb + 16.0;
-    // reverse step of the coupled adjoint (one kernel; link and field adjoints
-    // in the arithmetic type, sb bytes): reads the link adjoints of h, g, f,
+    // reverse step of the coupled adjoint (its algorithmic minimum: the scratch
+    // field between its two launches and their shared sphi fields are not
+    // counted; link and field adjoints in the arithmetic type, sb bytes):
+    // reads the link adjoints of h, g, f,
     // sphi, sT and lu1, the PDFs h, g, f of step n, phi^n, T^n, u^n, and
     // phi^{n+1}, u^{n+1}; writes the link adjoints, sphi, sT and lu1; the FP64
     // source adjoint is read and written
