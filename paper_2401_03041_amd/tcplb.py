@@ -197,6 +197,7 @@ class Domain:
         self.nx, self.ny, self.nz = (int(v) for v in cfg["shape"])
         self._p = params_from_config(cfg)
         self.n_sources = 0
+        self.device = int(device)
         self._alloc = None
         stream = None
         if use_torch:
@@ -246,6 +247,8 @@ class Domain:
             raise TypeError(f"{what}: device arrays are float32 or float64, not {t.dtype}")
         if t.numel() != self.nx * self.ny * self.nz or not t.is_contiguous():
             raise ValueError(f"{what}: a contiguous device array of {self.nx * self.ny * self.nz} values is required")
+        if t.device.index is not None and t.device.index != self.device:
+            raise ValueError(f"{what}: the array is on cuda:{t.device.index}, the domain on cuda:{self.device}")
         return t
 
     def set_field(self, name: str, value) -> None:
