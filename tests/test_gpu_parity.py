@@ -225,7 +225,8 @@ def test_rk_heat_sources_changed_mid_run(thermal, graphs):
 
 @pytest.mark.parametrize("precision,q_pf,q_th,thermal", [("fp64", 15, 7, "lb"), ("fp32", 27, 19, "lb"),
                                                          ("fp16", 15, 15, "lb"), ("fp64", 27, 27, "lb"),
-                                                         ("fp64", 27, 7, "rk2"), ("fp32", 15, 7, "rk4")])
+                                                         ("fp64", 27, 7, "rk2"), ("fp32", 15, 7, "rk4"),
+                                                         ("fp16", 27, 7, "rk2")])
 def test_fused_step_matches_three_kernels(precision, q_pf, q_th, thermal):
     """With the thermal LB a step runs as one fused kernel, with the RK schemes
     the phase-field and hydrodynamic updates do; it must agree with the
